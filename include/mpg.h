@@ -1,0 +1,254 @@
+/*
+ * mpg.h -- spliced protein-to-genome DP on AMD Instinct MI355X (gfx950).
+ *
+ * The library aligns a protein to a genomic region with the dynamic program of
+ * Li 2022, "Protein-to-genome alignment with miniprot" (Methods, subsection
+ * "DP for protein-to-genome alignment", Eq. (full)): codon translation scored
+ * by a 24x24 substitution matrix, affine gaps (a gap of g residues or codons
+ * costs q + e*g), frameshifts (penalty f; "DP for protein-to-DNA alignment",
+ * Eq. (fs)) and phase-0/1/2 introns (penalty r plus splice-signal penalties
+ * d() and a(); "Splice models").  Tools of this kind take a protein and a
+ * nucleotide sequence and return a spliced alignment between them
+ * (Introduction); the DP is used to close gaps between anchors and to extend
+ * from terminal anchors (Methods, opening paragraph and "Residue alignment
+ * with dynamic programming").  All DP work runs in HIP kernels on the GPU;
+ * there is no CPU fallback.
+ *
+ * Conventions for every call:
+ *  - functions return MPG_OK (0) or a negative MPG_E_* status; no exception
+ *    crosses the ABI;
+ *  - genome rows i = 1..n are nucleotides, protein columns j = 1..m residues;
+ *    coordinates returned are 0-based half-open: the alignment covers genome
+ *    [g_beg, g_end) and protein [p_beg, p_end); g_end / p_end are the DP row
+ *    and column of the end cell;
+ *  - scores are exact integers (int32 storage; mpg_params_check proves that
+ *    every reachable value fits with room for packed tie-break keys);
+ *  - only the forward strand is aligned: the caller passes the reverse
+ *    complement for the other strand (the paper indexes each strand as a
+ *    separate sequence, "Indexing the genome").
+ */
+#ifndef MPG_H
+#define MPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    MPG_OK = 0,
+    MPG_E_INVAL = -1,     /* bad argument: NULL pointer, bad params, bad flags */
+    MPG_E_RANGE = -2,     /* a length or the score bound exceeds the limits */
+    MPG_E_NOMEM = -3,     /* device or host allocation failed */
+    MPG_E_AGAIN = -4,     /* serving queue full; retry later */
+    MPG_E_DEVICE = -5,    /* a HIP call failed */
+    MPG_E_NOALN = -6,     /* GLOBAL: the end cell (n,m) is unreachable */
+    MPG_E_CANCELLED = -7  /* serving: job cancelled before it ran */
+};
+
+/* ---- boundary modes (sources and sinks of the DP) ---------------------- */
+enum {
+    MPG_LOCAL = 0,  /* start and end anywhere; H never drops below 0 */
+    MPG_EXTEND = 1, /* start at H(0,0)=0 (an anchor), end anywhere */
+    MPG_GLOBAL = 2  /* start at H(0,0)=0, end at (n,m): closing a gap between anchors */
+};
+
+/* ---- flags -------------------------------------------------------------- */
+enum {
+    MPG_NO_INTRON = 1u,     /* drop the intron states A, B, C (Eq. (fs)) */
+    MPG_NO_FRAMESHIFT = 2u, /* drop the four frameshift terms */
+    MPG_WANT_TB = 4u,       /* per pair (or for all pairs in params.flags): op string */
+    MPG_ALLOW_I16 = 8u      /* LOCAL score-only pairs may run in the int16 kernel */
+};
+
+#define MPG_MAX_DNA 1040000 /* longest genomic region (nucleotides) */
+#define MPG_MAX_PROT 32000  /* longest protein (residues) */
+
+/*
+ * Scoring parameters (Eq. (full) and "Splice models").
+ * Amino-acid order of mat: "ARNDCQEGHILKMFPSTWYVBZX*"; row = translated codon,
+ * column = protein residue.  gcode maps the codon 16*b1 + 4*b2 + b3 with
+ * A,C,G,T = 0..3 to an amino-acid index.  donor[25*b1+5*b2+b3] is d(i) for
+ * the 3-mer T[i+1..i+3] over A,C,G,T,N = 0..4 (the first three intron bases);
+ * acceptor[...] is a(i) for T[i-2..i] (the last three intron bases).  Bases
+ * outside the region count as N.  Penalties are non-negative, q + e > 0.
+ */
+typedef struct {
+    int32_t q, e, f, r;   /* gap open, gap extend, frameshift, intron */
+    uint32_t flags;       /* MPG_NO_INTRON | MPG_NO_FRAMESHIFT | MPG_WANT_TB | MPG_ALLOW_I16 */
+    int32_t mode;         /* MPG_LOCAL / MPG_EXTEND / MPG_GLOBAL */
+    int8_t mat[24][24];
+    uint8_t gcode[64];
+    uint8_t donor[125];
+    uint8_t acceptor[125];
+    uint8_t _pad[2];
+} mpg_params;
+
+/* One pair in host memory.  Letters are ASCII, case-insensitive; DNA letters
+ * other than ACGT are N, protein letters outside the alphabet are X. */
+typedef struct {
+    const char *prot;
+    int32_t plen;
+    const char *dna;
+    int32_t dlen;
+    uint32_t flags; /* MPG_WANT_TB for this pair (OR-ed with params.flags) */
+} mpg_pair;
+
+/* One result.  beg fields are -1 and ops is NULL for score-only pairs. */
+typedef struct {
+    int32_t status;   /* MPG_OK, MPG_E_RANGE, MPG_E_NOALN, MPG_E_CANCELLED */
+    int32_t score;
+    int32_t g_beg, g_end, p_beg, p_end;
+    const char *ops;  /* run-length op string, owned by the library until released */
+    int32_t ops_len;
+    int32_t _pad;
+    uint64_t job_id;       /* serving: the id returned by mpg_submit; batch: pair index */
+    int64_t t_arrive_ns;   /* serving: submit time (CLOCK_MONOTONIC) */
+    int64_t t_done_ns;     /* serving: time the result became visible to mpg_poll */
+} mpg_result;
+/*
+ * Op string: tokens "<len><op>" in forward order.  M codon:residue (len =
+ * codons), I residues against no genome (len = residues), D codons against no
+ * residue (len = codons), F frameshift substitution (len = 1 or 2 nt, one
+ * residue), G frameshift insertion (len = 1 or 2 nt), N phase-0 intron (len =
+ * nt), U / V phase-1 / phase-2 intron with its split codon (len = total nt
+ * consumed, one residue).  M, I and D runs are merged; F, G, N, U, V never.
+ * Symbols follow the paper's worked alignment ("Residue alignment with
+ * dynamic programming"): F is its "$", G its "+".
+ */
+
+typedef struct mpg_ctx mpg_ctx;
+
+/* Create a context on HIP device `device`.  tb_budget_bytes caps the device
+ * memory used for traceback direction bits at any time (0 = 64 GiB); larger
+ * batches are run in waves under the cap.  flags: reserved, pass 0. */
+int mpg_ctx_create(mpg_ctx **ctx, int device, uint64_t tb_budget_bytes, uint32_t flags);
+
+/* Destroy a context; waits for its device work and frees everything. */
+void mpg_ctx_destroy(mpg_ctx *ctx);
+
+/* Use an existing hipStream_t for all batch work of this context (NULL =
+ * the context's own stream).  The stream stays owned by the caller. */
+int mpg_set_stream(mpg_ctx *ctx, void *hip_stream);
+
+/* Fill *p with the defaults: q=11, e=1, f=23, r=29, BLOSUM62, the standard
+ * genetic code, the final splice model of "Splice models", LOCAL mode. */
+void mpg_params_default(mpg_params *p);
+
+/* Check params for pairs up to max_plen residues and max_dlen nucleotides.
+ * MPG_E_INVAL: negative penalty, q+e == 0, bad mode/flags or gcode entry.
+ * MPG_E_RANGE: lengths beyond MPG_MAX_*, or the bound on |score| for these
+ * lengths is not provably below 2^24. */
+int mpg_params_check(const mpg_params *p, int32_t max_plen, int32_t max_dlen);
+
+/*
+ * Align n pairs held in host memory; synchronous.  `pairs` and the strings
+ * are borrowed for the call only.  out[k] receives pair k; its ops string is
+ * owned by the library until mpg_result_release(ctx, out, n).  Per-pair
+ * failures (MPG_E_RANGE, MPG_E_NOALN) are reported in out[k].status; the
+ * call itself fails only for MPG_E_INVAL / MPG_E_NOMEM / MPG_E_DEVICE.
+ */
+int mpg_align_batch(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pairs, int32_t n,
+                    mpg_result *out);
+
+/* ---- device-resident batch ---------------------------------------------- */
+
+/* One pair whose letters already sit in device memory (offsets into the
+ * caller's concatenated device buffers). */
+typedef struct {
+    int64_t prot_off;
+    int64_t dna_off;
+    int32_t plen;
+    int32_t dlen;
+    uint32_t flags; /* MPG_WANT_TB */
+    int32_t _pad;
+} mpg_seg;
+
+/* Device-side result record written by mpg_align_batch_dev (40 bytes). */
+typedef struct {
+    int32_t status, score, g_beg, g_end, p_beg, p_end;
+    int64_t ops_off; /* byte offset of this pair's op string in the ops buffer */
+    int32_t ops_len;
+    int32_t _pad;
+} mpg_dev_result;
+
+/* Bytes of op-string buffer that mpg_align_batch_dev needs for these pairs
+ * (an upper bound: 2*(plen+dlen)+1 per traceback pair). */
+int64_t mpg_ops_capacity(const mpg_seg *segs, int32_t n);
+
+/*
+ * Enqueue the alignment of n pairs whose letters are in device memory
+ * (d_prot, d_dna) on the context's stream and return without waiting.
+ * segs (host memory, n entries) gives offsets and lengths; d_out (device,
+ * n records) and d_ops (device, ops_cap bytes, NUL-terminated strings) receive
+ * the results.  The device buffers must stay valid until the stream has
+ * finished the work.  Returns MPG_E_RANGE if ops_cap is too small.
+ */
+int mpg_align_batch_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot,
+                        const uint8_t *d_dna, const mpg_seg *segs, int32_t n,
+                        mpg_dev_result *d_out, char *d_ops, int64_t ops_cap);
+
+/* Wait for all work enqueued on the context's stream. */
+int mpg_sync(mpg_ctx *ctx);
+
+/* ---- serving ------------------------------------------------------------ */
+
+/*
+ * Submit one job.  The sequences are copied before the call returns.  All
+ * jobs of one context must use the same params (the first submit fixes them;
+ * a different set returns MPG_E_INVAL).  A job whose traceback bytes exceed
+ * the whole traceback budget returns MPG_E_RANGE; a full queue returns
+ * MPG_E_AGAIN.  *job_id receives the job's id.  Thread-safe against mpg_poll.
+ */
+int mpg_submit(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pair, uint64_t *job_id);
+
+/* Move up to max_results finished jobs into out, in completion order, waiting
+ * at most timeout_us microseconds for the first one (0 = do not wait).
+ * Returns the number of results (>= 0) or a negative status.  Each result's
+ * ops string is owned by the library until mpg_result_release. */
+int mpg_poll(mpg_ctx *ctx, mpg_result *out, int32_t max_results, int32_t timeout_us);
+
+/* Cancel a job that has not been admitted to the device yet; it completes
+ * with status MPG_E_CANCELLED.  MPG_E_INVAL if unknown or already running. */
+int mpg_cancel(mpg_ctx *ctx, uint64_t job_id);
+
+/* Serving statistics (all counters since ctx creation). */
+typedef struct {
+    uint64_t submitted, completed, cancelled, rejected_again, rejected_range;
+    uint64_t batches, cells;
+    uint64_t queue_depth;   /* jobs submitted but not yet admitted */
+    uint64_t in_flight;     /* jobs admitted to the device, not yet completed */
+    uint64_t tb_bytes_in_use, tb_bytes_peak, tb_budget;
+} mpg_stats;
+int mpg_get_stats(mpg_ctx *ctx, mpg_stats *st);
+
+/* ---- kernel timing ------------------------------------------------------- */
+
+/* Cumulative device time of the batch calls of this context, measured with
+ * hipEvents on the context's stream around the prepass kernel, the DP kernels
+ * and the traceback walk (only while timing is enabled). */
+typedef struct {
+    double prepass_ms, dp_ms, walk_ms;
+    uint64_t dp_spans; /* number of timed DP spans (one per batch wave) */
+    uint64_t calls;    /* batch calls since the last reset */
+} mpg_timing;
+
+/* Turn event timing of batch calls on (1) or off (0). */
+int mpg_enable_timing(mpg_ctx *ctx, int on);
+
+/* Wait for the timed work, fill *t, and zero the counters if reset != 0. */
+int mpg_get_timing(mpg_ctx *ctx, mpg_timing *t, int reset);
+
+/* Release the ops strings of n results returned by this context. */
+void mpg_result_release(mpg_ctx *ctx, mpg_result *r, int32_t n);
+
+const char *mpg_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPG_H */

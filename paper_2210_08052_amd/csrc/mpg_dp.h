@@ -1,0 +1,537 @@
+// Device helpers and the templated DP kernel, shared by the per-K
+// translation units (mpg_dp_k1/k2/k4.hip) and the other kernels.
+#pragma once
+
+#include <climits>
+
+#include "mpg_internal.h"
+
+// Minimum occupancy target of the DP kernels (waves per SIMD); 1 = no cap.
+#ifndef MPG_DP_WAVES_PER_EU
+#define MPG_DP_WAVES_PER_EU 1
+#endif
+
+namespace mpg {
+namespace dev {
+
+
+constexpr int kShr1 = 0x138;  // DPP wave_shr:1
+constexpr int kShl1 = 0x130;  // DPP wave_shl:1
+
+static __constant__ uint8_t kAaOfLetter[26] = {0,  20, 4,  3,  6,  13, 7,  8,  9,  22, 11, 10, 12,
+                                        2,  22, 14, 5,  1,  15, 16, 22, 19, 17, 22, 18, 21};
+
+__device__ __forceinline__ int dna_code(uint32_t ch) {
+    switch (ch | 0x20u) {
+        case 'a': return 0;
+        case 'c': return 1;
+        case 'g': return 2;
+        case 't': return 3;
+        default: return 4;
+    }
+}
+
+__device__ __forceinline__ int aa_code(uint32_t ch) {
+    if (ch == '*') return 23;
+    uint32_t u = (ch | 0x20u) - 'a';
+    return u < 26u ? kAaOfLetter[u] : 22;
+}
+
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int imax3(int a, int b, int c) { return imax(imax(a, b), c); }
+
+__device__ __forceinline__ int shr1(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, kShr1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int shl1(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, kShl1, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+        uint32_t olo = __shfl_xor((int)lo, o, 64), ohi = __shfl_xor((int)hi, o, 64);
+        uint64_t w = ((uint64_t)ohi << 32) | olo;
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// End-cell key: larger is better; score desc, then row asc, then column asc.
+__device__ __forceinline__ uint64_t end_key(int score, int row, int col) {
+    return ((uint64_t)(uint32_t)(score + (1 << 27)) << 36) |
+           ((uint64_t)(uint32_t)((1 << 21) - 1 - row) << 15) | (uint64_t)((1 << 15) - 1 - col);
+}
+
+__device__ __forceinline__ int neg_for(int mode, bool tb) {
+    return mode == MPG_LOCAL ? (tb ? -(1 << 29) : -(1 << 25)) : -(1 << 30);
+}
+
+// ---------------------------------------------------------------------- DP
+//
+// Score-only layout (TB = false): plain values, descriptor {tr, z, r+d(i+1),
+// a(i)}; r+d(i), r+d(i-1), a(i-1), a(i-2) are carried in registers.
+// Traceback layout (TB = true): H is 16*H; I, D, A, B, C are 16*v + their
+// fixed nibble (13, 12, 7, 6, 5); descriptor {tr, 16z+15, 16(r+d(i-1))-7,
+// 16(r+d(i))-6, 16(r+d(i+1))-5, 16a(i), 16a(i-2), 16a(i-1)}.
+// H winner codes: 0 start, 1 M, 2 I, 3 D, 4 F1, 5 F2, 6 G1, 7 G2, 8 A, 9 B,
+// 10 C; nibble = 15 - code.
+
+template <int K, bool TB>
+struct LdsLayout {
+    static constexpr int DS = TB ? 32 : 16;    // descriptor bytes per row
+    static constexpr int PS = TB ? 2 : 1;      // profile entry bytes
+    static constexpr int SW = 64 * K;          // strip width
+    static constexpr int RING = 128 * DS;      // two chunks of descriptors
+    static constexpr int PROF = 25 * SW * PS;  // profile: 24 aa + poison row
+    static constexpr int IN = 64 * 8;          // incoming boundary of the chunk
+    static constexpr int OUT = 64 * 8;         // outgoing boundary of the chunk
+    static constexpr int XR = 192 * 8;         // hand-off ring to the next wave
+    static constexpr int WAVE = RING + PROF + IN + OUT + XR;
+};
+
+// Sentinels per layout.  LOCAL keeps -infinity small enough that a shifted
+// end-tracking key of any sentinel-derived value stays negative.
+template <int MODE, bool TB>
+struct Sentinel {
+    static constexpr int NEG = MODE == MPG_LOCAL ? (TB ? -(1 << 29) : -(1 << 25)) : -(1 << 30);
+    static constexpr int UNREACH = MODE == MPG_LOCAL ? NEG / 2 : -(1 << 29);
+};
+
+extern "C" __device__ int mpg_writelane_i32(int val, int lane, int old) __asm(
+    "llvm.amdgcn.writelane.i32");
+
+template <int K, int MODE, bool TB, bool NOI, bool NOF>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP_WAVES_PER_EU))) dp_kernel(const PairJob* __restrict__ jobs,
+                                                 const int32_t* __restrict__ order,
+                                                 const uint8_t* __restrict__ prot,
+                                                 const uint8_t* __restrict__ desc,
+                                                 int2* __restrict__ bnd,
+                                                 uint8_t* __restrict__ tbbuf,
+                                                 mpg_dev_result* __restrict__ out, DevParams P) {
+    using LY = LdsLayout<K, TB>;
+    constexpr int NEG = Sentinel<MODE, TB>::NEG;
+    constexpr int UNREACH = Sentinel<MODE, TB>::UNREACH;
+    constexpr int ZN = TB ? 15 : 0;  // nibble of the start candidate
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6;
+    const PairJob J = jobs[order[blockIdx.x]];
+    if (J.status != MPG_OK) return;  // uniform for the whole workgroup
+
+    uint8_t* my = smem + wid * LY::WAVE;
+    uint8_t* ring = my;
+    uint8_t* prof = my + LY::RING;
+    int2* inb = (int2*)(my + LY::RING + LY::PROF);
+    int2* outb = (int2*)(my + LY::RING + LY::PROF + LY::IN);
+    int2* xr_out = (int2*)(my + LY::RING + LY::PROF + LY::IN + LY::OUT);
+    const int2* xr_in = (const int2*)(smem + (wid > 0 ? wid - 1 : 0) * LY::WAVE + LY::RING +
+                                      LY::PROF + LY::IN + LY::OUT);
+    uint64_t* red = (uint64_t*)(smem + W * LY::WAVE);
+    int* gsc = (int*)(red + 16);
+
+    const int n = J.n, m = J.m;
+    const int nchunks = J.nchunks, nstrips = J.nstrips;
+    const uint8_t* dsc_g = desc + J.desc_off;  // row r at (r + kDescLo) * DS
+    int2* bnd_g = bnd + J.bnd_off;             // row r at r + kBndLo
+    const uint8_t* Pa = prot + J.prot_off;
+    uint8_t* tbp = tbbuf + J.tb_off;
+
+    // penalties in the layout of this variant
+    const int cq = TB ? 16 * (P.q + P.e) - 13 : P.q;   // I open  (TB: nibble 13)
+    const int cqD = TB ? 16 * (P.q + P.e) - 12 : P.q;  // D open  (TB: nibble 12)
+    const int ce = TB ? 16 * P.e : P.e;
+    const int cf = TB ? 16 * P.f : P.f;
+
+    uint64_t best_key = 0;
+    if (threadIdx.x == 0) *gsc = NEG;
+
+    const int npasses = (nstrips + W - 1) / W;
+    for (int pass = 0; pass < npasses; ++pass) {
+        const int strip = pass * W + wid;
+        const bool act = strip < nstrips;
+        const int col0 = strip * LY::SW + lane * K;  // DP column of this lane's first column
+
+        // ---- strip set-up: profile, registers, first descriptors and boundary
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const int j = col0 + c;
+                const int pc = (j >= 1 && j <= m) ? aa_code(Pa[j - 1]) : -1;
+                for (int tr = 0; tr < 25; ++tr) {
+                    const bool poison = pc < 0 || tr == 24;
+                    const int sv = poison ? 0 : P.mat[tr * 24 + pc];
+                    if (TB)
+                        ((int16_t*)prof)[tr * LY::SW + lane * K + c] =
+                            (int16_t)(poison ? -32768 : 16 * sv + 14);
+                    else
+                        ((int8_t*)prof)[tr * LY::SW + lane * K + c] = (int8_t)(poison ? -128 : sv);
+                }
+            }
+            inb[lane] = make_int2(NEG, NEG);
+        }
+
+        int h1[K], h2[K], h3[K], d1[K], d2[K], d3[K], a1[K], b1[K], c1[K];
+        int zl[K], best[K], bstep[K], bk[K], bkt[K], hn[K];
+        uint32_t nacc[K];
+        int xlo[5][K], xhi[5][K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            h1[c] = h2[c] = h3[c] = NEG;
+            d1[c] = d2[c] = d3[c] = NEG;
+            a1[c] = b1[c] = c1[c] = NEG;
+            zl[c] = (col0 + c == 0) ? ZN : NEG + ZN;
+            best[c] = NEG;
+            bstep[c] = 0;
+            bk[c] = INT_MIN;
+            bkt[c] = 0;
+            hn[c] = NEG;
+            nacc[c] = 0;
+#pragma unroll
+            for (int x = 0; x < 5; ++x) xlo[x][c] = xhi[x][c] = 0;
+        }
+        int hl1 = NEG, hl2 = NEG, hl3 = NEG;
+        int Hout = NEG, Iout = NEG;
+        // registers carrying r+d(i), r+d(i-1), a(i-1), a(i-2) (score-only layout)
+        int dd0 = 0, ddm1 = 0, aam1 = 0, aam2 = 0;
+        if (!TB && act) {
+            const int4 u = *(const int4*)(dsc_g + (int64_t)(-lane - 1 + kDescLo) * LY::DS);
+            const int4 v = *(const int4*)(dsc_g + (int64_t)(-lane - 2 + kDescLo) * LY::DS);
+            dd0 = u.z; aam1 = u.w; ddm1 = v.z; aam2 = v.w;
+        }
+        // descriptor ring: rows -64..-1 then 0..63
+        int4 pf0 = make_int4(0, 0, 0, 0), pf1 = make_int4(0, 0, 0, 0);
+        if (act) {
+            const uint8_t* src = dsc_g + (int64_t)(lane - 64 + kDescLo) * LY::DS;
+            *(int4*)(ring + lane * LY::DS) = *(const int4*)src;
+            if (TB) *(int4*)(ring + lane * LY::DS + 16) = *(const int4*)(src + 16);
+            const uint8_t* src2 = dsc_g + (int64_t)(lane + kDescLo) * LY::DS;
+            *(int4*)(ring + (64 + lane) * LY::DS) = *(const int4*)src2;
+            if (TB) *(int4*)(ring + (64 + lane) * LY::DS + 16) = *(const int4*)(src2 + 16);
+        }
+        int2 nb = make_int2(NEG, NEG);
+        const bool from_global = act && strip > 0 && wid == 0;
+        if (from_global) nb = bnd_g[kBndLo + lane];
+
+        const int Eend = nchunks + 2 * (W - 1);
+        for (int E = 0; E < Eend; ++E) {
+            const int ch = E - 2 * wid;
+            if (act && ch >= 0 && ch < nchunks) {
+                // incoming boundary rows ch*64 .. ch*64+63 of the left strip
+                // (rows beyond n were never written by the left strip's last
+                // lane, or hold garbage-row values: they enter as -infinity)
+                const bool beyond = ch * 64 + lane > n;
+                if (from_global) {
+                    inb[lane] = beyond ? make_int2(NEG, NEG) : nb;
+                    nb = bnd_g[kBndLo + (ch + 1) * 64 + lane];
+                } else if (wid > 0) {
+                    const int2 v = xr_in[(ch * 64 + lane) % 192];
+                    inb[lane] = beyond ? make_int2(NEG, NEG) : v;
+                }
+                if (ch > 0) {
+                    // slide the descriptor ring: current chunk -> previous half
+                    const int4 o0 = *(const int4*)(ring + (64 + lane) * LY::DS);
+                    *(int4*)(ring + lane * LY::DS) = o0;
+                    *(int4*)(ring + (64 + lane) * LY::DS) = pf0;
+                    if (TB) {
+                        const int4 o1 = *(const int4*)(ring + (64 + lane) * LY::DS + 16);
+                        *(int4*)(ring + lane * LY::DS + 16) = o1;
+                        *(int4*)(ring + (64 + lane) * LY::DS + 16) = pf1;
+                    }
+                }
+                {
+                    const uint8_t* src =
+                        dsc_g + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS;
+                    pf0 = *(const int4*)src;
+                    if (TB) pf1 = *(const int4*)(src + 16);
+                }
+                const uint8_t* rb = ring + (64 - lane) * LY::DS;
+                uint8_t* tbblk = tbp + ((int64_t)strip * nchunks + ch) * (kTbBlockBytes * K);
+                const int srow_n = ch * 64 - n;  // GLOBAL: lane == t + srow_n  <=>  row == n
+
+                // Software pipeline: descriptors are read two steps ahead, the
+                // profile entries and the incoming boundary value one step ahead.
+                auto ld_desc = [&](int tt, int4& x0, int4& x1) {
+                    x0 = *(const int4*)(rb + tt * LY::DS);
+                    if (TB) x1 = *(const int4*)(rb + tt * LY::DS + 16);
+                };
+                auto ld_prof = [&](const int4& x0, int* scv) {
+                    if (TB) {
+                        const int16_t* pr = (const int16_t*)prof + x0.x * LY::SW + lane * K;
+#pragma unroll
+                        for (int c = 0; c < K; ++c) scv[c] = pr[c];
+                    } else {
+                        const int8_t* pr = (const int8_t*)prof + x0.x * LY::SW + lane * K;
+#pragma unroll
+                        for (int c = 0; c < K; ++c) scv[c] = pr[c];
+                    }
+                };
+                int4 cd0, cd1 = make_int4(0, 0, 0, 0), nd0, nd1 = make_int4(0, 0, 0, 0);
+                ld_desc(0, cd0, cd1);
+                ld_desc(1, nd0, nd1);
+                int csc[K];
+                ld_prof(cd0, csc);
+                int2 cin = inb[0];
+
+#pragma unroll
+                for (int t = 0; t < 64; ++t) {
+                    // ---- prefetch for steps t+1 and t+2
+                    int4 fd0 = make_int4(0, 0, 0, 0), fd1 = make_int4(0, 0, 0, 0);
+                    if (t + 2 < 64) ld_desc(t + 2, fd0, fd1);
+                    int nsc[K];
+                    int2 nin = make_int2(0, 0);
+                    if (t + 1 < 64) {
+                        ld_prof(nd0, nsc);
+                        nin = inb[t + 1];
+                    }
+                    const int4 ds0 = cd0, ds1 = cd1;
+                    const int hl0 = shr1(cin.x, Hout);
+                    const int il0 = shr1(cin.y, Iout);
+                    const int zr = ds0.y;
+                    int Hn[K], In[K], Dn[K], An[K], Bn[K], Cn[K];
+#pragma unroll
+                    for (int c = 0; c < K; ++c) {
+                        const int L0 = c ? Hn[c - 1] : hl0;
+                        const int IL = c ? In[c - 1] : il0;
+                        const int L1 = c ? h1[c - 1] : hl1;
+                        const int L2 = c ? h2[c - 1] : hl2;
+                        const int L3 = c ? h3[c - 1] : hl3;
+                        const int z = (MODE == MPG_LOCAL) ? zr : imin(zr, zl[c]);
+                        if (!TB) {
+                            const int D = imax(h3[c] - cqD, d3[c]) - ce;
+                            int H = D;
+                            if (!NOI) {
+                                const int A = imax(h1[c] - ddm1, a1[c]);
+                                const int B = imax(L1 - dd0, b1[c]);
+                                const int C = imax(L1 - ds0.z, c1[c]);
+                                H = imax3(H, A - ds0.w, imax(B - aam2, C - aam1));
+                                An[c] = A; Bn[c] = B; Cn[c] = C;
+                            }
+                            if (!NOF) {
+                                const int fg = imax(imax3(L1, L2, h1[c]), h2[c]) - cf;
+                                H = imax(H, fg);
+                            }
+                            const int I = imax(L0 - cq, IL) - ce;
+                            H = imax3(H, L3 + csc[c], I);
+                            H = imax(H, z);
+                            Hn[c] = H; In[c] = I; Dn[c] = D;
+                        } else {
+                            const int oD = h3[c] - cqD, xD = d3[c] - ce;
+                            const uint64_t mD = __builtin_amdgcn_ballot_w64(xD >= oD);
+                            const int D = imax(oD, xD);
+                            int Hk = D;
+                            if (!NOI) {
+                                const int oA = h1[c] - ds0.z;
+                                const uint64_t mA = __builtin_amdgcn_ballot_w64(a1[c] >= oA);
+                                const int A = imax(oA, a1[c]);
+                                const int oB = L1 - ds0.w;
+                                const uint64_t mB = __builtin_amdgcn_ballot_w64(b1[c] >= oB);
+                                const int B = imax(oB, b1[c]);
+                                const int oC = L1 - ds1.x;
+                                const uint64_t mC = __builtin_amdgcn_ballot_w64(c1[c] >= oC);
+                                const int C = imax(oC, c1[c]);
+                                Hk = imax3(Hk, A - ds1.y, B - ds1.z);
+                                Hk = imax(Hk, C - ds1.w);
+                                An[c] = A; Bn[c] = B; Cn[c] = C;
+                                xlo[2][c] = mpg_writelane_i32((int)(uint32_t)mA, t, xlo[2][c]);
+                                xhi[2][c] = mpg_writelane_i32((int)(uint32_t)(mA >> 32), t, xhi[2][c]);
+                                xlo[3][c] = mpg_writelane_i32((int)(uint32_t)mB, t, xlo[3][c]);
+                                xhi[3][c] = mpg_writelane_i32((int)(uint32_t)(mB >> 32), t, xhi[3][c]);
+                                xlo[4][c] = mpg_writelane_i32((int)(uint32_t)mC, t, xlo[4][c]);
+                                xhi[4][c] = mpg_writelane_i32((int)(uint32_t)(mC >> 32), t, xhi[4][c]);
+                            }
+                            if (!NOF) {
+                                Hk = imax3(Hk, L1 - (cf - 11), L2 - (cf - 10));
+                                Hk = imax3(Hk, h1[c] - (cf - 9), h2[c] - (cf - 8));
+                            }
+                            const int oI = L0 - cq, xI = IL - ce;
+                            const uint64_t mI = __builtin_amdgcn_ballot_w64(xI >= oI);
+                            const int I = imax(oI, xI);
+                            Hk = imax3(Hk, z, L3 + csc[c]);
+                            Hk = imax(Hk, I);
+                            xlo[0][c] = mpg_writelane_i32((int)(uint32_t)mI, t, xlo[0][c]);
+                            xhi[0][c] = mpg_writelane_i32((int)(uint32_t)(mI >> 32), t, xhi[0][c]);
+                            xlo[1][c] = mpg_writelane_i32((int)(uint32_t)mD, t, xlo[1][c]);
+                            xhi[1][c] = mpg_writelane_i32((int)(uint32_t)(mD >> 32), t, xhi[1][c]);
+                            nacc[c] = __builtin_amdgcn_alignbit(Hk, nacc[c], 4);
+                            Hn[c] = Hk & ~15;
+                            In[c] = I; Dn[c] = D;
+                        }
+                    }
+                    // end-cell tracking (chunk-local, merged after the chunk)
+                    if (MODE == MPG_GLOBAL) {
+                        const bool at_n = (lane == t + srow_n);
+#pragma unroll
+                        for (int c = 0; c < K; ++c) hn[c] = at_n ? Hn[c] : hn[c];
+                    } else if (MODE == MPG_LOCAL) {
+#pragma unroll
+                        for (int c = 0; c < K; ++c)
+                            bk[c] = imax(bk[c], (Hn[c] << (TB ? 2 : 6)) | (63 - t));
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < K; ++c) {
+                            const bool gt = Hn[c] > bk[c];
+                            bk[c] = gt ? Hn[c] : bk[c];
+                            bkt[c] = gt ? t : bkt[c];
+                        }
+                    }
+                    if (TB && (t & 7) == 7) {
+#pragma unroll
+                        for (int c = 0; c < K; ++c)
+                            *(uint32_t*)(tbblk + (((t >> 3) * K + c) * 64 + lane) * 4) = nacc[c];
+                    }
+                    // shift histories
+                    hl3 = hl2; hl2 = hl1; hl1 = hl0;
+#pragma unroll
+                    for (int c = 0; c < K; ++c) {
+                        h3[c] = h2[c]; h2[c] = h1[c]; h1[c] = Hn[c];
+                        d3[c] = d2[c]; d2[c] = d1[c]; d1[c] = Dn[c];
+                        if (!NOI) { a1[c] = An[c]; b1[c] = Bn[c]; c1[c] = Cn[c]; }
+                    }
+                    if (!TB) { ddm1 = dd0; dd0 = ds0.z; aam2 = aam1; aam1 = ds0.w; }
+                    Hout = Hn[K - 1];
+                    Iout = In[K - 1];
+                    if (lane == 63) outb[t] = make_int2(Hout, Iout);
+                    // rotate the pipeline
+                    cd0 = nd0; cd1 = nd1; nd0 = fd0; nd1 = fd1;
+#pragma unroll
+                    for (int c = 0; c < K; ++c) csc[c] = nsc[c];
+                    cin = nin;
+                    __builtin_amdgcn_sched_barrier(0);
+                }  // steps
+
+                // merge the chunk's best into the strip's best (first maximum)
+                if (MODE != MPG_GLOBAL) {
+#pragma unroll
+                    for (int c = 0; c < K; ++c) {
+                        int v, tt;
+                        if (MODE == MPG_LOCAL) { v = bk[c] >> 6; tt = 63 - (bk[c] & 63); }
+                        else { v = bk[c]; tt = bkt[c]; }
+                        if (TB && MODE == MPG_LOCAL) v <<= 4;  // back to 16*H units
+                        if (v > best[c]) { best[c] = v; bstep[c] = ch * 64 + tt; }
+                        bk[c] = INT_MIN;
+                    }
+                }
+                if (TB) {
+#pragma unroll
+                    for (int x = 0; x < 5; ++x) {
+                        if (NOI && x >= 2) continue;
+#pragma unroll
+                        for (int c = 0; c < K; ++c)
+                            *(uint2*)(tbblk + 2048 * K + ((x * K + c) * 64 + lane) * 8) =
+                                make_uint2((uint32_t)xlo[x][c], (uint32_t)xhi[x][c]);
+                    }
+                }
+                // publish the strip's last column for rows ch*64-63+lane
+                const int orow = ch * 64 - 63 + lane;
+                const int2 ov = outb[lane];
+                if (wid == W - 1) bnd_g[kBndLo + orow] = ov;
+                else xr_out[(orow + 192) % 192] = ov;
+            }
+            if (W > 1) __syncthreads();
+        }  // epochs
+
+        // ---- strip epilogue: best cell of the strip
+        if (act) {
+            if (MODE == MPG_GLOBAL) {
+#pragma unroll
+                for (int c = 0; c < K; ++c)
+                    if (col0 + c == m) *gsc = hn[c];
+            } else {
+                uint64_t key = 0;
+#pragma unroll
+                for (int c = 0; c < K; ++c) {
+                    const int row = bstep[c] - lane;
+                    const int col = col0 + c;
+                    const int v = TB ? (best[c] >> 4) : best[c];
+                    if (col <= m && row >= 0 && row <= n && best[c] > UNREACH) {
+                        const uint64_t k2 = end_key(v, row, col);
+                        key = k2 > key ? k2 : key;
+                    }
+                }
+                key = wave_max_u64(key);
+                best_key = key > best_key ? key : best_key;
+            }
+        }
+        __syncthreads();
+    }  // passes
+
+    if (lane == 0) red[wid] = best_key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mpg_dev_result R;
+        R.g_beg = -1;
+        R.p_beg = -1;
+        R.ops_off = J.ops_off;
+        R.ops_len = 0;
+        R._pad = 0;
+        if (MODE == MPG_GLOBAL) {
+            const int v = *gsc;
+            if (v < UNREACH) {
+                R.status = MPG_E_NOALN;
+                R.score = 0;
+                R.g_end = -1;
+                R.p_end = -1;
+            } else {
+                R.status = MPG_OK;
+                R.score = TB ? (v >> 4) : v;
+                R.g_end = n;
+                R.p_end = m;
+            }
+        } else {
+            uint64_t k = 0;
+            for (int w = 0; w < W; ++w) k = red[w] > k ? red[w] : k;
+            R.status = MPG_OK;
+            R.score = (int)(k >> 36) - (1 << 27);
+            R.g_end = (1 << 21) - 1 - (int)((k >> 15) & ((1u << 21) - 1));
+            R.p_end = (1 << 15) - 1 - (int)(k & ((1u << 15) - 1));
+        }
+        out[J.res] = R;
+    }
+}
+
+template <int K, int MODE, bool TB>
+hipError_t launch_dp_t(hipStream_t s, int W, const DevParams& P, const PairJob* jobs,
+                       const int32_t* order, int count, const uint8_t* prot, const uint8_t* desc,
+                       int2* bnd, uint8_t* tbbuf, mpg_dev_result* out) {
+    const bool noi = (P.flags & MPG_NO_INTRON) != 0;
+    const bool nof = (P.flags & MPG_NO_FRAMESHIFT) != 0;
+    const size_t lds = (size_t)dp_lds_bytes(K, W, TB);
+    dim3 grid(count), block(64 * W);
+    if (!noi && !nof)
+        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, false, false>), grid, block, lds, s, jobs, order,
+                           prot, desc, bnd, tbbuf, out, P);
+    else if (noi && !nof)
+        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, true, false>), grid, block, lds, s, jobs, order,
+                           prot, desc, bnd, tbbuf, out, P);
+    else if (!noi && nof)
+        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, false, true>), grid, block, lds, s, jobs, order,
+                           prot, desc, bnd, tbbuf, out, P);
+    else
+        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, true, true>), grid, block, lds, s, jobs, order,
+                           prot, desc, bnd, tbbuf, out, P);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_dp_k(hipStream_t s, int W, bool tb, const DevParams& P, const PairJob* jobs,
+                       const int32_t* order, int count, const uint8_t* prot, const uint8_t* desc,
+                       int2* bnd, uint8_t* tbbuf, mpg_dev_result* out) {
+    switch (P.mode) {
+        case MPG_LOCAL:
+            return tb ? launch_dp_t<K, MPG_LOCAL, true>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out)
+                      : launch_dp_t<K, MPG_LOCAL, false>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
+        case MPG_EXTEND:
+            return tb ? launch_dp_t<K, MPG_EXTEND, true>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out)
+                      : launch_dp_t<K, MPG_EXTEND, false>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
+        default:
+            return tb ? launch_dp_t<K, MPG_GLOBAL, true>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out)
+                      : launch_dp_t<K, MPG_GLOBAL, false>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
+    }
+}
+
+}  // namespace dev
+}  // namespace mpg

@@ -1,0 +1,295 @@
+// HIP kernels of the spliced protein-to-genome DP for gfx950 (CDNA4).
+//
+// The recurrence is Eq. (full) of Li 2022 (Methods, "DP for
+// protein-to-genome alignment"): states H, I, D and the intron states A, B, C
+// per cell (i = genome row, j = protein column), with the match term read as
+// H(i-3,j-1)+s(i,j) (the codon ending at i against residue j; the printed
+// H(i-3,j) consumes no residue), frameshift terms of Eq. (fs) and the splice
+// penalties of "Splice models" supplied as 3-mer tables.
+//
+// Data layout and schedule (see also the design notes):
+//  * prepass: one thread per genome row writes a row descriptor: the amino
+//    acid of the codon ending at the row, the start/floor value z(i) and the
+//    splice penalties the row needs (all rows -128 .. steps+64, with poison
+//    values outside 0..n);
+//  * dp: one wavefront owns a strip of 64*K consecutive protein columns, lane
+//    k holding K adjacent columns.  At step s lane k computes row s-k, so the
+//    anti-diagonal order satisfies every dependency (rows i-1..i-3 of its own
+//    columns live in registers; the left neighbour's H and I of the same row
+//    arrive by a DPP wave_shr:1).  Lane 0 takes the left strip's last column
+//    from a 64-row shift register (DPP wave_shl:1), which at the same time
+//    collects lane 63's outputs for the next strip.  W wavefronts of a
+//    workgroup take W consecutive strips, each lagging the previous by two
+//    64-step chunks, handing the boundary column over through an LDS ring;
+//    the last wavefront hands it to the next pass through HBM;
+//  * traceback variant: every value is kept as 16*v + nibble, where the
+//    nibble encodes the H winner (15 - code) so one max3 chain yields the
+//    value and the first-maximum tie-break together; gap/intron extension
+//    choices are wave ballots.  Both go to HBM as coalesced 256-512 B writes;
+//  * walk: one thread per pair follows the stored choices back from the end
+//    cell and writes the run-length op string.
+#include "mpg_dp.h"
+
+namespace mpg {
+
+using namespace dev;
+
+namespace dev {
+
+// ----------------------------------------------------------------- prepass
+__global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict__ jobs,
+                                                      const int64_t* __restrict__ row_start,
+                                                      int npairs, int64_t total_rows,
+                                                      const uint8_t* __restrict__ dna,
+                                                      uint8_t* __restrict__ desc, DevParams P) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_rows) return;
+    int lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_start[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const PairJob& J = jobs[lo];
+    const int i = (int)(g - row_start[lo]) - kDescLo;
+    const int n = J.n;
+    const uint8_t* T = dna + J.dna_off;
+    auto base = [&](int x) -> int { return (x >= 1 && x <= n) ? dna_code(T[x - 1]) : 4; };
+    int b[9];  // bases i-4 .. i+4
+#pragma unroll
+    for (int k = 0; k < 9; ++k) b[k] = base(i - 4 + k);
+    // codon ending at i: T[i-2..i]
+    int tr;
+    if (i > n || i < 0) tr = 24;  // poison row
+    else if (i < 3 || b[2] == 4 || b[3] == 4 || b[4] == 4) tr = 22;
+    else tr = P.gcode[16 * b[2] + 4 * b[3] + b[4]];
+    // d(x) uses T[x+1..x+3], a(x) uses T[x-2..x]; b[k] = T[i-4+k]
+    auto dpen = [&](int x) -> int {  // x in i-1 .. i+1
+        const int o = x - i + 4;
+        return P.donor[25 * b[o + 1] + 5 * b[o + 2] + b[o + 3]];
+    };
+    auto apen = [&](int x) -> int {  // x in i-2 .. i
+        const int o = x - i + 4;
+        return P.acceptor[25 * b[o - 2] + 5 * b[o - 1] + b[o]];
+    };
+    const bool valid = (i >= 0 && i <= n);
+    int z;
+    const int neg = neg_for(P.mode, J.tb != 0);
+    if (P.mode == MPG_LOCAL) z = valid ? 0 : neg;
+    else z = (i == 0) ? 0 : neg;
+    int4* out = (int4*)(desc + J.desc_off + (int64_t)(i + kDescLo) * (J.tb ? 32 : 16));
+    if (!J.tb) {
+        out[0] = make_int4(tr, z, P.r + dpen(i + 1), apen(i));
+    } else {
+        out[0] = make_int4(tr, z + 15, 16 * (P.r + dpen(i - 1)) - 7, 16 * (P.r + dpen(i)) - 6);
+        out[1] = make_int4(16 * (P.r + dpen(i + 1)) - 5, 16 * apen(i), 16 * apen(i - 2),
+                           16 * apen(i - 1));
+    }
+}
+
+// ------------------------------------------------------------------- walk
+
+struct TbView {
+    const uint8_t* base;
+    int K, nchunks;
+    __device__ __forceinline__ const uint8_t* blk(int i, int j, int& k, int& c, int& t) const {
+        const int SW = 64 * K;
+        const int S = j / SW;
+        const int jj = j - S * SW;
+        k = jj / K;
+        c = jj - k * K;
+        const int s = i + k;
+        t = s & 63;
+        return base + ((int64_t)S * nchunks + (s >> 6)) * (kTbBlockBytes * K);
+    }
+    __device__ __forceinline__ int code(int i, int j) const {
+        int k, c, t;
+        const uint8_t* b = blk(i, j, k, c, t);
+        const uint32_t w = *(const uint32_t*)(b + (((t >> 3) * K + c) * 64 + k) * 4);
+        return 15 - (int)((w >> ((t & 7) * 4)) & 15u);
+    }
+    __device__ __forceinline__ int ext(int x, int i, int j) const {
+        int k, c, t;
+        const uint8_t* b = blk(i, j, k, c, t);
+        const uint2 v = *(const uint2*)(b + 2048 * K + ((x * K + c) * 64 + t) * 8);
+        const uint32_t w = k < 32 ? v.x : v.y;
+        return (int)((w >> (k & 31)) & 1u);
+    }
+};
+
+__device__ __forceinline__ int ndigits(int v) {
+    int d = 1;
+    while (v >= 10) { v /= 10; ++d; }
+    return d;
+}
+
+// Walks back from (i, j) in state H.  Pass 0 returns the op-string length;
+// pass 1 writes the string backwards from txt[len].  Returns -1 on an
+// inconsistent path (never expected), and the start cell in (bi, bj).
+__device__ int walk_pair(const TbView& V, int i, int j, int n, int m, char* txt, int len,
+                         bool write, int& bi, int& bj) {
+    int st = 0;  // 0 H, 1 I, 2 D, 3 A, 4 B, 5 C
+    int kend = 0;
+    char pop = 0;
+    int plen = 0, total = 0, pos = len;
+    const int64_t guard = 4LL * (n + m) + 64;
+    auto flush = [&]() {
+        if (!pop) return;
+        total += ndigits(plen) + 1;
+        if (write) {
+            txt[--pos] = pop;
+            int v = plen;
+            do { txt[--pos] = (char)('0' + v % 10); v /= 10; } while (v);
+        }
+        pop = 0;
+    };
+    auto emit = [&](char op, int l, bool merge) {
+        if (merge && pop == op) { plen += l; return; }
+        flush();
+        pop = op;
+        plen = l;
+        if (!merge) flush();
+    };
+    for (int64_t it = 0; it < guard; ++it) {
+        if (i < 0 || j < 0 || i > n || j > m) return -1;
+        if (st == 0) {
+            const int hc = V.code(i, j);
+            if (hc == 0) {
+                flush();
+                bi = i;
+                bj = j;
+                return total;
+            }
+            switch (hc) {
+                case 1: emit('M', 1, true); i -= 3; j -= 1; break;
+                case 2: st = 1; break;
+                case 3: st = 2; break;
+                case 4: emit('F', 1, false); i -= 1; j -= 1; break;
+                case 5: emit('F', 2, false); i -= 2; j -= 1; break;
+                case 6: emit('G', 1, false); i -= 1; break;
+                case 7: emit('G', 2, false); i -= 2; break;
+                case 8: st = 3; kend = i; break;
+                case 9: st = 4; kend = i; break;
+                case 10: st = 5; kend = i; break;
+                default: return -1;
+            }
+        } else if (st == 1) {
+            emit('I', 1, true);
+            if (!V.ext(0, i, j)) st = 0;
+            j -= 1;
+        } else if (st == 2) {
+            emit('D', 1, true);
+            if (!V.ext(1, i, j)) st = 0;
+            i -= 3;
+        } else {
+            if (!V.ext(st - 1, i, j)) {
+                emit(st == 3 ? 'N' : st == 4 ? 'U' : 'V', kend - i + 1, false);
+                if (st != 3) j -= 1;
+                st = 0;
+            }
+            i -= 1;
+        }
+    }
+    return -1;
+}
+
+__global__ void __launch_bounds__(64) walk_kernel(const PairJob* __restrict__ jobs,
+                                                  const int32_t* __restrict__ order, int count,
+                                                  const uint8_t* __restrict__ tbbuf,
+                                                  mpg_dev_result* __restrict__ out,
+                                                  char* __restrict__ ops) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const PairJob J = jobs[order[k]];
+    mpg_dev_result R = out[J.res];
+    char* txt = ops + J.ops_off;
+    if (J.status != MPG_OK || R.status != MPG_OK) {
+        txt[0] = 0;
+        return;
+    }
+    TbView V{tbbuf + J.tb_off, J.K, J.nchunks};
+    int bi = -1, bj = -1;
+    const int len = walk_pair(V, R.g_end, R.p_end, J.n, J.m, txt, 0, false, bi, bj);
+    if (len < 0 || len > 2 * (J.n + J.m)) {
+        R.status = MPG_E_DEVICE;
+        txt[0] = 0;
+    } else {
+        walk_pair(V, R.g_end, R.p_end, J.n, J.m, txt, len, true, bi, bj);
+        txt[len] = 0;
+        R.g_beg = bi;
+        R.p_beg = bj;
+        R.ops_len = len;
+    }
+    out[J.res] = R;
+}
+
+// Records for pairs the host rejected before launch.
+__global__ void status_kernel(const PairJob* __restrict__ jobs, int npairs,
+                              mpg_dev_result* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npairs) return;
+    const PairJob J = jobs[k];
+    if (J.status == MPG_OK) return;
+    mpg_dev_result R;
+    R.status = J.status;
+    R.score = 0;
+    R.g_beg = R.g_end = R.p_beg = R.p_end = -1;
+    R.ops_off = J.ops_off;
+    R.ops_len = 0;
+    R._pad = 0;
+    out[J.res] = R;
+}
+
+}  // namespace dev
+
+hipError_t launch_dp_k1(hipStream_t, int, bool, const DevParams&, const PairJob*, const int32_t*,
+                        int, const uint8_t*, const uint8_t*, int2*, uint8_t*, mpg_dev_result*);
+hipError_t launch_dp_k2(hipStream_t, int, bool, const DevParams&, const PairJob*, const int32_t*,
+                        int, const uint8_t*, const uint8_t*, int2*, uint8_t*, mpg_dev_result*);
+hipError_t launch_dp_k4(hipStream_t, int, bool, const DevParams&, const PairJob*, const int32_t*,
+                        int, const uint8_t*, const uint8_t*, int2*, uint8_t*, mpg_dev_result*);
+
+int dp_lds_bytes(int K, int W, bool tb) {
+    int wave;
+    if (K == 1) wave = tb ? LdsLayout<1, true>::WAVE : LdsLayout<1, false>::WAVE;
+    else if (K == 2) wave = tb ? LdsLayout<2, true>::WAVE : LdsLayout<2, false>::WAVE;
+    else wave = tb ? LdsLayout<4, true>::WAVE : LdsLayout<4, false>::WAVE;
+    return wave * W + 16 * 8 + 16;
+}
+
+hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row_start, int npairs,
+                          int64_t total_rows, const uint8_t* dna, uint8_t* desc, const DevParams& P) {
+    if (total_rows <= 0) return hipSuccess;
+    const int64_t blocks = (total_rows + 255) / 256;
+    hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)blocks), dim3(256), 0, s, jobs, row_start,
+                       npairs, total_rows, dna, desc, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_dp(hipStream_t s, int K, int W, bool tb, const DevParams& P, const PairJob* jobs,
+                     const int32_t* order, int count, const uint8_t* prot, const uint8_t* desc,
+                     int2* bnd, uint8_t* tbbuf, mpg_dev_result* out) {
+    if (count <= 0) return hipSuccess;
+    switch (K) {
+        case 1: return launch_dp_k1(s, W, tb, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
+        case 2: return launch_dp_k2(s, W, tb, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
+        case 4: return launch_dp_k4(s, W, tb, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_walk(hipStream_t s, const PairJob* jobs, const int32_t* order, int count,
+                       const uint8_t* tbbuf, mpg_dev_result* out, char* ops) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(walk_kernel, dim3((count + 63) / 64), dim3(64), 0, s, jobs, order, count,
+                       tbbuf, out, ops);
+    return hipGetLastError();
+}
+
+hipError_t launch_status(hipStream_t s, const PairJob* jobs, int npairs, mpg_dev_result* out) {
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(status_kernel, dim3((npairs + 255) / 256), dim3(256), 0, s, jobs, npairs, out);
+    return hipGetLastError();
+}
+
+}  // namespace mpg

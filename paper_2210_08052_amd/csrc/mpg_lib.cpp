@@ -1,0 +1,1009 @@
+// Host runtime of the spliced protein-to-genome DP library: parameters,
+// validation, planning, device memory, batch entry points and the serving
+// loop.  All DP arithmetic runs in the HIP kernels of mpg_kernels.hip; this
+// file only marshals arguments, sizes buffers and orders launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mpg_internal.h"
+
+using namespace mpg;
+
+namespace {
+
+// ---------------------------------------------------------------- defaults
+// BLOSUM62 (Henikoff & Henikoff 1992) in the order ARNDCQEGHILKMFPSTWYVBZX*.
+const int8_t kBlosum62[24][24] = {
+    {4, -1, -2, -2, 0, -1, -1, 0, -2, -1, -1, -1, -1, -2, -1, 1, 0, -3, -2, 0, -2, -1, 0, -4},
+    {-1, 5, 0, -2, -3, 1, 0, -2, 0, -3, -2, 2, -1, -3, -2, -1, -1, -3, -2, -3, -1, 0, -1, -4},
+    {-2, 0, 6, 1, -3, 0, 0, 0, 1, -3, -3, 0, -2, -3, -2, 1, 0, -4, -2, -3, 3, 0, -1, -4},
+    {-2, -2, 1, 6, -3, 0, 2, -1, -1, -3, -4, -1, -3, -3, -1, 0, -1, -4, -3, -3, 4, 1, -1, -4},
+    {0, -3, -3, -3, 9, -3, -4, -3, -3, -1, -1, -3, -1, -2, -3, -1, -1, -2, -2, -1, -3, -3, -2, -4},
+    {-1, 1, 0, 0, -3, 5, 2, -2, 0, -3, -2, 1, 0, -3, -1, 0, -1, -2, -1, -2, 0, 3, -1, -4},
+    {-1, 0, 0, 2, -4, 2, 5, -2, 0, -3, -3, 1, -2, -3, -1, 0, -1, -3, -2, -2, 1, 4, -1, -4},
+    {0, -2, 0, -1, -3, -2, -2, 6, -2, -4, -4, -2, -3, -3, -2, 0, -2, -2, -3, -3, -1, -2, -1, -4},
+    {-2, 0, 1, -1, -3, 0, 0, -2, 8, -3, -3, -1, -2, -1, -2, -1, -2, -2, 2, -3, 0, 0, -1, -4},
+    {-1, -3, -3, -3, -1, -3, -3, -4, -3, 4, 2, -3, 1, 0, -3, -2, -1, -3, -1, 3, -3, -3, -1, -4},
+    {-1, -2, -3, -4, -1, -2, -3, -4, -3, 2, 4, -2, 2, 0, -3, -2, -1, -2, -1, 1, -4, -3, -1, -4},
+    {-1, 2, 0, -1, -3, 1, 1, -2, -1, -3, -2, 5, -1, -3, -1, 0, -1, -3, -2, -2, 0, 1, -1, -4},
+    {-1, -1, -2, -3, -1, 0, -2, -3, -2, 1, 2, -1, 5, 0, -2, -1, -1, -1, -1, 1, -3, -1, -1, -4},
+    {-2, -3, -3, -3, -2, -3, -3, -3, -1, 0, 0, -3, 0, 6, -4, -2, -2, 1, 3, -1, -3, -3, -1, -4},
+    {-1, -2, -2, -1, -3, -1, -1, -2, -2, -3, -3, -1, -2, -4, 7, -1, -1, -4, -3, -2, -2, -1, -2, -4},
+    {1, -1, 1, 0, -1, 0, 0, 0, -1, -2, -2, 0, -1, -2, -1, 4, 1, -3, -2, -2, 0, 0, 0, -4},
+    {0, -1, 0, -1, -1, -1, -1, -2, -2, -1, -1, -1, -1, -2, -1, 1, 5, -2, -2, 0, -1, -1, 0, -4},
+    {-3, -3, -4, -4, -2, -2, -3, -2, -2, -3, -2, -3, -1, 1, -4, -3, -2, 11, 2, -3, -4, -3, -2, -4},
+    {-2, -2, -2, -3, -2, -1, -2, -3, 2, -1, -1, -2, -1, 3, -3, -2, -2, 2, 7, -1, -3, -2, -1, -4},
+    {0, -3, -3, -3, -1, -2, -2, -3, -3, 3, 1, -2, 1, -1, -2, -2, 0, -3, -1, 4, -3, -2, -1, -4},
+    {-2, -1, 3, 4, -3, 0, 1, -1, 0, -3, -4, 0, -3, -3, -2, 0, -1, -4, -3, -3, 4, 1, -1, -4},
+    {-1, 0, 0, 1, -3, 3, 4, -2, 0, -3, -3, 1, -1, -3, -1, 0, -1, -3, -2, -2, 1, 4, -1, -4},
+    {0, -1, -1, -1, -2, -1, -1, -1, -1, -1, -1, -1, -1, -1, -2, 0, 0, -2, -1, -1, -1, -1, -1, -4},
+    {-4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, -4, 1},
+};
+
+const char kAlphabet[] = "ARNDCQEGHILKMFPSTWYVBZX*";
+// Standard genetic code, codons in A,C,G,T nesting order (AAA, AAC, ..., TTT).
+const char kCodeACGT[] = "KNKNTTTTRSRSIIMIQHQHPPPPRRRRLLLLEDEDAAAAGGGGVVVV*Y*YSSSS*CWCLFLF";
+
+// Final splice model ("Splice models"): donor penalty from the intron's first
+// three bases, acceptor penalty from its last three; N and out-of-range bases
+// never match a listed pattern.
+int donor_pen(int b1, int b2, int b3) {
+    enum { A = 0, C = 1, G = 2, T = 3 };
+    if (b1 == G && b2 == T && (b3 == A || b3 == G)) return 0;
+    if (b1 == G && b2 == T && (b3 == C || b3 == T)) return 8;
+    if (b1 == G && b2 == C) return 15;
+    if (b1 == A && b2 == T) return 21;
+    return 30;
+}
+int acceptor_pen(int b1, int b2, int b3) {
+    enum { A = 0, C = 1, G = 2, T = 3 };
+    if ((b1 == C || b1 == T) && b2 == A && b3 == G) return 0;
+    if ((b1 == A || b1 == G) && b2 == A && b3 == G) return 8;
+    if (b2 == A && b3 == C) return 21;
+    return 30;
+}
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// ------------------------------------------------------------- device memory
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return MPG_OK;
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(bytes, 256);
+        want = want + want / 4;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            if (hipMalloc(&p, bytes) != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                return MPG_E_NOMEM;
+            }
+            want = bytes;
+        }
+        cap = want;
+        return MPG_OK;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct HostBuf {  // pinned host staging
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return MPG_OK;
+        if (p) hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(bytes, 4096);
+        want = want + want / 4;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return MPG_E_NOMEM;
+        }
+        cap = want;
+        return MPG_OK;
+    }
+    void release() {
+        if (p) hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// Everything one in-flight batch needs on the device.
+struct Workspace {
+    DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops;
+    HostBuf hplan, hseq, hout, hops;
+    void release() {
+        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops};
+        for (auto* b : d) b->release();
+        HostBuf* h[] = {&hplan, &hseq, &hout, &hops};
+        for (auto* b : h) b->release();
+    }
+};
+
+// ------------------------------------------------------------------ planning
+struct Group {
+    int K, W;
+    bool tb;
+    std::vector<int32_t> order;  // pair indices, longest first
+};
+
+struct Plan {
+    std::vector<PairJob> jobs;
+    std::vector<int64_t> row_start;
+    std::vector<Group> groups;
+    std::vector<int32_t> walk;
+    int64_t desc_bytes = 0, bnd_elems = 0, tb_bytes = 0;
+    int64_t total_rows = 0;
+};
+
+int g_max_lds = 65536;
+
+// Debug-only overrides (tests use them to reach every kernel variant on
+// small inputs): MPG_FORCE_K = columns per lane, MPG_FORCE_W = waves per pair.
+int env_int(const char* name) {
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : 0;
+}
+
+int choose_K(int m) {
+    (void)m;
+    const int f = env_int("MPG_FORCE_K");
+    if (f == 1 || f == 2 || f == 4) return f;
+    return 2;
+}
+
+int choose_W(int K, int nstrips, int n, bool tb) {
+    int W;
+    const int f = env_int("MPG_FORCE_W");
+    if (f >= 1) W = std::min(f, 8);
+    else if (nstrips <= 2 || (int64_t)n * nstrips < 4000000) W = 1;
+    else W = std::min(8, nstrips / 2);
+    while (W > 1 && dp_lds_bytes(K, W, tb) > g_max_lds) --W;
+    return std::max(W, 1);
+}
+
+int64_t tb_bytes_of(int n, int m, int K) {
+    const int nsteps = ((n + 64 + 63) / 64) * 64;
+    const int nstrips = (m + 1 + 64 * K - 1) / (64 * K);
+    return (int64_t)nstrips * (nsteps / 64) * kTbBlockBytes * K;
+}
+
+// Bound on |value| of reachable cells (see the public header).
+bool score_bound_ok(const mpg_params* p, int64_t n, int64_t m) {
+    int maxpos = 0, minneg = 0;
+    for (int a = 0; a < 24; ++a)
+        for (int b = 0; b < 24; ++b) {
+            maxpos = std::max<int>(maxpos, p->mat[a][b]);
+            minneg = std::min<int>(minneg, p->mat[a][b]);
+        }
+    const int64_t lim = (int64_t)1 << 24;
+    if ((int64_t)maxpos * (m + 1) >= lim) return false;
+    int dmax = 0, amax = 0;
+    for (int k = 0; k < 125; ++k) {
+        dmax = std::max<int>(dmax, p->donor[k]);
+        amax = std::max<int>(amax, p->acceptor[k]);
+    }
+    const int64_t pmax = std::max<int64_t>(
+        {(int64_t)p->q + p->e, (int64_t)p->f, (int64_t)p->r + dmax + amax, (int64_t)-minneg});
+    if (p->mode == MPG_LOCAL) return pmax * 4 < lim;
+    return (n + m + 4) * pmax < lim;
+}
+
+void make_dev_params(const mpg_params* p, DevParams* d) {
+    std::memset(d, 0, sizeof(*d));
+    d->q = p->q;
+    d->e = p->e;
+    d->f = p->f;
+    d->r = p->r;
+    d->mode = p->mode;
+    d->flags = (int32_t)p->flags;
+    std::memcpy(d->mat, p->mat, sizeof(d->mat));
+    std::memcpy(d->gcode, p->gcode, 64);
+    std::memcpy(d->donor, p->donor, 125);
+    std::memcpy(d->acceptor, p->acceptor, 125);
+}
+
+// Build the plan for the pairs idx[0..cnt) of a call with n pairs.  Each
+// job writes result record idx[k] and its op string at ops_off[idx[k]].
+void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
+                const std::vector<int64_t>& ops_off, Plan& P, uint64_t tb_budget) {
+    P.jobs.assign(cnt, PairJob{});
+    P.row_start.assign(cnt, 0);
+    P.groups.clear();
+    P.walk.clear();
+    P.desc_bytes = P.bnd_elems = P.tb_bytes = P.total_rows = 0;
+    std::vector<std::pair<int64_t, int32_t>> bysize;
+    bysize.reserve(cnt);
+    for (int32_t k = 0; k < cnt; ++k) {
+        const mpg_seg& s = segs[idx[k]];
+        PairJob& J = P.jobs[k];
+        J.n = s.dlen;
+        J.m = s.plen;
+        J.res = idx[k];
+        J.tb = ((s.flags | p->flags) & MPG_WANT_TB) ? 1 : 0;
+        J.dna_off = s.dna_off;
+        J.prot_off = s.prot_off;
+        J.status = MPG_OK;
+        if (s.dlen < 0 || s.plen < 0 || s.dlen > MPG_MAX_DNA || s.plen > MPG_MAX_PROT ||
+            !score_bound_ok(p, s.dlen, s.plen))
+            J.status = MPG_E_RANGE;
+        const int K = choose_K(std::max(0, s.plen));
+        J.K = K;
+        const int nn = std::max(0, J.n), mm = std::max(0, J.m);
+        const int nsteps = ((nn + 64 + 63) / 64) * 64;
+        J.nchunks = nsteps / 64;
+        J.nstrips = (mm + 1 + 64 * K - 1) / (64 * K);
+        if (J.tb && J.status == MPG_OK && (uint64_t)tb_bytes_of(nn, mm, K) > tb_budget)
+            J.status = MPG_E_RANGE;
+        J.ops_off = ops_off[idx[k]];
+        if (J.status != MPG_OK) continue;
+        J.desc_off = P.desc_bytes;
+        const int64_t rows = (int64_t)nsteps + kDescLo + kDescHi;
+        P.row_start[k] = P.total_rows;
+        P.total_rows += rows;
+        P.desc_bytes += rows * (J.tb ? 32 : 16);
+        J.bnd_off = P.bnd_elems;
+        P.bnd_elems += (int64_t)nsteps + kBndLo + kBndHi;
+        J.tb_off = P.tb_bytes;
+        if (J.tb) P.tb_bytes += tb_bytes_of(nn, mm, K);
+        bysize.push_back({(int64_t)(nn + 64) * (mm + 1), k});
+    }
+    std::sort(bysize.begin(), bysize.end(),
+              [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
+                  return a.first > b.first || (a.first == b.first && a.second < b.second);
+              });
+    for (auto& e : bysize) {
+        const PairJob& J = P.jobs[e.second];
+        const int W = choose_W(J.K, J.nstrips, J.n, J.tb != 0);
+        Group* g = nullptr;
+        for (auto& gg : P.groups)
+            if (gg.K == J.K && gg.W == W && gg.tb == (J.tb != 0)) g = &gg;
+        if (!g) {
+            P.groups.push_back(Group{J.K, W, J.tb != 0, {}});
+            g = &P.groups.back();
+        }
+        g->order.push_back(e.second);
+        if (J.tb) P.walk.push_back(e.second);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct mpg_ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    uint64_t tb_budget = 64ull << 30;
+    Workspace ws;
+    std::mutex batch_mu;
+    // optional kernel timing (hipEvents on the batch stream)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pre, ev_dp, ev_walk;
+    std::vector<hipEvent_t> ev_pool;
+    double t_pre = 0, t_dp = 0, t_walk = 0;
+    uint64_t n_dp = 0, n_calls = 0;
+
+    // ---- serving
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool params_set = false;
+    mpg_params sparams;
+    struct Job {
+        uint64_t id;
+        std::string prot, dna;
+        uint32_t flags;
+        int64_t t_arrive;
+        int64_t tb_bytes;
+        int64_t cells;
+    };
+    std::deque<Job> pending;
+    std::deque<mpg_result> done;
+    uint64_t next_id = 1;
+    bool stop = false;
+    std::thread sched;
+    bool sched_running = false;
+    size_t max_pending = 1 << 20;
+    int nslots = 3;
+    int64_t slot_cells = 1500000000LL;
+    int max_jobs_per_batch = 4096;
+    mpg_stats stats{};
+    uint64_t tb_in_use = 0;
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? MPG_OK : MPG_E_DEVICE; }
+
+// Records hipEvent pairs around the prepass (0), DP (1) and walk (2) launches
+// of a batch; resolved lazily by mpg_get_timing.
+struct Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev[3];
+    std::vector<hipEvent_t>* pool;
+    hipEvent_t open[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t get() {
+        hipEvent_t e = nullptr;
+        if (!pool->empty()) {
+            e = pool->back();
+            pool->pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+    void begin(hipStream_t st, int k) {
+        open[k] = get();
+        if (open[k]) hipEventRecord(open[k], st);
+    }
+    void end(hipStream_t st, int k) {
+        if (!open[k]) return;
+        hipEvent_t e = get();
+        if (!e) return;
+        hipEventRecord(e, st);
+        ev[k]->push_back({open[k], e});
+        open[k] = nullptr;
+    }
+};
+
+// Enqueue the pairs idx[0..cnt) of a call whose letters are on the device.
+int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
+            const uint8_t* d_dna, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
+            const std::vector<int64_t>& ops_off, mpg_dev_result* d_out, char* d_ops,
+            uint64_t tb_budget, Timer* tm) {
+    Plan P;
+    plan_pairs(p, segs, idx, cnt, ops_off, P, tb_budget);
+    DevParams DP;
+    make_dev_params(p, &DP);
+    // prepass list: planned pairs only, row_start ascending
+    std::vector<PairJob> pjobs;
+    std::vector<int64_t> pstarts;
+    pjobs.reserve(cnt);
+    pstarts.reserve(cnt);
+    for (int32_t k = 0; k < cnt; ++k)
+        if (P.jobs[k].status == MPG_OK) {
+            pjobs.push_back(P.jobs[k]);
+            pstarts.push_back(P.row_start[k]);
+        }
+    // launch orders (local job indices), then the walk order
+    std::vector<int32_t> orders;
+    std::vector<size_t> goff;
+    for (auto& g : P.groups) {
+        goff.push_back(orders.size());
+        orders.insert(orders.end(), g.order.begin(), g.order.end());
+    }
+    const size_t walk_off = orders.size();
+    orders.insert(orders.end(), P.walk.begin(), P.walk.end());
+
+    const size_t jobs_b = sizeof(PairJob) * (size_t)cnt;
+    const size_t pj_b = sizeof(PairJob) * pjobs.size();
+    const size_t ps_b = sizeof(int64_t) * pstarts.size();
+    const size_t ord_b = sizeof(int32_t) * orders.size();
+    int rc;
+    // the staging buffer and workspace may still be in use by earlier work
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    if ((rc = ws.jobs.ensure(jobs_b + pj_b + 256)) != MPG_OK) return rc;
+    if ((rc = ws.row_start.ensure(ps_b + 64)) != MPG_OK) return rc;
+    if ((rc = ws.order.ensure(ord_b + 64)) != MPG_OK) return rc;
+    if ((rc = ws.desc.ensure((size_t)P.desc_bytes + 64)) != MPG_OK) return rc;
+    if ((rc = ws.bnd.ensure(sizeof(int2) * (size_t)P.bnd_elems + 64)) != MPG_OK) return rc;
+    if ((rc = ws.tb.ensure((size_t)P.tb_bytes + 64)) != MPG_OK) return rc;
+    const size_t plan_b = jobs_b + pj_b + ps_b + ord_b + 1024;
+    if ((rc = ws.hplan.ensure(plan_b)) != MPG_OK) return rc;
+    uint8_t* h = (uint8_t*)ws.hplan.p;
+    std::memcpy(h, P.jobs.data(), jobs_b);
+    std::memcpy(h + jobs_b, pjobs.data(), pj_b);
+    std::memcpy(h + jobs_b + pj_b, pstarts.data(), ps_b);
+    std::memcpy(h + jobs_b + pj_b + ps_b, orders.data(), ord_b);
+    PairJob* d_jobs = (PairJob*)ws.jobs.p;
+    PairJob* d_pjobs = (PairJob*)((uint8_t*)ws.jobs.p + jobs_b);
+    int64_t* d_starts = (int64_t*)ws.row_start.p;
+    int32_t* d_order = (int32_t*)ws.order.p;
+    hipError_t e = hipSuccess;
+    if (jobs_b + pj_b) e = hipMemcpyAsync(ws.jobs.p, h, jobs_b + pj_b, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && ps_b)
+        e = hipMemcpyAsync(d_starts, h + jobs_b + pj_b, ps_b, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && ord_b)
+        e = hipMemcpyAsync(d_order, h + jobs_b + pj_b + ps_b, ord_b, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return MPG_E_DEVICE;
+
+    if (launch_status(st, d_jobs, cnt, d_out) != hipSuccess) return MPG_E_DEVICE;
+    if (tm) tm->begin(st, 0);
+    if (launch_prepass(st, d_pjobs, d_starts, (int)pjobs.size(), P.total_rows, d_dna,
+                       (uint8_t*)ws.desc.p, DP) != hipSuccess)
+        return MPG_E_DEVICE;
+    if (tm) tm->end(st, 0);
+    if (tm) tm->begin(st, 1);
+    for (size_t g = 0; g < P.groups.size(); ++g) {
+        const Group& G = P.groups[g];
+        e = launch_dp(st, G.K, G.W, G.tb, DP, d_jobs, d_order + goff[g], (int)G.order.size(),
+                      d_prot, (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, (uint8_t*)ws.tb.p,
+                      d_out);
+        if (e != hipSuccess) return MPG_E_DEVICE;
+    }
+    if (tm) tm->end(st, 1);
+    if (!P.walk.empty()) {
+        if (tm) tm->begin(st, 2);
+        e = launch_walk(st, d_jobs, d_order + walk_off, (int)P.walk.size(),
+                        (const uint8_t*)ws.tb.p, d_out, d_ops);
+        if (e != hipSuccess) return MPG_E_DEVICE;
+        if (tm) tm->end(st, 2);
+    }
+    return MPG_OK;
+}
+
+bool seg_tb(const mpg_seg& s, const mpg_params* p) {
+    return ((s.flags | p->flags) & MPG_WANT_TB) != 0;
+}
+
+// Run all n pairs.  Traceback pairs whose direction bits together exceed the
+// budget are split into waves that reuse the same buffer one after another on
+// the stream; each wave writes straight into the caller's records and ops.
+int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
+                  const uint8_t* d_dna, const mpg_seg* segs, int32_t n, mpg_dev_result* d_out,
+                  char* d_ops, uint64_t tb_budget, Timer* tm) {
+    std::vector<int64_t> ops_off(n);
+    int64_t o = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        ops_off[k] = o;
+        o += seg_tb(segs[k], p) ? 2 * ((int64_t)std::max(0, segs[k].dlen) +
+                                       std::max(0, segs[k].plen)) + 1
+                                : 1;
+    }
+    std::vector<int32_t> idx;
+    idx.reserve(n);
+    int64_t acc = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const mpg_seg& s = segs[k];
+        const int64_t b = (seg_tb(s, p) && s.plen >= 0 && s.dlen >= 0)
+                              ? tb_bytes_of(s.dlen, s.plen, choose_K(s.plen))
+                              : 0;
+        if (b <= (int64_t)tb_budget && acc + b > (int64_t)tb_budget && !idx.empty()) {
+            int rc = run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(),
+                             ops_off, d_out, d_ops, tb_budget, tm);
+            if (rc != MPG_OK) return rc;
+            idx.clear();
+            acc = 0;
+        }
+        idx.push_back(k);
+        if (b <= (int64_t)tb_budget) acc += b;
+    }
+    if (idx.empty()) return MPG_OK;
+    return run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(), ops_off,
+                   d_out, d_ops, tb_budget, tm);
+}
+
+int params_check_impl(const mpg_params* p) {
+    if (!p) return MPG_E_INVAL;
+    if (p->q < 0 || p->e < 0 || p->f < 0 || p->r < 0 || p->q + p->e <= 0) return MPG_E_INVAL;
+    if (p->mode < MPG_LOCAL || p->mode > MPG_GLOBAL) return MPG_E_INVAL;
+    if (p->flags & ~(uint32_t)(MPG_NO_INTRON | MPG_NO_FRAMESHIFT | MPG_WANT_TB | MPG_ALLOW_I16))
+        return MPG_E_INVAL;
+    for (int k = 0; k < 64; ++k)
+        if (p->gcode[k] >= 24) return MPG_E_INVAL;
+    if (p->q > (1 << 20) || p->e > (1 << 20) || p->f > (1 << 20) || p->r > (1 << 20))
+        return MPG_E_RANGE;
+    return MPG_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* mpg_strerror(int status) {
+    switch (status) {
+        case MPG_OK: return "ok";
+        case MPG_E_INVAL: return "invalid argument";
+        case MPG_E_RANGE: return "length or score bound out of range";
+        case MPG_E_NOMEM: return "out of memory";
+        case MPG_E_AGAIN: return "queue full, try again";
+        case MPG_E_DEVICE: return "device error";
+        case MPG_E_NOALN: return "no alignment reaches the end cell";
+        case MPG_E_CANCELLED: return "cancelled";
+        default: return "unknown status";
+    }
+}
+
+void mpg_params_default(mpg_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->q = 11;
+    p->e = 1;
+    p->f = 23;
+    p->r = 29;
+    p->flags = 0;
+    p->mode = MPG_LOCAL;
+    std::memcpy(p->mat, kBlosum62, sizeof(p->mat));
+    for (int k = 0; k < 64; ++k) {
+        const char* hit = std::strchr(kAlphabet, kCodeACGT[k]);
+        p->gcode[k] = (uint8_t)(hit - kAlphabet);
+    }
+    for (int b1 = 0; b1 < 5; ++b1)
+        for (int b2 = 0; b2 < 5; ++b2)
+            for (int b3 = 0; b3 < 5; ++b3) {
+                p->donor[25 * b1 + 5 * b2 + b3] = (uint8_t)donor_pen(b1, b2, b3);
+                p->acceptor[25 * b1 + 5 * b2 + b3] = (uint8_t)acceptor_pen(b1, b2, b3);
+            }
+}
+
+int mpg_params_check(const mpg_params* p, int32_t max_plen, int32_t max_dlen) {
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    if (max_plen < 0 || max_dlen < 0) return MPG_E_INVAL;
+    if (max_plen > MPG_MAX_PROT || max_dlen > MPG_MAX_DNA) return MPG_E_RANGE;
+    if (!score_bound_ok(p, max_dlen, max_plen)) return MPG_E_RANGE;
+    return MPG_OK;
+}
+
+int mpg_ctx_create(mpg_ctx** out, int device, uint64_t tb_budget_bytes, uint32_t flags) {
+    if (!out) return MPG_E_INVAL;
+    *out = nullptr;
+    if (flags != 0) return MPG_E_INVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return MPG_E_DEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return MPG_E_DEVICE;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+            hipSuccess &&
+        lds > 0)
+        g_max_lds = std::min(lds, 65536);
+    mpg_ctx* c = new (std::nothrow) mpg_ctx();
+    if (!c) return MPG_E_NOMEM;
+    c->device = device;
+    if (tb_budget_bytes) c->tb_budget = tb_budget_bytes;
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return MPG_E_DEVICE;
+    }
+    c->stream = c->own_stream;
+    c->stats.tb_budget = c->tb_budget;
+    *out = c;
+    return MPG_OK;
+}
+
+int mpg_set_stream(mpg_ctx* ctx, void* s) {
+    if (!ctx) return MPG_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    ctx->stream = s ? (hipStream_t)s : ctx->own_stream;
+    return MPG_OK;
+}
+
+int mpg_sync(mpg_ctx* ctx) {
+    if (!ctx) return MPG_E_INVAL;
+    hipSetDevice(ctx->device);
+    return hip_status(hipStreamSynchronize(ctx->stream));
+}
+
+int64_t mpg_ops_capacity(const mpg_seg* segs, int32_t n) {
+    if (!segs || n < 0) return -1;
+    int64_t o = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const bool tb = (segs[k].flags & MPG_WANT_TB) != 0;
+        o += tb ? 2 * ((int64_t)std::max(0, segs[k].dlen) + std::max(0, segs[k].plen)) + 1 : 1;
+    }
+    return o;
+}
+
+int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot,
+                        const uint8_t* d_dna, const mpg_seg* segs, int32_t n,
+                        mpg_dev_result* d_out, char* d_ops, int64_t ops_cap) {
+    if (!ctx || !p || (n > 0 && (!segs || !d_out))) return MPG_E_INVAL;
+    if (n < 0) return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    if (n == 0) return MPG_OK;
+    // capacity needed with params.flags applied
+    int64_t need = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const bool tb = ((segs[k].flags | p->flags) & MPG_WANT_TB) != 0;
+        need += tb ? 2 * ((int64_t)std::max(0, segs[k].dlen) + std::max(0, segs[k].plen)) + 1 : 1;
+    }
+    if (need > 0 && (!d_ops || ops_cap < need)) return MPG_E_RANGE;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool};
+    ctx->n_calls++;
+    return run_dev_waves(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, n, d_out, d_ops,
+                         ctx->tb_budget, ctx->timing ? &tm : nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Synchronous host-memory batch on a given stream/workspace; fills out[].
+int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pair* pairs,
+               int32_t n, mpg_result* out, uint64_t tb_budget, Timer* tm) {
+    std::vector<mpg_seg> segs(n);
+    int64_t pbytes = 0, dbytes = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        if (pairs[k].plen < 0 || pairs[k].dlen < 0 || (pairs[k].plen && !pairs[k].prot) ||
+            (pairs[k].dlen && !pairs[k].dna))
+            return MPG_E_INVAL;
+        segs[k].prot_off = pbytes;
+        segs[k].plen = pairs[k].plen;
+        segs[k].dna_off = dbytes;
+        segs[k].dlen = pairs[k].dlen;
+        segs[k].flags = pairs[k].flags | (p->flags & MPG_WANT_TB);
+        segs[k]._pad = 0;
+        pbytes += pairs[k].plen;
+        dbytes += pairs[k].dlen;
+    }
+    const int64_t ops_cap = mpg_ops_capacity(segs.data(), n);
+    int rc;
+    if ((rc = ws.seq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return rc;
+    if ((rc = ws.out.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return rc;
+    if ((rc = ws.ops.ensure((size_t)ops_cap + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hseq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hout.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    uint8_t* hs = (uint8_t*)ws.hseq.p;
+    for (int32_t k = 0; k < n; ++k) {
+        if (pairs[k].plen) std::memcpy(hs + segs[k].prot_off, pairs[k].prot, pairs[k].plen);
+        if (pairs[k].dlen) std::memcpy(hs + pbytes + segs[k].dna_off, pairs[k].dna, pairs[k].dlen);
+    }
+    uint8_t* d_seq = (uint8_t*)ws.seq.p;
+    if (pbytes + dbytes > 0 &&
+        hipMemcpyAsync(d_seq, hs, (size_t)(pbytes + dbytes), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        return MPG_E_DEVICE;
+    rc = run_dev_waves(st, ws, p, d_seq, d_seq + pbytes, segs.data(), n,
+                       (mpg_dev_result*)ws.out.p, (char*)ws.ops.p, tb_budget, tm);
+    if (rc != MPG_OK) return rc;
+    if (hipMemcpyAsync(ws.hout.p, ws.out.p, sizeof(mpg_dev_result) * (size_t)n,
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+        return MPG_E_DEVICE;
+    bool any_tb = false;
+    for (int32_t k = 0; k < n; ++k) any_tb |= (segs[k].flags & MPG_WANT_TB) != 0;
+    if (any_tb) {
+        if ((rc = ws.hops.ensure((size_t)ops_cap + 64)) != MPG_OK) return rc;
+        if (hipMemcpyAsync(ws.hops.p, ws.ops.p, (size_t)ops_cap, hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+            return MPG_E_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    const mpg_dev_result* R = (const mpg_dev_result*)ws.hout.p;
+    for (int32_t k = 0; k < n; ++k) {
+        mpg_result& o = out[k];
+        std::memset(&o, 0, sizeof(o));
+        o.status = R[k].status;
+        o.score = R[k].score;
+        o.g_beg = R[k].g_beg;
+        o.g_end = R[k].g_end;
+        o.p_beg = R[k].p_beg;
+        o.p_end = R[k].p_end;
+        o.job_id = (uint64_t)k;
+        o.ops = nullptr;
+        o.ops_len = 0;
+        if ((segs[k].flags & MPG_WANT_TB) && o.status == MPG_OK) {
+            char* sdup = (char*)std::malloc((size_t)R[k].ops_len + 1);
+            if (!sdup) return MPG_E_NOMEM;
+            std::memcpy(sdup, (const char*)ws.hops.p + R[k].ops_off, (size_t)R[k].ops_len);
+            sdup[R[k].ops_len] = 0;
+            o.ops = sdup;
+            o.ops_len = R[k].ops_len;
+        }
+    }
+    return MPG_OK;
+}
+
+// ------------------------------------------------------------------ serving
+// One scheduler thread admits pending jobs into micro-batches while a slot
+// (stream + workspace) and traceback budget are free; up to nslots batches
+// are on the device at once, so arrivals overlap running work.
+void scheduler(mpg_ctx* c) {
+    hipSetDevice(c->device);
+    const int ns = std::max(1, c->nslots);
+    std::vector<hipStream_t> streams(ns);
+    std::vector<Workspace> wss(ns);
+    std::vector<bool> busy(ns, false);
+    std::vector<std::thread> workers(ns);
+    for (int k = 0; k < ns; ++k) hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking);
+    std::unique_lock<std::mutex> lk(c->mu);
+    for (;;) {
+        // admit
+        int slot = -1;
+        for (int k = 0; k < ns; ++k)
+            if (!busy[k]) { slot = k; break; }
+        if (c->stop && c->pending.empty()) {
+            bool any = false;
+            for (int k = 0; k < ns; ++k) any |= busy[k];
+            if (!any) break;
+        }
+        if (slot < 0 || c->pending.empty()) {
+            c->cv_work.wait_for(lk, std::chrono::milliseconds(20));
+            continue;
+        }
+        std::vector<mpg_ctx::Job> batch;
+        int64_t cells = 0, tb = 0;
+        while (!c->pending.empty() && (int)batch.size() < c->max_jobs_per_batch) {
+            mpg_ctx::Job& j = c->pending.front();
+            if (!batch.empty() && cells + j.cells > c->slot_cells) break;
+            if (c->tb_in_use + tb + (uint64_t)j.tb_bytes > c->tb_budget) break;
+            cells += j.cells;
+            tb += j.tb_bytes;
+            batch.push_back(std::move(j));
+            c->pending.pop_front();
+        }
+        if (batch.empty()) {
+            c->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            continue;
+        }
+        busy[slot] = true;
+        c->tb_in_use += (uint64_t)tb;
+        c->stats.tb_bytes_in_use = c->tb_in_use;
+        c->stats.tb_bytes_peak = std::max<uint64_t>(c->stats.tb_bytes_peak, c->tb_in_use);
+        c->stats.in_flight += batch.size();
+        c->stats.queue_depth = c->pending.size();
+        c->stats.batches += 1;
+        if (workers[slot].joinable()) workers[slot].join();
+        mpg_params params = c->sparams;
+        workers[slot] = std::thread([c, slot, tb, params, &streams, &wss, &busy,
+                                     b = std::move(batch)]() mutable {
+            hipSetDevice(c->device);
+            std::vector<mpg_pair> pairs(b.size());
+            for (size_t k = 0; k < b.size(); ++k) {
+                pairs[k].prot = b[k].prot.data();
+                pairs[k].plen = (int32_t)b[k].prot.size();
+                pairs[k].dna = b[k].dna.data();
+                pairs[k].dlen = (int32_t)b[k].dna.size();
+                pairs[k].flags = b[k].flags;
+            }
+            std::vector<mpg_result> res(b.size());
+            params.flags &= ~(uint32_t)MPG_WANT_TB;
+            int rc = align_host(streams[slot], wss[slot], &params, pairs.data(),
+                                (int32_t)pairs.size(), res.data(), (uint64_t)tb + 1, nullptr);
+            const int64_t t = now_ns();
+            std::lock_guard<std::mutex> g(c->mu);
+            for (size_t k = 0; k < b.size(); ++k) {
+                mpg_result r = res[k];
+                if (rc != MPG_OK) {
+                    std::memset(&r, 0, sizeof(r));
+                    r.status = rc;
+                    r.g_beg = r.g_end = r.p_beg = r.p_end = -1;
+                }
+                r.job_id = b[k].id;
+                r.t_arrive_ns = b[k].t_arrive;
+                r.t_done_ns = t;
+                c->done.push_back(r);
+                c->stats.cells += (uint64_t)b[k].cells;
+            }
+            c->stats.completed += b.size();
+            c->stats.in_flight -= b.size();
+            c->tb_in_use -= (uint64_t)tb;
+            c->stats.tb_bytes_in_use = c->tb_in_use;
+            busy[slot] = false;
+            c->cv_done.notify_all();
+            c->cv_work.notify_all();
+        });
+    }
+    lk.unlock();
+    for (auto& w : workers)
+        if (w.joinable()) w.join();
+    for (auto& w : wss) w.release();
+    for (auto& s : streams) hipStreamDestroy(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, int32_t n,
+                    mpg_result* out) {
+    if (!ctx || !p || n < 0 || (n > 0 && (!pairs || !out))) return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    if (n == 0) return MPG_OK;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool};
+    ctx->n_calls++;
+    return align_host(ctx->stream, ctx->ws, p, pairs, n, out, ctx->tb_budget,
+                      ctx->timing ? &tm : nullptr);
+}
+
+int mpg_submit(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pair, uint64_t* job_id) {
+    if (!ctx || !p || !pair || !job_id) return MPG_E_INVAL;
+    if (pair->plen < 0 || pair->dlen < 0 || (pair->plen && !pair->prot) ||
+        (pair->dlen && !pair->dna))
+        return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    if (!ctx->params_set) {
+        ctx->sparams = *p;
+        ctx->params_set = true;
+    } else if (std::memcmp(&ctx->sparams, p, sizeof(*p)) != 0) {
+        return MPG_E_INVAL;
+    }
+    const bool tb = ((pair->flags | p->flags) & MPG_WANT_TB) != 0;
+    const int64_t tbb = tb ? tb_bytes_of(pair->dlen, pair->plen, choose_K(pair->plen)) : 0;
+    if (pair->dlen > MPG_MAX_DNA || pair->plen > MPG_MAX_PROT || (uint64_t)tbb > ctx->tb_budget ||
+        !score_bound_ok(p, pair->dlen, pair->plen)) {
+        ctx->stats.rejected_range++;
+        return MPG_E_RANGE;
+    }
+    if (ctx->pending.size() >= ctx->max_pending) {
+        ctx->stats.rejected_again++;
+        return MPG_E_AGAIN;
+    }
+    mpg_ctx::Job j;
+    j.id = ctx->next_id++;
+    j.prot.assign(pair->prot ? pair->prot : "", (size_t)pair->plen);
+    j.dna.assign(pair->dna ? pair->dna : "", (size_t)pair->dlen);
+    j.flags = tb ? (uint32_t)MPG_WANT_TB : 0u;
+    j.t_arrive = now_ns();
+    j.tb_bytes = tbb;
+    j.cells = (int64_t)(pair->dlen + 64) * (pair->plen + 1);
+    *job_id = j.id;
+    ctx->pending.push_back(std::move(j));
+    ctx->stats.submitted++;
+    ctx->stats.queue_depth = ctx->pending.size();
+    if (!ctx->sched_running) {
+        ctx->stop = false;
+        ctx->sched = std::thread(scheduler, ctx);
+        ctx->sched_running = true;
+    }
+    lk.unlock();
+    ctx->cv_work.notify_one();
+    return MPG_OK;
+}
+
+int mpg_poll(mpg_ctx* ctx, mpg_result* out, int32_t max_results, int32_t timeout_us) {
+    if (!ctx || (max_results > 0 && !out) || max_results < 0) return MPG_E_INVAL;
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    if (ctx->done.empty() && timeout_us > 0)
+        ctx->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
+                              [ctx] { return !ctx->done.empty(); });
+    int k = 0;
+    const int64_t t = now_ns();
+    while (k < max_results && !ctx->done.empty()) {
+        out[k] = ctx->done.front();
+        if (out[k].t_done_ns == 0) out[k].t_done_ns = t;
+        ctx->done.pop_front();
+        ++k;
+    }
+    return k;
+}
+
+int mpg_cancel(mpg_ctx* ctx, uint64_t job_id) {
+    if (!ctx) return MPG_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto it = ctx->pending.begin(); it != ctx->pending.end(); ++it) {
+        if (it->id == job_id) {
+            mpg_result r;
+            std::memset(&r, 0, sizeof(r));
+            r.status = MPG_E_CANCELLED;
+            r.g_beg = r.g_end = r.p_beg = r.p_end = -1;
+            r.job_id = job_id;
+            r.t_arrive_ns = it->t_arrive;
+            r.t_done_ns = now_ns();
+            ctx->pending.erase(it);
+            ctx->done.push_back(r);
+            ctx->stats.cancelled++;
+            ctx->stats.queue_depth = ctx->pending.size();
+            ctx->cv_done.notify_all();
+            return MPG_OK;
+        }
+    }
+    return MPG_E_INVAL;
+}
+
+int mpg_enable_timing(mpg_ctx* ctx, int on) {
+    if (!ctx) return MPG_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    ctx->timing = on != 0;
+    return MPG_OK;
+}
+
+int mpg_get_timing(mpg_ctx* ctx, mpg_timing* t, int reset) {
+    if (!ctx || !t) return MPG_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    auto drain = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& acc,
+                     uint64_t* cnt) -> int {
+        for (auto& pr : v) {
+            if (hipEventSynchronize(pr.second) != hipSuccess) return MPG_E_DEVICE;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) return MPG_E_DEVICE;
+            acc += ms;
+            if (cnt) ++*cnt;
+            ctx->ev_pool.push_back(pr.first);
+            ctx->ev_pool.push_back(pr.second);
+        }
+        v.clear();
+        return MPG_OK;
+    };
+    int rc;
+    if ((rc = drain(ctx->ev_pre, ctx->t_pre, nullptr)) != MPG_OK) return rc;
+    if ((rc = drain(ctx->ev_dp, ctx->t_dp, &ctx->n_dp)) != MPG_OK) return rc;
+    if ((rc = drain(ctx->ev_walk, ctx->t_walk, nullptr)) != MPG_OK) return rc;
+    t->prepass_ms = ctx->t_pre;
+    t->dp_ms = ctx->t_dp;
+    t->walk_ms = ctx->t_walk;
+    t->dp_spans = ctx->n_dp;
+    t->calls = ctx->n_calls;
+    if (reset) {
+        ctx->t_pre = ctx->t_dp = ctx->t_walk = 0;
+        ctx->n_dp = ctx->n_calls = 0;
+    }
+    return MPG_OK;
+}
+
+int mpg_get_stats(mpg_ctx* ctx, mpg_stats* st) {
+    if (!ctx || !st) return MPG_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *st = ctx->stats;
+    st->tb_budget = ctx->tb_budget;
+    return MPG_OK;
+}
+
+void mpg_result_release(mpg_ctx* ctx, mpg_result* r, int32_t n) {
+    (void)ctx;
+    if (!r) return;
+    for (int32_t k = 0; k < n; ++k) {
+        std::free((void*)r[k].ops);
+        r[k].ops = nullptr;
+        r[k].ops_len = 0;
+    }
+}
+
+void mpg_ctx_destroy(mpg_ctx* ctx) {
+    if (!ctx) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->stop = true;
+    }
+    ctx->cv_work.notify_all();
+    if (ctx->sched_running && ctx->sched.joinable()) ctx->sched.join();
+    hipSetDevice(ctx->device);
+    if (ctx->own_stream) {
+        hipStreamSynchronize(ctx->own_stream);
+        hipStreamDestroy(ctx->own_stream);
+    }
+    ctx->ws.release();
+    for (auto* v : {&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk})
+        for (auto& pr : *v) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+    for (auto e : ctx->ev_pool) hipEventDestroy(e);
+    for (auto& r : ctx->done) std::free((void*)r.ops);
+    delete ctx;
+}
+
+}  // extern "C"

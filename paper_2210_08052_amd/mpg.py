@@ -1,0 +1,289 @@
+"""Thin ctypes binding of ``libmpg.so`` (the C ABI declared in include/mpg.h).
+
+Only argument marshalling happens here: every step of the alignment runs in
+the library's HIP kernels.  If the library is not built this module raises on
+import of the library (``lib()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpg.so")
+
+MPG_OK, MPG_E_INVAL, MPG_E_RANGE, MPG_E_NOMEM = 0, -1, -2, -3
+MPG_E_AGAIN, MPG_E_DEVICE, MPG_E_NOALN, MPG_E_CANCELLED = -4, -5, -6, -7
+MPG_LOCAL, MPG_EXTEND, MPG_GLOBAL = 0, 1, 2
+MPG_NO_INTRON, MPG_NO_FRAMESHIFT, MPG_WANT_TB, MPG_ALLOW_I16 = 1, 2, 4, 8
+MPG_MAX_DNA, MPG_MAX_PROT = 1040000, 32000
+
+
+class mpg_params(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("e", ctypes.c_int32), ("f", ctypes.c_int32),
+                ("r", ctypes.c_int32), ("flags", ctypes.c_uint32), ("mode", ctypes.c_int32),
+                ("mat", (ctypes.c_int8 * 24) * 24), ("gcode", ctypes.c_uint8 * 64),
+                ("donor", ctypes.c_uint8 * 125), ("acceptor", ctypes.c_uint8 * 125),
+                ("_pad", ctypes.c_uint8 * 2)]
+
+
+class mpg_pair(ctypes.Structure):
+    _fields_ = [("prot", ctypes.c_char_p), ("plen", ctypes.c_int32),
+                ("dna", ctypes.c_char_p), ("dlen", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class mpg_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("score", ctypes.c_int32),
+                ("g_beg", ctypes.c_int32), ("g_end", ctypes.c_int32),
+                ("p_beg", ctypes.c_int32), ("p_end", ctypes.c_int32),
+                ("ops", ctypes.c_void_p), ("ops_len", ctypes.c_int32), ("_pad", ctypes.c_int32),
+                ("job_id", ctypes.c_uint64), ("t_arrive_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class mpg_seg(ctypes.Structure):
+    _fields_ = [("prot_off", ctypes.c_int64), ("dna_off", ctypes.c_int64),
+                ("plen", ctypes.c_int32), ("dlen", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("_pad", ctypes.c_int32)]
+
+
+class mpg_dev_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("score", ctypes.c_int32),
+                ("g_beg", ctypes.c_int32), ("g_end", ctypes.c_int32),
+                ("p_beg", ctypes.c_int32), ("p_end", ctypes.c_int32),
+                ("ops_off", ctypes.c_int64), ("ops_len", ctypes.c_int32),
+                ("_pad", ctypes.c_int32)]
+
+
+class mpg_stats(ctypes.Structure):
+    _fields_ = [(nm, ctypes.c_uint64) for nm in (
+        "submitted", "completed", "cancelled", "rejected_again", "rejected_range", "batches",
+        "cells", "queue_depth", "in_flight", "tb_bytes_in_use", "tb_bytes_peak", "tb_budget")]
+
+
+class mpg_timing(ctypes.Structure):
+    _fields_ = [("prepass_ms", ctypes.c_double), ("dp_ms", ctypes.c_double),
+                ("walk_ms", ctypes.c_double), ("dp_spans", ctypes.c_uint64),
+                ("calls", ctypes.c_uint64)]
+
+
+SEG_DTYPE = np.dtype([("prot_off", "<i8"), ("dna_off", "<i8"), ("plen", "<i4"),
+                      ("dlen", "<i4"), ("flags", "<u4"), ("_pad", "<i4")])
+DEV_RESULT_DTYPE = np.dtype([("status", "<i4"), ("score", "<i4"), ("g_beg", "<i4"),
+                             ("g_end", "<i4"), ("p_beg", "<i4"), ("p_end", "<i4"),
+                             ("ops_off", "<i8"), ("ops_len", "<i4"), ("_pad", "<i4")])
+
+EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_default",
+           "mpg_params_check", "mpg_align_batch", "mpg_ops_capacity", "mpg_align_batch_dev",
+           "mpg_sync", "mpg_submit", "mpg_poll", "mpg_cancel", "mpg_get_stats",
+           "mpg_result_release", "mpg_strerror", "mpg_enable_timing", "mpg_get_timing"]
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes this library bind to that copy, so one process never
+        # holds two HIP runtimes (the second would find no GPU).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmpg.so is not built; run python -m paper_2210_08052_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.mpg_ctx_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int, ctypes.c_uint64,
+                                     ctypes.c_uint32]
+        L.mpg_ctx_destroy.argtypes = [ctypes.c_void_p]
+        L.mpg_ctx_destroy.restype = None
+        L.mpg_set_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.mpg_params_default.argtypes = [P(mpg_params)]
+        L.mpg_params_default.restype = None
+        L.mpg_params_check.argtypes = [P(mpg_params), ctypes.c_int32, ctypes.c_int32]
+        L.mpg_align_batch.argtypes = [ctypes.c_void_p, P(mpg_params), P(mpg_pair),
+                                      ctypes.c_int32, P(mpg_result)]
+        L.mpg_ops_capacity.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.mpg_ops_capacity.restype = ctypes.c_int64
+        L.mpg_align_batch_dev.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.mpg_sync.argtypes = [ctypes.c_void_p]
+        L.mpg_submit.argtypes = [ctypes.c_void_p, P(mpg_params), P(mpg_pair),
+                                 P(ctypes.c_uint64)]
+        L.mpg_poll.argtypes = [ctypes.c_void_p, P(mpg_result), ctypes.c_int32, ctypes.c_int32]
+        L.mpg_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        L.mpg_get_stats.argtypes = [ctypes.c_void_p, P(mpg_stats)]
+        L.mpg_result_release.argtypes = [ctypes.c_void_p, P(mpg_result), ctypes.c_int32]
+        L.mpg_result_release.restype = None
+        L.mpg_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.mpg_get_timing.argtypes = [ctypes.c_void_p, P(mpg_timing), ctypes.c_int]
+        L.mpg_strerror.argtypes = [ctypes.c_int]
+        L.mpg_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(st: int) -> str:
+    return lib().mpg_strerror(st).decode()
+
+
+def check(st: int, what: str = "mpg call"):
+    if st < 0:
+        raise RuntimeError("%s failed: %s (%d)" % (what, strerror(st), st))
+    return st
+
+
+def params(**kw) -> mpg_params:
+    """Library defaults (mpg_params_default) with fields overridden by kw:
+    q, e, f, r, flags, mode (ints) and mat (24x24), gcode (64), donor and
+    acceptor (125) arrays."""
+    p = mpg_params()
+    lib().mpg_params_default(ctypes.byref(p))
+    for k in ("q", "e", "f", "r", "flags", "mode"):
+        if k in kw and kw[k] is not None:
+            setattr(p, k, int(kw[k]))
+    if kw.get("mat") is not None:
+        m = np.ascontiguousarray(kw["mat"], dtype=np.int8).reshape(24, 24)
+        ctypes.memmove(ctypes.addressof(p.mat), m.ctypes.data, 576)
+    for k, n in (("gcode", 64), ("donor", 125), ("acceptor", 125)):
+        if kw.get(k) is not None:
+            a = np.ascontiguousarray(kw[k], dtype=np.uint8).reshape(n)
+            ctypes.memmove(ctypes.addressof(getattr(p, k)), a.ctypes.data, n)
+    return p
+
+
+def params_arrays(p: mpg_params) -> dict:
+    """The arrays of a params struct (for comparisons in tests)."""
+    return {"q": p.q, "e": p.e, "f": p.f, "r": p.r, "flags": p.flags, "mode": p.mode,
+            "mat": np.ctypeslib.as_array(p.mat).copy(),
+            "gcode": np.ctypeslib.as_array(p.gcode).copy(),
+            "donor": np.ctypeslib.as_array(p.donor).copy(),
+            "acceptor": np.ctypeslib.as_array(p.acceptor).copy()}
+
+
+class Context:
+    """Owns one mpg_ctx on a HIP device."""
+
+    def __init__(self, device: int = 0, tb_budget_bytes: int = 0):
+        self.ptr = ctypes.c_void_p()
+        check(lib().mpg_ctx_create(ctypes.byref(self.ptr), device, tb_budget_bytes, 0),
+              "mpg_ctx_create")
+
+    def close(self):
+        if self.ptr:
+            lib().mpg_ctx_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_handle: int):
+        check(lib().mpg_set_stream(self.ptr, ctypes.c_void_p(stream_handle)), "mpg_set_stream")
+
+    # ---- host-memory batch
+    def align_batch(self, pairs, p: mpg_params, want_tb=None):
+        """pairs: list of (prot, dna[, want_tb]) bytes; returns a list of dicts."""
+        n = len(pairs)
+        arr = (mpg_pair * max(n, 1))()
+        keep = []
+        for k, pr in enumerate(pairs):
+            prot, dna = pr[0], pr[1]
+            tb = pr[2] if len(pr) > 2 else want_tb
+            prot = prot.encode() if isinstance(prot, str) else bytes(prot)
+            dna = dna.encode() if isinstance(dna, str) else bytes(dna)
+            keep.append((prot, dna))
+            arr[k].prot = prot
+            arr[k].plen = len(prot)
+            arr[k].dna = dna
+            arr[k].dlen = len(dna)
+            arr[k].flags = MPG_WANT_TB if tb else 0
+        out = (mpg_result * max(n, 1))()
+        check(lib().mpg_align_batch(self.ptr, ctypes.byref(p), arr, n, out), "mpg_align_batch")
+        res = [_result_dict(out[k]) for k in range(n)]
+        lib().mpg_result_release(self.ptr, out, n)
+        return res
+
+    # ---- device-resident batch (torch tensors for memory only)
+    def align_batch_dev(self, p: mpg_params, d_prot, d_dna, segs: np.ndarray, d_out, d_ops,
+                        ops_cap: int):
+        """Enqueue on the context's stream.  d_prot/d_dna/d_out/d_ops are
+        device pointers (ints); segs a SEG_DTYPE numpy array."""
+        segs = np.ascontiguousarray(segs, dtype=SEG_DTYPE)
+        check(lib().mpg_align_batch_dev(self.ptr, ctypes.byref(p), ctypes.c_void_p(d_prot),
+                                        ctypes.c_void_p(d_dna), segs.ctypes.data, len(segs),
+                                        ctypes.c_void_p(d_out), ctypes.c_void_p(d_ops),
+                                        int(ops_cap)), "mpg_align_batch_dev")
+
+    def sync(self):
+        check(lib().mpg_sync(self.ptr), "mpg_sync")
+
+    def enable_timing(self, on: bool = True):
+        check(lib().mpg_enable_timing(self.ptr, 1 if on else 0), "mpg_enable_timing")
+
+    def timing(self, reset: bool = True) -> dict:
+        t = mpg_timing()
+        check(lib().mpg_get_timing(self.ptr, ctypes.byref(t), 1 if reset else 0),
+              "mpg_get_timing")
+        return {k: getattr(t, k) for k, _ in mpg_timing._fields_}
+
+    # ---- serving
+    def submit(self, p: mpg_params, prot: bytes, dna: bytes, want_tb: bool = False) -> int:
+        pr = mpg_pair(prot, len(prot), dna, len(dna), MPG_WANT_TB if want_tb else 0)
+        jid = ctypes.c_uint64(0)
+        st = lib().mpg_submit(self.ptr, ctypes.byref(p), ctypes.byref(pr), ctypes.byref(jid))
+        if st < 0:
+            return st
+        return int(jid.value)
+
+    def poll(self, max_results: int = 256, timeout_us: int = 0):
+        out = (mpg_result * max_results)()
+        k = check(lib().mpg_poll(self.ptr, out, max_results, timeout_us), "mpg_poll")
+        res = [_result_dict(out[i]) for i in range(k)]
+        lib().mpg_result_release(self.ptr, out, k)
+        return res
+
+    def cancel(self, job_id: int) -> int:
+        return lib().mpg_cancel(self.ptr, ctypes.c_uint64(job_id))
+
+    def stats(self) -> dict:
+        s = mpg_stats()
+        check(lib().mpg_get_stats(self.ptr, ctypes.byref(s)), "mpg_get_stats")
+        return {k: int(getattr(s, k)) for k, _ in mpg_stats._fields_}
+
+
+def _result_dict(r: mpg_result) -> dict:
+    ops = ctypes.string_at(r.ops, r.ops_len).decode() if r.ops else None
+    return {"status": r.status, "score": r.score, "g_beg": r.g_beg, "g_end": r.g_end,
+            "p_beg": r.p_beg, "p_end": r.p_end, "ops": ops, "job_id": int(r.job_id),
+            "t_arrive_ns": int(r.t_arrive_ns), "t_done_ns": int(r.t_done_ns)}
+
+
+def pack_pairs(pairs):
+    """Concatenate proteins and regions; returns (prot_bytes, dna_bytes, segs)."""
+    segs = np.zeros(len(pairs), dtype=SEG_DTYPE)
+    pb, db = [], []
+    po = do = 0
+    for k, pr in enumerate(pairs):
+        prot, dna = pr[0], pr[1]
+        tb = pr[2] if len(pr) > 2 else False
+        segs[k] = (po, do, len(prot), len(dna), MPG_WANT_TB if tb else 0, 0)
+        pb.append(prot)
+        db.append(dna)
+        po += len(prot)
+        do += len(dna)
+    return b"".join(pb), b"".join(db), segs

@@ -1,0 +1,220 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle,
+element by element, on the same seeded inputs.  Integer results, so the bar
+is exact equality of score, begin/end coordinates and op string."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_08052_amd import mpg
+from paper_2210_08052_amd import workloads as W
+
+from _cases import compare, key_gpu, key_orc, scorings
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mpg.Context(0)
+    yield c
+    c.close()
+
+
+def _pairs(seed, n=40, max_prot=150, max_dna=700, dna="ACGTGTAGN", min_prot=0, min_dna=0):
+    return [(p.prot, p.dna) for p in W.random_pairs(n, seed, max_prot=max_prot, max_dna=max_dna,
+                                                    alphabet_dna=dna, min_prot=min_prot,
+                                                    min_dna=min_dna)]
+
+
+@pytest.mark.parametrize("tb", [False, True])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_random_small_default_scoring(ctx, mode, flags, tb):
+    print("case mode=%d flags=%d tb=%d" % (mode, flags, tb), flush=True)
+    g, o = scorings(mode, flags)
+    compare(ctx, _pairs(100 + 10 * mode + flags), g, o, tb, label="default")
+
+
+@pytest.mark.parametrize("tb", [False, True])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_random_small_random_scoring(ctx, mode, tb):
+    for rs in range(3):
+        print("case mode=%d tb=%d rs=%d" % (mode, tb, rs), flush=True)
+        g, o = scorings(mode, rs % 4, rand_seed=200 + rs)
+        compare(ctx, _pairs(300 + rs + 7 * mode, n=30), g, o, tb, label="random%d" % rs)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+@pytest.mark.parametrize("Wv", [1, 2, 3])
+def test_kernel_variants(ctx, K, Wv, monkeypatch):
+    """Every columns-per-lane width and the multi-wavefront tiled schedule
+    (W waves per pair handing the boundary column over through LDS) give
+    identical results; proteins span several strips and ragged tails."""
+    monkeypatch.setenv("MPG_FORCE_K", str(K))
+    monkeypatch.setenv("MPG_FORCE_W", str(Wv))
+    pairs = _pairs(400 + K * 10 + Wv, n=24, max_prot=700, max_dna=900, min_prot=100)
+    for mode in (0, 1, 2):
+        for tb in (False, True):
+            print("case K=%d W=%d mode=%d tb=%d" % (K, Wv, mode, tb), flush=True)
+            g, o = scorings(mode, 0)
+            compare(ctx, pairs, g, o, tb, label="K%d W%d m%d" % (K, Wv, mode))
+
+
+def test_edge_cases(ctx):
+    cases = [("", ""), ("M", ""), ("", "ACG"), ("MKV", "A"), ("W", "TGG"), ("WW", "tggtgg"),
+             ("XB*Z", "NNNTAGNNN"), ("acdefghik", "gcttgtgatgaattttggtcatattaaa"),
+             ("JOU?", "RYKMACGT"), ("M" * 200, "ATG"), ("M", "ATG" * 400),
+             ("MKVLAT", "ATGAAAGTAAGTAAGTTTTTTTTCAGCTGGCGACC")]
+    for mode in (0, 1, 2):
+        for tb in (False, True):
+            print("case edge mode=%d tb=%d" % (mode, tb), flush=True)
+            g, o = scorings(mode, 0)
+            compare(ctx, cases, g, o, tb, label="edge m%d" % mode)
+            g, o = scorings(mode, 3)
+            compare(ctx, cases, g, o, tb, label="edge flags3 m%d" % mode)
+
+
+def test_single_planted_pair(ctx):
+    """3,000-nt region, 100 aa, two introns: exact traceback."""
+    p = W.single_pair(1)
+    g, o = scorings(0, 0)
+    r = compare(ctx, [(p.prot, p.dna)], g, o, True, label="single")[0]
+    print("single pair:", r["score"], r["g_beg"], r["g_end"], r["ops"], flush=True)
+    # the alignment spans the planted gene through at least one intron (a very
+    # short middle exon may legitimately be absorbed into a longer intron)
+    ex = p.truth["exons"]
+    assert sum(1 for ch in r["ops"] if ch in "NUV") >= 1
+    assert r["g_beg"] <= ex[0][0] + 30 and r["g_end"] >= ex[-1][1] - 30
+
+
+def test_batch_full_size_sampled(ctx):
+    """The 10,000-pair planted batch at full size in one call (score-only and
+    traceback); a seeded sample is checked against the oracle, and scores,
+    end cells and traceback runs agree for every pair."""
+    pairs = W.batch_pairs(10000, seed=2)
+    g, o = scorings(0, 0)
+    so = ctx.align_batch([(p.prot, p.dna, False) for p in pairs], g)
+    tb = ctx.align_batch([(p.prot, p.dna, True) for p in pairs], g)
+    for a, b in zip(so, tb):
+        assert a["status"] == b["status"] == 0
+        assert (a["score"], a["g_end"], a["p_end"]) == (b["score"], b["g_end"], b["p_end"])
+    rng = np.random.default_rng(7)
+    idx = rng.choice(len(pairs), size=40, replace=False)
+    sample = [(pairs[k].prot, pairs[k].dna) for k in idx]
+    exp_tb = oracle.align_many(sample, o, want_tb=True)
+    for k, e in zip(idx, exp_tb):
+        assert key_gpu(tb[k], True) == key_orc(e, True), int(k)
+        assert key_gpu(so[k], False) == key_orc(e, False), int(k)
+
+
+def test_long_pairs_tiled(ctx):
+    """Long proteins against long regions run in the multi-wavefront tiled
+    kernel; a few moderately long planted pairs are checked exactly."""
+    rng = np.random.default_rng(11)
+    pairs = []
+    for s in range(3):
+        gen = np.random.Generator(np.random.PCG64(900 + s))
+        L = int(gen.integers(1500, 2500))
+        ilens = [int(x) for x in gen.integers(500, 4000, size=8)]
+        prot, gene, _ = W.planted_gene(gen, L, 0.25, 2, ilens, [True] * 8)
+        pad = W.BASES[gen.integers(0, 4, size=4000)].tobytes()
+        pairs.append((prot, pad + gene.tobytes() + pad))
+    g, o = scorings(0, 0)
+    os.environ["MPG_FORCE_W"] = "4"
+    try:
+        compare(ctx, pairs, g, o, True, label="long tb")
+        compare(ctx, pairs, g, o, False, label="long so")
+    finally:
+        del os.environ["MPG_FORCE_W"]
+
+
+def test_batching_invariance(ctx):
+    pairs = _pairs(555, n=30, max_prot=300, max_dna=2000)
+    g, _ = scorings(0, 0)
+    whole = ctx.align_batch([(p, d, True) for p, d in pairs], g)
+    rev = ctx.align_batch([(p, d, True) for p, d in reversed(pairs)], g)[::-1]
+    alone = [ctx.align_batch([(p, d, True)], g)[0] for p, d in pairs[:8]]
+    mixed = ctx.align_batch([(p, d, k % 2 == 0) for k, (p, d) in enumerate(pairs)], g)
+    for k in range(len(pairs)):
+        assert key_gpu(whole[k], True) == key_gpu(rev[k], True)
+        assert key_gpu(whole[k], False) == key_gpu(mixed[k], False)
+        if k % 2 == 0:
+            assert key_gpu(whole[k], True) == key_gpu(mixed[k], True)
+    for k in range(8):
+        assert key_gpu(whole[k], True) == key_gpu(alone[k], True)
+
+
+def test_traceback_budget_waves(ctx):
+    """A traceback budget far below the batch's needs runs it in waves with
+    identical results; a pair above the whole budget is rejected."""
+    pairs = _pairs(777, n=20, max_prot=300, max_dna=3000, min_prot=50, min_dna=500)
+    g, _ = scorings(0, 0)
+    ref = ctx.align_batch([(p, d, True) for p, d in pairs], g)
+    with mpg.Context(0, tb_budget_bytes=2 << 20) as small:
+        got = small.align_batch([(p, d, True) for p, d in pairs], g)
+        big = small.align_batch([(b"M" * 3000, b"ACGT" * 20000, True)], g)[0]
+    for a, b in zip(ref, got):
+        assert key_gpu(a, True) == key_gpu(b, True)
+    assert big["status"] == mpg.MPG_E_RANGE
+
+
+def test_range_errors(ctx):
+    g, _ = scorings(2, 0)
+    res = ctx.align_batch([(b"M" * 10, b"A" * 900000, False), (b"MK", b"ATGAAA", False)], g)
+    assert res[0]["status"] == mpg.MPG_E_RANGE
+    assert res[1]["status"] == 0 and res[1]["score"] > 0
+
+
+def test_device_resident_entry(ctx):
+    import torch
+    pairs = _pairs(888, n=50, max_prot=400, max_dna=3000)
+    g, _ = scorings(0, 0)
+    ref = ctx.align_batch([(p, d, k % 3 == 0) for k, (p, d) in enumerate(pairs)], g)
+    pb, db, segs = mpg.pack_pairs([(p, d, k % 3 == 0) for k, (p, d) in enumerate(pairs)])
+    dev = torch.device("cuda:0")
+    d_prot = torch.frombuffer(bytearray(pb), dtype=torch.uint8).to(dev)
+    d_dna = torch.frombuffer(bytearray(db), dtype=torch.uint8).to(dev)
+    cap = mpg.lib().mpg_ops_capacity(segs.ctypes.data, len(segs))
+    d_ops = torch.zeros(cap, dtype=torch.uint8, device=dev)
+    d_out = torch.zeros(len(pairs) * mpg.DEV_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    ctx.align_batch_dev(g, d_prot.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
+                        d_ops.data_ptr(), cap)
+    ctx.sync()
+    out = np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=mpg.DEV_RESULT_DTYPE)
+    ops = d_ops.cpu().numpy().tobytes()
+    for k, r in enumerate(ref):
+        assert (out["status"][k], out["score"][k], out["g_end"][k], out["p_end"][k]) == (
+            r["status"], r["score"], r["g_end"], r["p_end"])
+        if k % 3 == 0:
+            o0 = int(out["ops_off"][k])
+            assert ops[o0:o0 + int(out["ops_len"][k])].decode() == r["ops"]
+            assert (out["g_beg"][k], out["p_beg"][k]) == (r["g_beg"], r["p_beg"])
+
+
+def test_serving_matches_batch(ctx):
+    """Jobs submitted one by one are admitted into overlapping micro-batches;
+    each result equals the same pair's batch result."""
+    pairs = _pairs(999, n=60, max_prot=400, max_dna=4000)
+    g, _ = scorings(0, 0)
+    ref = ctx.align_batch([(p, d, k % 2 == 0) for k, (p, d) in enumerate(pairs)], g)
+    with mpg.Context(0) as srv:
+        ids = {}
+        for k, (p, d) in enumerate(pairs):
+            jid = srv.submit(g, p, d, want_tb=(k % 2 == 0))
+            assert jid > 0
+            ids[jid] = k
+        got = {}
+        import time
+        t0 = time.time()
+        while len(got) < len(pairs) and time.time() - t0 < 60:
+            for r in srv.poll(64, 100000):
+                got[ids[r["job_id"]]] = r
+        st = srv.stats()
+    assert len(got) == len(pairs)
+    assert st["completed"] == len(pairs) and st["tb_bytes_in_use"] == 0
+    for k in range(len(pairs)):
+        tb = k % 2 == 0
+        assert key_gpu(got[k], tb) == key_gpu(ref[k], tb)
+        assert got[k]["t_done_ns"] >= got[k]["t_arrive_ns"] > 0
