@@ -100,6 +100,20 @@ struct Sentinel {
     static constexpr int UNREACH = MODE == MPG_LOCAL ? NEG / 2 : -(1 << 29);
 };
 
+// Bounded wait for a workgroup-local progress counter.  Gives up (and tells
+// every other wave to give up) after about 2^22 polls, so no wave can spin
+// forever; the pair then reports MPG_E_DEVICE.
+__device__ __forceinline__ bool wait_at_least(int* flag, int target, int* dead) {
+    for (int it = 0; it < (1 << 22); ++it) {
+        if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target)
+            return true;
+        if (__hip_atomic_load(dead, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(dead, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return false;
+}
+
 extern "C" __device__ int mpg_writelane_i32(int val, int lane, int old) __asm(
     "llvm.amdgcn.writelane.i32");
 
@@ -132,6 +146,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
                                       LY::PROF + LY::IN + LY::OUT);
     uint64_t* red = (uint64_t*)(smem + W * LY::WAVE);
     int* gsc = (int*)(red + 16);
+    int* prog = gsc + 4;   // chunks whose last column wave w has published (all passes)
+    int* cons = prog + 16; // chunks whose input wave w has copied out of the ring
+    int* dead = cons + 16; // set when a bounded wait gave up
 
     const int n = J.n, m = J.m;
     const int nchunks = J.nchunks, nstrips = J.nstrips;
@@ -147,12 +164,27 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
     const int cf = TB ? 16 * P.f : P.f;
 
     uint64_t best_key = 0;
-    if (threadIdx.x == 0) *gsc = NEG;
+    if (threadIdx.x < 16) {
+        prog[threadIdx.x] = 0;
+        cons[threadIdx.x] = 0;
+    }
+    if (threadIdx.x == 0) {
+        *gsc = NEG;
+        *dead = 0;
+    }
+    __syncthreads();
 
-    const int npasses = (nstrips + W - 1) / W;
-    for (int pass = 0; pass < npasses; ++pass) {
-        const int strip = pass * W + wid;
-        const bool act = strip < nstrips;
+    // W_eff waves take the strips W_eff at a time; surplus waves stay idle
+    int Weff = W < nstrips ? W : nstrips;
+    const int npasses = (nstrips + Weff - 1) / Weff;
+    Weff = (nstrips + npasses - 1) / npasses;
+    bool failed = false;
+    for (int pass = 0; pass < npasses && !failed; ++pass) {
+        const int strip = pass * Weff + wid;
+        const bool act = wid < Weff && strip < nstrips;
+        if (!act) break;
+        const int base = pass * nchunks;  // chunk counters run across passes
+        const bool has_next = strip + 1 < nstrips;
         const int col0 = strip * LY::SW + lane * K;  // DP column of this lane's first column
 
         // ---- strip set-up: profile, registers, first descriptors and boundary
@@ -213,23 +245,46 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
             if (TB) *(int4*)(ring + (64 + lane) * LY::DS + 16) = *(const int4*)(src2 + 16);
         }
         int2 nb = make_int2(NEG, NEG);
-        const bool from_global = act && strip > 0 && wid == 0;
-        if (from_global) nb = bnd_g[kBndLo + lane];
+        // wave 0 of a later pass reads the last column of the previous pass's
+        // last strip from HBM, published by wave Weff-1 chunk by chunk
+        const bool from_global = strip > 0 && wid == 0;
+        const int gprev = base - nchunks;
+        if (from_global) {
+            if (!wait_at_least(&prog[Weff - 1], gprev + (nchunks < 2 ? nchunks : 2), dead)) {
+                failed = true;
+                break;
+            }
+            nb = bnd_g[kBndLo + lane];
+        }
 
-        const int Eend = nchunks + 2 * (W - 1);
-        for (int E = 0; E < Eend; ++E) {
-            const int ch = E - 2 * wid;
-            if (act && ch >= 0 && ch < nchunks) {
+        for (int ch = 0; ch < nchunks; ++ch) {
+            {
                 // incoming boundary rows ch*64 .. ch*64+63 of the left strip
                 // (rows beyond n were never written by the left strip's last
                 // lane, or hold garbage-row values: they enter as -infinity)
                 const bool beyond = ch * 64 + lane > n;
                 if (from_global) {
                     inb[lane] = beyond ? make_int2(NEG, NEG) : nb;
-                    nb = bnd_g[kBndLo + (ch + 1) * 64 + lane];
+                    if (ch + 1 < nchunks) {
+                        const int need = gprev + (ch + 3 < nchunks ? ch + 3 : nchunks);
+                        if (!wait_at_least(&prog[Weff - 1], need, dead)) {
+                            failed = true;
+                            break;
+                        }
+                        nb = bnd_g[kBndLo + (ch + 1) * 64 + lane];
+                    }
                 } else if (wid > 0) {
+                    const int need = base + (ch + 2 < nchunks ? ch + 2 : nchunks);
+                    if (!wait_at_least(&prog[wid - 1], need, dead)) {
+                        failed = true;
+                        break;
+                    }
                     const int2 v = xr_in[(ch * 64 + lane) % 192];
                     inb[lane] = beyond ? make_int2(NEG, NEG) : v;
+                    // the ring rows of this chunk are no longer needed
+                    if (lane == 0)
+                        __hip_atomic_store(&cons[wid], base + ch + 1, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
                 if (ch > 0) {
                     // slide the descriptor ring: current chunk -> previous half
@@ -428,14 +483,27 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
                 // publish the strip's last column for rows ch*64-63+lane
                 const int orow = ch * 64 - 63 + lane;
                 const int2 ov = outb[lane];
-                if (wid == W - 1) bnd_g[kBndLo + orow] = ov;
-                else xr_out[(orow + 192) % 192] = ov;
+                if (wid == Weff - 1) {
+                    bnd_g[kBndLo + orow] = ov;
+                } else if (has_next) {
+                    // the ring slots hold rows of the consumer's chunks ch-4 and
+                    // ch-3 (or of the previous pass): wait until they are copied
+                    const int need = base + (ch - 2 > 0 ? ch - 2 : 0);
+                    if (!wait_at_least(&cons[wid + 1], need, dead)) {
+                        failed = true;
+                        break;
+                    }
+                    xr_out[(orow + 192) % 192] = ov;
+                }
+                if (lane == 0)
+                    __hip_atomic_store(&prog[wid], base + ch + 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            if (W > 1) __syncthreads();
-        }  // epochs
+        }  // chunks
+        if (failed) break;
 
         // ---- strip epilogue: best cell of the strip
-        if (act) {
+        {
             if (MODE == MPG_GLOBAL) {
 #pragma unroll
                 for (int c = 0; c < K; ++c)
@@ -456,7 +524,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
                 best_key = key > best_key ? key : best_key;
             }
         }
-        __syncthreads();
     }  // passes
 
     if (lane == 0) red[wid] = best_key;
@@ -468,7 +535,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
         R.ops_off = J.ops_off;
         R.ops_len = 0;
         R._pad = 0;
-        if (MODE == MPG_GLOBAL) {
+        if (*dead) {
+            R.status = MPG_E_DEVICE;
+            R.score = 0;
+            R.g_end = -1;
+            R.p_end = -1;
+        } else if (MODE == MPG_GLOBAL) {
             const int v = *gsc;
             if (v < UNREACH) {
                 R.status = MPG_E_NOALN;

@@ -254,7 +254,7 @@ int dp_lds_bytes(int K, int W, bool tb) {
     if (K == 1) wave = tb ? LdsLayout<1, true>::WAVE : LdsLayout<1, false>::WAVE;
     else if (K == 2) wave = tb ? LdsLayout<2, true>::WAVE : LdsLayout<2, false>::WAVE;
     else wave = tb ? LdsLayout<4, true>::WAVE : LdsLayout<4, false>::WAVE;
-    return wave * W + 16 * 8 + 16;
+    return wave * W + 512;  // + reduction slots and progress flags
 }
 
 hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row_start, int npairs,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -139,15 +140,43 @@ struct HostBuf {  // pinned host staging
     }
 };
 
-// Everything one in-flight batch needs on the device.
+// Everything one in-flight batch needs on the device.  The DP launches of a
+// batch (one per kernel variant) run concurrently on side streams forked
+// from the batch stream and joined back with events.
+constexpr int kSideStreams = 8;
 struct Workspace {
     DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops;
     HostBuf hplan, hseq, hout, hops;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kSideStreams] = {};
+    bool streams_ready = false;
+    int ensure_streams() {
+        if (streams_ready) return MPG_OK;
+        for (int k = 0; k < kSideStreams; ++k) {
+            if (hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking) != hipSuccess)
+                return MPG_E_DEVICE;
+            if (hipEventCreateWithFlags(&join_ev[k], hipEventDisableTiming) != hipSuccess)
+                return MPG_E_DEVICE;
+        }
+        if (hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming) != hipSuccess)
+            return MPG_E_DEVICE;
+        streams_ready = true;
+        return MPG_OK;
+    }
     void release() {
         DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops};
         for (auto* b : d) b->release();
         HostBuf* h[] = {&hplan, &hseq, &hout, &hops};
         for (auto* b : h) b->release();
+        if (streams_ready) {
+            for (int k = 0; k < kSideStreams; ++k) {
+                hipStreamSynchronize(side[k]);
+                hipStreamDestroy(side[k]);
+                hipEventDestroy(join_ev[k]);
+            }
+            hipEventDestroy(fork_ev);
+            streams_ready = false;
+        }
     }
 };
 
@@ -183,12 +212,24 @@ int choose_K(int m) {
     return 2;
 }
 
-int choose_W(int K, int nstrips, int n, bool tb) {
-    int W;
+// Waves per pair.  A pair runs its strips W at a time; W is raised until the
+// pair's sequential work (strip passes x steps) is no more than a balanced
+// share of the whole launch, so the largest pairs do not set the makespan.
+// W is then evened out so the last pass has no idle waves.
+int g_wave_slots = 2048;  // concurrent DP wavefronts the device holds (CUs x 4 SIMDs x 2)
+
+int choose_W(int K, int nstrips, int nchunks, bool tb, double slot_steps) {
+    // Pairs whose sequential work exceeds a balanced slot share run in the
+    // multi-wavefront kernel: up to 8 waves per workgroup, each pair using
+    // as many as evenly divide its strips (the rest stay idle).
+    int W = 1;
     const int f = env_int("MPG_FORCE_W");
-    if (f >= 1) W = std::min(f, 8);
-    else if (nstrips <= 2 || (int64_t)n * nstrips < 4000000) W = 1;
-    else W = std::min(8, nstrips / 2);
+    if (f >= 1) {
+        W = std::min(f, 8);
+    } else {
+        const double steps = (double)nstrips * nchunks * 64.0;
+        if (nstrips > 1 && slot_steps > 0 && steps > slot_steps) W = 8;
+    }
     while (W > 1 && dp_lds_bytes(K, W, tb) > g_max_lds) --W;
     return std::max(W, 1);
 }
@@ -283,9 +324,17 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
               [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
                   return a.first > b.first || (a.first == b.first && a.second < b.second);
               });
+    double total_steps = 0;
     for (auto& e : bysize) {
         const PairJob& J = P.jobs[e.second];
-        const int W = choose_W(J.K, J.nstrips, J.n, J.tb != 0);
+        total_steps += (double)J.nstrips * J.nchunks * 64.0;
+    }
+    const int wf = env_int("MPG_W_FACTOR");  // debug: threshold in % of a slot's share
+    const double slot_steps =
+        total_steps / std::max(1, g_wave_slots) * (wf > 0 ? wf / 100.0 : 1.0);
+    for (auto& e : bysize) {
+        const PairJob& J = P.jobs[e.second];
+        const int W = choose_W(J.K, J.nstrips, J.nchunks, J.tb != 0, slot_steps);
         Group* g = nullptr;
         for (auto& gg : P.groups)
             if (gg.K == J.K && gg.W == W && gg.tb == (J.tb != 0)) g = &gg;
@@ -296,6 +345,8 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         g->order.push_back(e.second);
         if (J.tb) P.walk.push_back(e.second);
     }
+    std::stable_sort(P.groups.begin(), P.groups.end(),
+                     [](const Group& a, const Group& b) { return a.W > b.W; });
 }
 
 }  // namespace
@@ -444,12 +495,31 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
         return MPG_E_DEVICE;
     if (tm) tm->end(st, 0);
     if (tm) tm->begin(st, 1);
-    for (size_t g = 0; g < P.groups.size(); ++g) {
-        const Group& G = P.groups[g];
-        e = launch_dp(st, G.K, G.W, G.tb, DP, d_jobs, d_order + goff[g], (int)G.order.size(),
+    if (P.groups.size() == 1) {
+        const Group& G = P.groups[0];
+        e = launch_dp(st, G.K, G.W, G.tb, DP, d_jobs, d_order + goff[0], (int)G.order.size(),
                       d_prot, (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, (uint8_t*)ws.tb.p,
                       d_out);
         if (e != hipSuccess) return MPG_E_DEVICE;
+    } else if (!P.groups.empty()) {
+        // fork: every variant's launch starts after the prepass, concurrently
+        if ((rc = ws.ensure_streams()) != MPG_OK) return rc;
+        if (hipEventRecord(ws.fork_ev, st) != hipSuccess) return MPG_E_DEVICE;
+        const int ng = (int)std::min<size_t>(P.groups.size(), kSideStreams);
+        for (int k = 0; k < ng; ++k)
+            if (hipStreamWaitEvent(ws.side[k], ws.fork_ev, 0) != hipSuccess) return MPG_E_DEVICE;
+        for (size_t g = 0; g < P.groups.size(); ++g) {
+            const Group& G = P.groups[g];
+            e = launch_dp(ws.side[g % kSideStreams], G.K, G.W, G.tb, DP, d_jobs,
+                          d_order + goff[g], (int)G.order.size(), d_prot,
+                          (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, d_out);
+            if (e != hipSuccess) return MPG_E_DEVICE;
+        }
+        // join
+        for (int k = 0; k < ng; ++k) {
+            if (hipEventRecord(ws.join_ev[k], ws.side[k]) != hipSuccess) return MPG_E_DEVICE;
+            if (hipStreamWaitEvent(st, ws.join_ev[k], 0) != hipSuccess) return MPG_E_DEVICE;
+        }
     }
     if (tm) tm->end(st, 1);
     if (!P.walk.empty()) {
@@ -581,6 +651,10 @@ int mpg_ctx_create(mpg_ctx** out, int device, uint64_t tb_budget_bytes, uint32_t
             hipSuccess &&
         lds > 0)
         g_max_lds = std::min(lds, 65536);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        ncu > 0)
+        g_wave_slots = ncu * 4 * 2;
     mpg_ctx* c = new (std::nothrow) mpg_ctx();
     if (!c) return MPG_E_NOMEM;
     c->device = device;
