@@ -102,7 +102,19 @@ def main():
     ap.add_argument("--config", default="batch")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibrate:
+        import torch
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 3 x 1 GiB")
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: pairs are independent and this build "
               "measures one GPU's share (see the design notes for the sharded layout).",
@@ -161,8 +173,10 @@ def main():
     peak = PEAK_INT_OPS / 1e12
     kernel_gcups = cells / (dp_ms * 1e-3) / 1e9
     log("step %.3f ms, GCUPS %.1f; DP kernels %.3f ms/step (%.1f GCUPS), prepass %.3f ms, "
-        "walk %.3f ms" % (ms_step, gcups, dp_ms, kernel_gcups,
-                          tim["prepass_ms"] / args.steps, tim["walk_ms"] / args.steps))
+        "walk %.3f ms, host %.3f ms" % (ms_step, gcups, dp_ms, kernel_gcups,
+                                        tim["prepass_ms"] / args.steps,
+                                        tim["walk_ms"] / args.steps,
+                                        tim["host_ms"] / args.steps))
 
     cpu = None
     if args.cpu_budget > 0:

@@ -234,6 +234,7 @@ typedef struct {
     double prepass_ms, dp_ms, walk_ms;
     uint64_t dp_spans; /* number of timed DP spans (one per batch wave) */
     uint64_t calls;    /* batch calls since the last reset */
+    double host_ms;    /* host wall time planning and enqueuing the device work */
 } mpg_timing;
 
 /* Turn event timing of batch calls on (1) or off (0). */

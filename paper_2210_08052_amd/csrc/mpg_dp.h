@@ -88,8 +88,7 @@ struct LdsLayout {
     static constexpr int PROF = 25 * SW * PS;  // profile: 24 aa + poison row
     static constexpr int IN = 64 * 8;          // incoming boundary of the chunk
     static constexpr int OUT = 64 * 8;         // outgoing boundary of the chunk
-    static constexpr int XR = 192 * 8;         // hand-off ring to the next wave
-    static constexpr int WAVE = RING + PROF + IN + OUT + XR;
+    static constexpr int WAVE = RING + PROF + IN + OUT;
 };
 
 // Sentinels per layout.  LOCAL keeps -infinity small enough that a shifted
@@ -117,45 +116,71 @@ __device__ __forceinline__ bool wait_at_least(int* flag, int target, int* dead) 
 extern "C" __device__ int mpg_writelane_i32(int val, int lane, int old) __asm(
     "llvm.amdgcn.writelane.i32");
 
+// Per-pair state shared by the waves that work on the pair's strips.
+struct PairState {
+    unsigned long long key;  // best end-cell key over the finished strips
+    int done;                // strips finished
+    int gsc;                 // GLOBAL: H(n, m)
+    int bad;                 // a bounded wait gave up
+    int pad;
+};
+
+// Device-scope relaxed atomics: coherent across every CU and XCD without
+// cache-wide fences (loads and stores carry the device-scope cache bits).
+__device__ __forceinline__ int ld_dev(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int2 ld_dev2(const int2* p) {
+    const unsigned long long v = __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    return make_int2((int)(uint32_t)v, (int)(uint32_t)(v >> 32));
+}
+__device__ __forceinline__ void st_dev2(int2* p, int2 v) {
+    const unsigned long long u = (unsigned long long)(uint32_t)v.x |
+                                 ((unsigned long long)(uint32_t)v.y << 32);
+    __hip_atomic_store((unsigned long long*)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait until the left strip has published `target` chunks.  Gives up
+// after about 2^18 polls (well under a second) so no wave can spin forever;
+// the pair then reports MPG_E_DEVICE.
+// The polled value goes through readfirstlane: the loop exit is then uniform
+// for the compiler too, so the wave never runs it in divergent form.
+__device__ __forceinline__ bool wait_prog(const int* flag, int target) {
+    for (int it = 0; it < (1 << 18); ++it) {
+        if (__builtin_amdgcn_readfirstlane(ld_dev(flag)) >= target) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
+
+// The DP kernel.  Persistent single-wavefront workgroups take (pair, strip)
+// work items from one queue ordered longest pair first, strips in order.  A
+// strip streams its left boundary (H and I of the previous strip's last
+// column) from HBM as the previous strip publishes it chunk by chunk, so the
+// strips of a long pair run as a pipeline spread over many CUs, and every
+// wavefront slot stays busy until the queue is empty.  Dependencies only point
+// to items taken earlier by running wavefronts, so the waits always end.
 template <int K, int MODE, bool TB, bool NOI, bool NOF>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP_WAVES_PER_EU))) dp_kernel(const PairJob* __restrict__ jobs,
-                                                 const int32_t* __restrict__ order,
-                                                 const uint8_t* __restrict__ prot,
-                                                 const uint8_t* __restrict__ desc,
-                                                 int2* __restrict__ bnd,
-                                                 uint8_t* __restrict__ tbbuf,
-                                                 mpg_dev_result* __restrict__ out, DevParams P) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MPG_DP_WAVES_PER_EU)))
+dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int nitems,
+          int* __restrict__ qhead, PairState* __restrict__ pst, int* __restrict__ prog_g,
+          const uint8_t* __restrict__ prot, const uint8_t* __restrict__ desc,
+          int2* __restrict__ bnd, uint8_t* __restrict__ tbbuf,
+          mpg_dev_result* __restrict__ out, DevParams P) {
     using LY = LdsLayout<K, TB>;
     constexpr int NEG = Sentinel<MODE, TB>::NEG;
     constexpr int UNREACH = Sentinel<MODE, TB>::UNREACH;
     constexpr int ZN = TB ? 15 : 0;  // nibble of the start candidate
     extern __shared__ __align__(16) uint8_t smem[];
     const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int W = blockDim.x >> 6;
-    const PairJob J = jobs[order[blockIdx.x]];
-    if (J.status != MPG_OK) return;  // uniform for the whole workgroup
-
-    uint8_t* my = smem + wid * LY::WAVE;
-    uint8_t* ring = my;
-    uint8_t* prof = my + LY::RING;
-    int2* inb = (int2*)(my + LY::RING + LY::PROF);
-    int2* outb = (int2*)(my + LY::RING + LY::PROF + LY::IN);
-    int2* xr_out = (int2*)(my + LY::RING + LY::PROF + LY::IN + LY::OUT);
-    const int2* xr_in = (const int2*)(smem + (wid > 0 ? wid - 1 : 0) * LY::WAVE + LY::RING +
-                                      LY::PROF + LY::IN + LY::OUT);
-    uint64_t* red = (uint64_t*)(smem + W * LY::WAVE);
-    int* gsc = (int*)(red + 16);
-    int* prog = gsc + 4;   // chunks whose last column wave w has published (all passes)
-    int* cons = prog + 16; // chunks whose input wave w has copied out of the ring
-    int* dead = cons + 16; // set when a bounded wait gave up
-
-    const int n = J.n, m = J.m;
-    const int nchunks = J.nchunks, nstrips = J.nstrips;
-    const uint8_t* dsc_g = desc + J.desc_off;  // row r at (r + kDescLo) * DS
-    int2* bnd_g = bnd + J.bnd_off;             // row r at r + kBndLo
-    const uint8_t* Pa = prot + J.prot_off;
-    uint8_t* tbp = tbbuf + J.tb_off;
+    uint8_t* ring = smem;
+    uint8_t* prof = smem + LY::RING;
+    int2* inb = (int2*)(smem + LY::RING + LY::PROF);
+    int2* outb = (int2*)(smem + LY::RING + LY::PROF + LY::IN);
 
     // penalties in the layout of this variant
     const int cq = TB ? 16 * (P.q + P.e) - 13 : P.q;   // I open  (TB: nibble 13)
@@ -163,29 +188,30 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
     const int ce = TB ? 16 * P.e : P.e;
     const int cf = TB ? 16 * P.f : P.f;
 
-    uint64_t best_key = 0;
-    if (threadIdx.x < 16) {
-        prog[threadIdx.x] = 0;
-        cons[threadIdx.x] = 0;
-    }
-    if (threadIdx.x == 0) {
-        *gsc = NEG;
-        *dead = 0;
-    }
-    __syncthreads();
-
-    // W_eff waves take the strips W_eff at a time; surplus waves stay idle
-    int Weff = W < nstrips ? W : nstrips;
-    const int npasses = (nstrips + Weff - 1) / Weff;
-    Weff = (nstrips + npasses - 1) / npasses;
-    bool failed = false;
-    for (int pass = 0; pass < npasses && !failed; ++pass) {
-        const int strip = pass * Weff + wid;
-        const bool act = wid < Weff && strip < nstrips;
-        if (!act) break;
-        const int base = pass * nchunks;  // chunk counters run across passes
+    for (;;) {
+        // take the next item without a divergent branch: lane 0 adds 1, the
+        // other lanes add 0, so lane 0 always receives the old head; its value
+        // through readfirstlane is wave-uniform, which keeps the loop exit
+        // uniform, so no cross-lane operation below ever runs with part of
+        // the wave masked off
+        const int it = __builtin_amdgcn_readfirstlane(atomicAdd(qhead, lane == 0 ? 1 : 0));
+        if (it >= nitems) break;
+        const int2 item = items[it];
+        const PairJob J = jobs[item.x];
+        const int strip = item.y;
+        const int n = J.n, m = J.m;
+        const int nchunks = J.nchunks, nstrips = J.nstrips;
+        const uint8_t* dsc_g = desc + J.desc_off;  // row r at (r + kDescLo) * DS
+        int2* bnd_g = bnd + J.bnd_off;             // row r at r + kBndLo
+        const uint8_t* Pa = prot + J.prot_off;
+        uint8_t* tbp = tbbuf + J.tb_off;
+        int* prog = prog_g + J.prog_off;           // chunks published, per strip
+        PairState* ps = pst + item.x;
         const bool has_next = strip + 1 < nstrips;
         const int col0 = strip * LY::SW + lane * K;  // DP column of this lane's first column
+        const bool act = true;
+        bool failed = false;
+        uint64_t best_key = 0;
 
         // ---- strip set-up: profile, registers, first descriptors and boundary
         if (act) {
@@ -245,46 +271,28 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
             if (TB) *(int4*)(ring + (64 + lane) * LY::DS + 16) = *(const int4*)(src2 + 16);
         }
         int2 nb = make_int2(NEG, NEG);
-        // wave 0 of a later pass reads the last column of the previous pass's
-        // last strip from HBM, published by wave Weff-1 chunk by chunk
-        const bool from_global = strip > 0 && wid == 0;
-        const int gprev = base - nchunks;
-        if (from_global) {
-            if (!wait_at_least(&prog[Weff - 1], gprev + (nchunks < 2 ? nchunks : 2), dead)) {
-                failed = true;
-                break;
-            }
-            nb = bnd_g[kBndLo + lane];
+        // the left strip's last column arrives from HBM as that strip
+        // publishes it; rows of chunk c need its chunks c and c+1
+        const bool from_left = strip > 0;
+        if (from_left) {
+            if (!wait_prog(&prog[strip - 1], nchunks < 2 ? nchunks : 2)) failed = true;
+            nb = ld_dev2(&bnd_g[kBndLo + lane]);
         }
 
-        for (int ch = 0; ch < nchunks; ++ch) {
+        for (int ch = 0; ch < nchunks && !failed; ++ch) {
             {
-                // incoming boundary rows ch*64 .. ch*64+63 of the left strip
-                // (rows beyond n were never written by the left strip's last
-                // lane, or hold garbage-row values: they enter as -infinity)
+                // incoming boundary rows ch*64 .. ch*64+63 (rows beyond n hold
+                // garbage-row values or were never written: -infinity)
                 const bool beyond = ch * 64 + lane > n;
-                if (from_global) {
+                if (from_left) {
                     inb[lane] = beyond ? make_int2(NEG, NEG) : nb;
                     if (ch + 1 < nchunks) {
-                        const int need = gprev + (ch + 3 < nchunks ? ch + 3 : nchunks);
-                        if (!wait_at_least(&prog[Weff - 1], need, dead)) {
+                        if (!wait_prog(&prog[strip - 1], ch + 3 < nchunks ? ch + 3 : nchunks)) {
                             failed = true;
                             break;
                         }
-                        nb = bnd_g[kBndLo + (ch + 1) * 64 + lane];
+                        nb = ld_dev2(&bnd_g[kBndLo + (ch + 1) * 64 + lane]);
                     }
-                } else if (wid > 0) {
-                    const int need = base + (ch + 2 < nchunks ? ch + 2 : nchunks);
-                    if (!wait_at_least(&prog[wid - 1], need, dead)) {
-                        failed = true;
-                        break;
-                    }
-                    const int2 v = xr_in[(ch * 64 + lane) % 192];
-                    inb[lane] = beyond ? make_int2(NEG, NEG) : v;
-                    // the ring rows of this chunk are no longer needed
-                    if (lane == 0)
-                        __hip_atomic_store(&cons[wid], base + ch + 1, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
                 if (ch > 0) {
                     // slide the descriptor ring: current chunk -> previous half
@@ -481,33 +489,28 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
                     }
                 }
                 // publish the strip's last column for rows ch*64-63+lane
-                const int orow = ch * 64 - 63 + lane;
-                const int2 ov = outb[lane];
-                if (wid == Weff - 1) {
-                    bnd_g[kBndLo + orow] = ov;
-                } else if (has_next) {
-                    // the ring slots hold rows of the consumer's chunks ch-4 and
-                    // ch-3 (or of the previous pass): wait until they are copied
-                    const int need = base + (ch - 2 > 0 ? ch - 2 : 0);
-                    if (!wait_at_least(&cons[wid + 1], need, dead)) {
-                        failed = true;
-                        break;
-                    }
-                    xr_out[(orow + 192) % 192] = ov;
+                if (has_next) {
+                    const int orow = ch * 64 - 63 + lane;
+                    st_dev2(&bnd_g[kBndLo + orow], outb[lane]);
+                    __builtin_amdgcn_s_waitcnt(0);  // rows reach the coherence point first
+                    if (lane == 0) st_dev(&prog[strip], ch + 1);
                 }
-                if (lane == 0)
-                    __hip_atomic_store(&prog[wid], base + ch + 1, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }  // chunks
-        if (failed) break;
+        if (failed) {
+            // let the strips to the right drain quickly; the pair reports an error
+            if (lane == 0) {
+                st_dev(&prog[strip], nchunks);
+                atomicMax(&ps->bad, 1);
+            }
+        }
 
-        // ---- strip epilogue: best cell of the strip
-        {
+        // ---- strip epilogue: best cell of the strip, folded into the pair
+        if (!failed) {
             if (MODE == MPG_GLOBAL) {
 #pragma unroll
                 for (int c = 0; c < K; ++c)
-                    if (col0 + c == m) *gsc = hn[c];
+                    if (col0 + c == m) st_dev(&ps->gsc, hn[c]);
             } else {
                 uint64_t key = 0;
 #pragma unroll
@@ -522,87 +525,87 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MPG_DP
                 }
                 key = wave_max_u64(key);
                 best_key = key > best_key ? key : best_key;
+                if (lane == 0 && best_key) atomicMax(&ps->key, (unsigned long long)best_key);
             }
         }
-    }  // passes
-
-    if (lane == 0) red[wid] = best_key;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        mpg_dev_result R;
-        R.g_beg = -1;
-        R.p_beg = -1;
-        R.ops_off = J.ops_off;
-        R.ops_len = 0;
-        R._pad = 0;
-        if (*dead) {
-            R.status = MPG_E_DEVICE;
-            R.score = 0;
-            R.g_end = -1;
-            R.p_end = -1;
-        } else if (MODE == MPG_GLOBAL) {
-            const int v = *gsc;
-            if (v < UNREACH) {
-                R.status = MPG_E_NOALN;
-                R.score = 0;
-                R.g_end = -1;
-                R.p_end = -1;
-            } else {
-                R.status = MPG_OK;
-                R.score = TB ? (v >> 4) : v;
-                R.g_end = n;
-                R.p_end = m;
+        __builtin_amdgcn_s_waitcnt(0);
+        // the wave that finishes the pair's last strip writes the result
+        if (lane == 0) {
+            const int done = atomicAdd(&ps->done, 1);
+            if (done == nstrips - 1) {
+                mpg_dev_result R;
+                R.g_beg = -1;
+                R.p_beg = -1;
+                R.ops_off = J.ops_off;
+                R.ops_len = 0;
+                R._pad = 0;
+                const int gv = atomicAdd(&ps->gsc, 0);
+                const unsigned long long k = atomicAdd(&ps->key, 0ull);
+                if (atomicAdd(&ps->bad, 0)) {
+                    R.status = MPG_E_DEVICE;
+                    R.score = 0;
+                    R.g_end = -1;
+                    R.p_end = -1;
+                } else if (MODE == MPG_GLOBAL) {
+                    if (gv < UNREACH) {
+                        R.status = MPG_E_NOALN;
+                        R.score = 0;
+                        R.g_end = -1;
+                        R.p_end = -1;
+                    } else {
+                        R.status = MPG_OK;
+                        R.score = TB ? (gv >> 4) : gv;
+                        R.g_end = n;
+                        R.p_end = m;
+                    }
+                } else {
+                    R.status = MPG_OK;
+                    R.score = (int)(k >> 36) - (1 << 27);
+                    R.g_end = (1 << 21) - 1 - (int)((k >> 15) & ((1u << 21) - 1));
+                    R.p_end = (1 << 15) - 1 - (int)(k & ((1u << 15) - 1));
+                }
+                out[J.res] = R;
             }
-        } else {
-            uint64_t k = 0;
-            for (int w = 0; w < W; ++w) k = red[w] > k ? red[w] : k;
-            R.status = MPG_OK;
-            R.score = (int)(k >> 36) - (1 << 27);
-            R.g_end = (1 << 21) - 1 - (int)((k >> 15) & ((1u << 21) - 1));
-            R.p_end = (1 << 15) - 1 - (int)(k & ((1u << 15) - 1));
         }
-        out[J.res] = R;
-    }
+    }  // queue
 }
 
 template <int K, int MODE, bool TB>
-hipError_t launch_dp_t(hipStream_t s, int W, const DevParams& P, const PairJob* jobs,
-                       const int32_t* order, int count, const uint8_t* prot, const uint8_t* desc,
-                       int2* bnd, uint8_t* tbbuf, mpg_dev_result* out) {
+hipError_t launch_dp_t(hipStream_t s, int grid, const DevParams& P, const PairJob* jobs,
+                       const int2* items, int nitems, int* qhead, PairState* pst, int* prog,
+                       const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
+                       mpg_dev_result* out) {
     const bool noi = (P.flags & MPG_NO_INTRON) != 0;
     const bool nof = (P.flags & MPG_NO_FRAMESHIFT) != 0;
-    const size_t lds = (size_t)dp_lds_bytes(K, W, TB);
-    dim3 grid(count), block(64 * W);
-    if (!noi && !nof)
-        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, false, false>), grid, block, lds, s, jobs, order,
-                           prot, desc, bnd, tbbuf, out, P);
-    else if (noi && !nof)
-        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, true, false>), grid, block, lds, s, jobs, order,
-                           prot, desc, bnd, tbbuf, out, P);
-    else if (!noi && nof)
-        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, false, true>), grid, block, lds, s, jobs, order,
-                           prot, desc, bnd, tbbuf, out, P);
-    else
-        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, true, true>), grid, block, lds, s, jobs, order,
-                           prot, desc, bnd, tbbuf, out, P);
+    const size_t lds = (size_t)LdsLayout<K, TB>::WAVE;
+    dim3 g(grid), b(64);
+#define MPG_LAUNCH(NI, NF)                                                                      \
+    hipLaunchKernelGGL((dp_kernel<K, MODE, TB, NI, NF>), g, b, lds, s, jobs, items, nitems,    \
+                       qhead, pst, prog, prot, desc, bnd, tbbuf, out, P)
+    if (!noi && !nof) MPG_LAUNCH(false, false);
+    else if (noi && !nof) MPG_LAUNCH(true, false);
+    else if (!noi && nof) MPG_LAUNCH(false, true);
+    else MPG_LAUNCH(true, true);
+#undef MPG_LAUNCH
     return hipGetLastError();
 }
 
 template <int K>
-hipError_t launch_dp_k(hipStream_t s, int W, bool tb, const DevParams& P, const PairJob* jobs,
-                       const int32_t* order, int count, const uint8_t* prot, const uint8_t* desc,
-                       int2* bnd, uint8_t* tbbuf, mpg_dev_result* out) {
+hipError_t launch_dp_k(hipStream_t s, int grid, bool tb, const DevParams& P, const PairJob* jobs,
+                       const int2* items, int nitems, int* qhead, PairState* pst, int* prog,
+                       const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
+                       mpg_dev_result* out) {
+#define MPG_MODE(M)                                                                             \
+    return tb ? launch_dp_t<K, M, true>(s, grid, P, jobs, items, nitems, qhead, pst, prog, prot, \
+                                        desc, bnd, tbbuf, out)                                  \
+              : launch_dp_t<K, M, false>(s, grid, P, jobs, items, nitems, qhead, pst, prog,     \
+                                         prot, desc, bnd, tbbuf, out)
     switch (P.mode) {
-        case MPG_LOCAL:
-            return tb ? launch_dp_t<K, MPG_LOCAL, true>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out)
-                      : launch_dp_t<K, MPG_LOCAL, false>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
-        case MPG_EXTEND:
-            return tb ? launch_dp_t<K, MPG_EXTEND, true>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out)
-                      : launch_dp_t<K, MPG_EXTEND, false>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
-        default:
-            return tb ? launch_dp_t<K, MPG_GLOBAL, true>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out)
-                      : launch_dp_t<K, MPG_GLOBAL, false>(s, W, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
+        case MPG_LOCAL: MPG_MODE(MPG_LOCAL);
+        case MPG_EXTEND: MPG_MODE(MPG_EXTEND);
+        default: MPG_MODE(MPG_GLOBAL);
     }
+#undef MPG_MODE
 }
 
 }  // namespace dev

@@ -51,26 +51,37 @@ struct PairJob {
     int32_t nstrips;     // strips of 64*K columns covering columns 0..m
     int32_t K;           // columns per lane
     int32_t status;      // host pre-check status (MPG_OK or MPG_E_RANGE)
+    int32_t prog_off;    // index of strip 0's progress counter
+    int32_t _pad;
 };
+
+// Bytes of per-pair shared state of the DP launch (end-cell key, counters).
+constexpr int kPairStateBytes = 24;
 
 // Kernel launch helpers implemented in mpg_kernels.hip.
 hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row_start,
                           int npairs, int64_t total_rows, const uint8_t* dna, uint8_t* desc,
                           const DevParams& P);
 
-// One DP launch over `count` pairs (indices into jobs via order[]) that share
-// (K, W, traceback); all pairs of a call share mode and flags.
-hipError_t launch_dp(hipStream_t s, int K, int W, bool tb, const DevParams& P,
-                     const PairJob* jobs, const int32_t* order, int count,
-                     const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
-                     mpg_dev_result* out);
+// One DP launch of `grid` persistent wavefronts over the work items
+// (job index, strip) of pairs that share K and traceback; all pairs of a
+// call share mode and flags.  qhead must be zero, pst and prog zeroed by
+// launch_init.
+hipError_t launch_dp(hipStream_t s, int K, bool tb, int grid, const DevParams& P,
+                     const PairJob* jobs, const int2* items, int nitems, int* qhead, void* pst,
+                     int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
+                     uint8_t* tbbuf, mpg_dev_result* out);
+
+// Zero the per-pair state, the strips' progress counters and the queue heads.
+hipError_t launch_init(hipStream_t s, const PairJob* jobs, int npairs, void* pst, int* prog,
+                       int* qheads, int nq, int gsc_init);
 
 hipError_t launch_walk(hipStream_t s, const PairJob* jobs, const int32_t* order, int count,
                        const uint8_t* tbbuf, mpg_dev_result* out, char* ops);
 
 hipError_t launch_status(hipStream_t s, const PairJob* jobs, int npairs, mpg_dev_result* out);
 
-// Dynamic LDS bytes one DP workgroup of W waves needs.
-int dp_lds_bytes(int K, int W, bool tb);
+// Dynamic LDS bytes of one DP wavefront.
+int dp_lds_bytes(int K, bool tb);
 
 }  // namespace mpg

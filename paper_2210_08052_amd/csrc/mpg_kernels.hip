@@ -87,6 +87,22 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
     }
 }
 
+// ------------------------------------------------------------------- init
+__global__ void init_kernel(const PairJob* __restrict__ jobs, int npairs, PairState* __restrict__ pst,
+                            int* __restrict__ prog, int* __restrict__ qheads, int nq, int gsc_init) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nq) qheads[k] = 0;
+    if (k >= npairs) return;
+    const PairJob& J = jobs[k];
+    pst[k].key = 0;
+    pst[k].done = 0;
+    pst[k].gsc = gsc_init;
+    pst[k].bad = 0;
+    pst[k].pad = 0;
+    if (J.status != MPG_OK) return;
+    for (int s = 0; s < J.nstrips; ++s) prog[J.prog_off + s] = 0;
+}
+
 // ------------------------------------------------------------------- walk
 
 struct TbView {
@@ -242,19 +258,20 @@ __global__ void status_kernel(const PairJob* __restrict__ jobs, int npairs,
 
 }  // namespace dev
 
-hipError_t launch_dp_k1(hipStream_t, int, bool, const DevParams&, const PairJob*, const int32_t*,
-                        int, const uint8_t*, const uint8_t*, int2*, uint8_t*, mpg_dev_result*);
-hipError_t launch_dp_k2(hipStream_t, int, bool, const DevParams&, const PairJob*, const int32_t*,
-                        int, const uint8_t*, const uint8_t*, int2*, uint8_t*, mpg_dev_result*);
-hipError_t launch_dp_k4(hipStream_t, int, bool, const DevParams&, const PairJob*, const int32_t*,
-                        int, const uint8_t*, const uint8_t*, int2*, uint8_t*, mpg_dev_result*);
+hipError_t launch_dp_k1(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
+                        int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
+                        mpg_dev_result*);
+hipError_t launch_dp_k2(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
+                        int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
+                        mpg_dev_result*);
+hipError_t launch_dp_k4(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
+                        int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
+                        mpg_dev_result*);
 
-int dp_lds_bytes(int K, int W, bool tb) {
-    int wave;
-    if (K == 1) wave = tb ? LdsLayout<1, true>::WAVE : LdsLayout<1, false>::WAVE;
-    else if (K == 2) wave = tb ? LdsLayout<2, true>::WAVE : LdsLayout<2, false>::WAVE;
-    else wave = tb ? LdsLayout<4, true>::WAVE : LdsLayout<4, false>::WAVE;
-    return wave * W + 512;  // + reduction slots and progress flags
+int dp_lds_bytes(int K, bool tb) {
+    if (K == 1) return tb ? LdsLayout<1, true>::WAVE : LdsLayout<1, false>::WAVE;
+    if (K == 2) return tb ? LdsLayout<2, true>::WAVE : LdsLayout<2, false>::WAVE;
+    return tb ? LdsLayout<4, true>::WAVE : LdsLayout<4, false>::WAVE;
 }
 
 hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row_start, int npairs,
@@ -266,16 +283,26 @@ hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row
     return hipGetLastError();
 }
 
-hipError_t launch_dp(hipStream_t s, int K, int W, bool tb, const DevParams& P, const PairJob* jobs,
-                     const int32_t* order, int count, const uint8_t* prot, const uint8_t* desc,
-                     int2* bnd, uint8_t* tbbuf, mpg_dev_result* out) {
-    if (count <= 0) return hipSuccess;
+hipError_t launch_dp(hipStream_t s, int K, bool tb, int grid, const DevParams& P,
+                     const PairJob* jobs, const int2* items, int nitems, int* qhead, void* pst,
+                     int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
+                     uint8_t* tbbuf, mpg_dev_result* out) {
+    if (nitems <= 0) return hipSuccess;
     switch (K) {
-        case 1: return launch_dp_k1(s, W, tb, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
-        case 2: return launch_dp_k2(s, W, tb, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
-        case 4: return launch_dp_k4(s, W, tb, P, jobs, order, count, prot, desc, bnd, tbbuf, out);
+        case 1: return launch_dp_k1(s, grid, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
+        case 2: return launch_dp_k2(s, grid, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
+        case 4: return launch_dp_k4(s, grid, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_init(hipStream_t s, const PairJob* jobs, int npairs, void* pst, int* prog,
+                       int* qheads, int nq, int gsc_init) {
+    if (npairs <= 0 && nq <= 0) return hipSuccess;
+    const int n = npairs > nq ? npairs : nq;
+    hipLaunchKernelGGL(init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, jobs, npairs,
+                       (PairState*)pst, prog, qheads, nq, gsc_init);
+    return hipGetLastError();
 }
 
 hipError_t launch_walk(hipStream_t s, const PairJob* jobs, const int32_t* order, int count,

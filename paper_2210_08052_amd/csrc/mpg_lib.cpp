@@ -145,7 +145,7 @@ struct HostBuf {  // pinned host staging
 // from the batch stream and joined back with events.
 constexpr int kSideStreams = 8;
 struct Workspace {
-    DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops;
+    DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops, state;
     HostBuf hplan, hseq, hout, hops;
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork_ev = nullptr, join_ev[kSideStreams] = {};
@@ -164,7 +164,7 @@ struct Workspace {
         return MPG_OK;
     }
     void release() {
-        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops};
+        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state};
         for (auto* b : d) b->release();
         HostBuf* h[] = {&hplan, &hseq, &hout, &hops};
         for (auto* b : h) b->release();
@@ -181,10 +181,12 @@ struct Workspace {
 };
 
 // ------------------------------------------------------------------ planning
+// One DP launch: the strips of every pair sharing (K, traceback), as a
+// queue of (job, strip) items, longest pair first, strips in order.
 struct Group {
-    int K, W;
+    int K;
     bool tb;
-    std::vector<int32_t> order;  // pair indices, longest first
+    std::vector<int2> items;
 };
 
 struct Plan {
@@ -194,45 +196,31 @@ struct Plan {
     std::vector<int32_t> walk;
     int64_t desc_bytes = 0, bnd_elems = 0, tb_bytes = 0;
     int64_t total_rows = 0;
+    int64_t nprog = 0;
 };
 
 int g_max_lds = 65536;
 
-// Debug-only overrides (tests use them to reach every kernel variant on
-// small inputs): MPG_FORCE_K = columns per lane, MPG_FORCE_W = waves per pair.
+// Debug-only override (tests use it to reach every kernel variant on small
+// inputs): MPG_FORCE_K = columns per lane.
 int env_int(const char* name) {
     const char* v = std::getenv(name);
     return v ? std::atoi(v) : 0;
 }
 
-int choose_K(int m) {
+// Debug overrides are read once per call (getenv per pair is too slow).
+struct Overrides {
+    int K = 0;
+    Overrides() : K(env_int("MPG_FORCE_K")) {}
+};
+
+int choose_K(int m, const Overrides& ov) {
     (void)m;
-    const int f = env_int("MPG_FORCE_K");
-    if (f == 1 || f == 2 || f == 4) return f;
+    if (ov.K == 1 || ov.K == 2 || ov.K == 4) return ov.K;
     return 2;
 }
 
-// Waves per pair.  A pair runs its strips W at a time; W is raised until the
-// pair's sequential work (strip passes x steps) is no more than a balanced
-// share of the whole launch, so the largest pairs do not set the makespan.
-// W is then evened out so the last pass has no idle waves.
 int g_wave_slots = 2048;  // concurrent DP wavefronts the device holds (CUs x 4 SIMDs x 2)
-
-int choose_W(int K, int nstrips, int nchunks, bool tb, double slot_steps) {
-    // Pairs whose sequential work exceeds a balanced slot share run in the
-    // multi-wavefront kernel: up to 8 waves per workgroup, each pair using
-    // as many as evenly divide its strips (the rest stay idle).
-    int W = 1;
-    const int f = env_int("MPG_FORCE_W");
-    if (f >= 1) {
-        W = std::min(f, 8);
-    } else {
-        const double steps = (double)nstrips * nchunks * 64.0;
-        if (nstrips > 1 && slot_steps > 0 && steps > slot_steps) W = 8;
-    }
-    while (W > 1 && dp_lds_bytes(K, W, tb) > g_max_lds) --W;
-    return std::max(W, 1);
-}
 
 int64_t tb_bytes_of(int n, int m, int K) {
     const int nsteps = ((n + 64 + 63) / 64) * 64;
@@ -240,26 +228,38 @@ int64_t tb_bytes_of(int n, int m, int K) {
     return (int64_t)nstrips * (nsteps / 64) * kTbBlockBytes * K;
 }
 
-// Bound on |value| of reachable cells (see the public header).
-bool score_bound_ok(const mpg_params* p, int64_t n, int64_t m) {
-    int maxpos = 0, minneg = 0;
-    for (int a = 0; a < 24; ++a)
-        for (int b = 0; b < 24; ++b) {
-            maxpos = std::max<int>(maxpos, p->mat[a][b]);
-            minneg = std::min<int>(minneg, p->mat[a][b]);
+// Bound on |value| of reachable cells (see the public header): the largest
+// match score times the protein length, and (EXTEND/GLOBAL) the largest
+// per-unit penalty times the number of units a path can consume.
+struct BoundInfo {
+    int64_t maxpos = 0, pmax = 0;
+    int mode = MPG_LOCAL;
+    explicit BoundInfo(const mpg_params* p) {
+        int mp = 0, mn = 0;
+        for (int a = 0; a < 24; ++a)
+            for (int b = 0; b < 24; ++b) {
+                mp = std::max<int>(mp, p->mat[a][b]);
+                mn = std::min<int>(mn, p->mat[a][b]);
+            }
+        int dmax = 0, amax = 0;
+        for (int k = 0; k < 125; ++k) {
+            dmax = std::max<int>(dmax, p->donor[k]);
+            amax = std::max<int>(amax, p->acceptor[k]);
         }
-    const int64_t lim = (int64_t)1 << 24;
-    if ((int64_t)maxpos * (m + 1) >= lim) return false;
-    int dmax = 0, amax = 0;
-    for (int k = 0; k < 125; ++k) {
-        dmax = std::max<int>(dmax, p->donor[k]);
-        amax = std::max<int>(amax, p->acceptor[k]);
+        maxpos = mp;
+        pmax = std::max<int64_t>({(int64_t)p->q + p->e, (int64_t)p->f,
+                                  (int64_t)p->r + dmax + amax, (int64_t)-mn});
+        mode = p->mode;
     }
-    const int64_t pmax = std::max<int64_t>(
-        {(int64_t)p->q + p->e, (int64_t)p->f, (int64_t)p->r + dmax + amax, (int64_t)-minneg});
-    if (p->mode == MPG_LOCAL) return pmax * 4 < lim;
-    return (n + m + 4) * pmax < lim;
-}
+    bool ok(int64_t n, int64_t m) const {
+        const int64_t lim = (int64_t)1 << 24;
+        if (maxpos * (m + 1) >= lim) return false;
+        if (mode == MPG_LOCAL) return pmax * 4 < lim;
+        return (n + m + 4) * pmax < lim;
+    }
+};
+
+bool score_bound_ok(const mpg_params* p, int64_t n, int64_t m) { return BoundInfo(p).ok(n, m); }
 
 void make_dev_params(const mpg_params* p, DevParams* d) {
     std::memset(d, 0, sizeof(*d));
@@ -286,6 +286,8 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     P.desc_bytes = P.bnd_elems = P.tb_bytes = P.total_rows = 0;
     std::vector<std::pair<int64_t, int32_t>> bysize;
     bysize.reserve(cnt);
+    const Overrides ov;
+    const BoundInfo bound(p);
     for (int32_t k = 0; k < cnt; ++k) {
         const mpg_seg& s = segs[idx[k]];
         PairJob& J = P.jobs[k];
@@ -297,9 +299,9 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         J.prot_off = s.prot_off;
         J.status = MPG_OK;
         if (s.dlen < 0 || s.plen < 0 || s.dlen > MPG_MAX_DNA || s.plen > MPG_MAX_PROT ||
-            !score_bound_ok(p, s.dlen, s.plen))
+            !bound.ok(s.dlen, s.plen))
             J.status = MPG_E_RANGE;
-        const int K = choose_K(std::max(0, s.plen));
+        const int K = choose_K(std::max(0, s.plen), ov);
         J.K = K;
         const int nn = std::max(0, J.n), mm = std::max(0, J.m);
         const int nsteps = ((nn + 64 + 63) / 64) * 64;
@@ -318,35 +320,26 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         P.bnd_elems += (int64_t)nsteps + kBndLo + kBndHi;
         J.tb_off = P.tb_bytes;
         if (J.tb) P.tb_bytes += tb_bytes_of(nn, mm, K);
-        bysize.push_back({(int64_t)(nn + 64) * (mm + 1), k});
+        J.prog_off = (int32_t)P.nprog;
+        P.nprog += J.nstrips;
+        bysize.push_back({(int64_t)J.nstrips * J.nchunks, k});
     }
     std::sort(bysize.begin(), bysize.end(),
               [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
                   return a.first > b.first || (a.first == b.first && a.second < b.second);
               });
-    double total_steps = 0;
     for (auto& e : bysize) {
         const PairJob& J = P.jobs[e.second];
-        total_steps += (double)J.nstrips * J.nchunks * 64.0;
-    }
-    const int wf = env_int("MPG_W_FACTOR");  // debug: threshold in % of a slot's share
-    const double slot_steps =
-        total_steps / std::max(1, g_wave_slots) * (wf > 0 ? wf / 100.0 : 1.0);
-    for (auto& e : bysize) {
-        const PairJob& J = P.jobs[e.second];
-        const int W = choose_W(J.K, J.nstrips, J.nchunks, J.tb != 0, slot_steps);
         Group* g = nullptr;
         for (auto& gg : P.groups)
-            if (gg.K == J.K && gg.W == W && gg.tb == (J.tb != 0)) g = &gg;
+            if (gg.K == J.K && gg.tb == (J.tb != 0)) g = &gg;
         if (!g) {
-            P.groups.push_back(Group{J.K, W, J.tb != 0, {}});
+            P.groups.push_back(Group{J.K, J.tb != 0, {}});
             g = &P.groups.back();
         }
-        g->order.push_back(e.second);
+        for (int st = 0; st < J.nstrips; ++st) g->items.push_back(make_int2(e.second, st));
         if (J.tb) P.walk.push_back(e.second);
     }
-    std::stable_sort(P.groups.begin(), P.groups.end(),
-                     [](const Group& a, const Group& b) { return a.W > b.W; });
 }
 
 }  // namespace
@@ -363,7 +356,7 @@ struct mpg_ctx {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pre, ev_dp, ev_walk;
     std::vector<hipEvent_t> ev_pool;
-    double t_pre = 0, t_dp = 0, t_walk = 0;
+    double t_pre = 0, t_dp = 0, t_walk = 0, t_host = 0;
     uint64_t n_dp = 0, n_calls = 0;
 
     // ---- serving
@@ -402,6 +395,7 @@ int hip_status(hipError_t e) { return e == hipSuccess ? MPG_OK : MPG_E_DEVICE; }
 struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev[3];
     std::vector<hipEvent_t>* pool;
+    double* host_ms;  // wall time spent planning and enqueuing on the host
     hipEvent_t open[3] = {nullptr, nullptr, nullptr};
     hipEvent_t get() {
         hipEvent_t e = nullptr;
@@ -432,6 +426,17 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
             const uint8_t* d_dna, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
             const std::vector<int64_t>& ops_off, mpg_dev_result* d_out, char* d_ops,
             uint64_t tb_budget, Timer* tm) {
+    const auto th0 = std::chrono::steady_clock::now();
+    struct HostClock {
+        Timer* tm;
+        std::chrono::steady_clock::time_point t0;
+        ~HostClock() {
+            if (tm && tm->host_ms)
+                *tm->host_ms += std::chrono::duration<double, std::milli>(
+                                    std::chrono::steady_clock::now() - t0)
+                                    .count();
+        }
+    } host_clock{tm, th0};
     Plan P;
     plan_pairs(p, segs, idx, cnt, ops_off, P, tb_budget);
     DevParams DP;
@@ -446,75 +451,88 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
             pjobs.push_back(P.jobs[k]);
             pstarts.push_back(P.row_start[k]);
         }
-    // launch orders (local job indices), then the walk order
-    std::vector<int32_t> orders;
+    // work items of every launch, then the walk order (local job indices)
+    std::vector<int2> items;
     std::vector<size_t> goff;
     for (auto& g : P.groups) {
-        goff.push_back(orders.size());
-        orders.insert(orders.end(), g.order.begin(), g.order.end());
+        goff.push_back(items.size());
+        items.insert(items.end(), g.items.begin(), g.items.end());
     }
-    const size_t walk_off = orders.size();
-    orders.insert(orders.end(), P.walk.begin(), P.walk.end());
+    const size_t ngroups = P.groups.size();
 
     const size_t jobs_b = sizeof(PairJob) * (size_t)cnt;
     const size_t pj_b = sizeof(PairJob) * pjobs.size();
     const size_t ps_b = sizeof(int64_t) * pstarts.size();
-    const size_t ord_b = sizeof(int32_t) * orders.size();
+    const size_t it_b = sizeof(int2) * items.size();
+    const size_t wk_b = sizeof(int32_t) * P.walk.size();
     int rc;
     // the staging buffer and workspace may still be in use by earlier work
     if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
     if ((rc = ws.jobs.ensure(jobs_b + pj_b + 256)) != MPG_OK) return rc;
     if ((rc = ws.row_start.ensure(ps_b + 64)) != MPG_OK) return rc;
-    if ((rc = ws.order.ensure(ord_b + 64)) != MPG_OK) return rc;
+    if ((rc = ws.order.ensure(it_b + wk_b + 64)) != MPG_OK) return rc;
     if ((rc = ws.desc.ensure((size_t)P.desc_bytes + 64)) != MPG_OK) return rc;
     if ((rc = ws.bnd.ensure(sizeof(int2) * (size_t)P.bnd_elems + 64)) != MPG_OK) return rc;
     if ((rc = ws.tb.ensure((size_t)P.tb_bytes + 64)) != MPG_OK) return rc;
-    const size_t plan_b = jobs_b + pj_b + ps_b + ord_b + 1024;
+    if ((rc = ws.state.ensure((size_t)kPairStateBytes * cnt + sizeof(int) * (P.nprog + 64))) !=
+        MPG_OK)
+        return rc;
+    const size_t plan_b = jobs_b + pj_b + ps_b + it_b + wk_b + 1024;
     if ((rc = ws.hplan.ensure(plan_b)) != MPG_OK) return rc;
     uint8_t* h = (uint8_t*)ws.hplan.p;
     std::memcpy(h, P.jobs.data(), jobs_b);
     std::memcpy(h + jobs_b, pjobs.data(), pj_b);
     std::memcpy(h + jobs_b + pj_b, pstarts.data(), ps_b);
-    std::memcpy(h + jobs_b + pj_b + ps_b, orders.data(), ord_b);
+    std::memcpy(h + jobs_b + pj_b + ps_b, items.data(), it_b);
+    std::memcpy(h + jobs_b + pj_b + ps_b + it_b, P.walk.data(), wk_b);
     PairJob* d_jobs = (PairJob*)ws.jobs.p;
     PairJob* d_pjobs = (PairJob*)((uint8_t*)ws.jobs.p + jobs_b);
     int64_t* d_starts = (int64_t*)ws.row_start.p;
-    int32_t* d_order = (int32_t*)ws.order.p;
+    int2* d_items = (int2*)ws.order.p;
+    int32_t* d_walk = (int32_t*)((uint8_t*)ws.order.p + it_b);
+    uint8_t* d_state = (uint8_t*)ws.state.p;
+    void* d_pst = d_state;
+    int* d_qhead = (int*)(d_state + (size_t)kPairStateBytes * cnt);  // one per launch
+    int* d_prog = d_qhead + 16;
     hipError_t e = hipSuccess;
     if (jobs_b + pj_b) e = hipMemcpyAsync(ws.jobs.p, h, jobs_b + pj_b, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && ps_b)
         e = hipMemcpyAsync(d_starts, h + jobs_b + pj_b, ps_b, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && ord_b)
-        e = hipMemcpyAsync(d_order, h + jobs_b + pj_b + ps_b, ord_b, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && it_b + wk_b)
+        e = hipMemcpyAsync(ws.order.p, h + jobs_b + pj_b + ps_b, it_b + wk_b,
+                           hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return MPG_E_DEVICE;
 
     if (launch_status(st, d_jobs, cnt, d_out) != hipSuccess) return MPG_E_DEVICE;
+    const int neg_init = -(1 << 30);
+    if (launch_init(st, d_jobs, cnt, d_pst, d_prog, d_qhead, 16, neg_init) != hipSuccess)
+        return MPG_E_DEVICE;
     if (tm) tm->begin(st, 0);
     if (launch_prepass(st, d_pjobs, d_starts, (int)pjobs.size(), P.total_rows, d_dna,
                        (uint8_t*)ws.desc.p, DP) != hipSuccess)
         return MPG_E_DEVICE;
     if (tm) tm->end(st, 0);
     if (tm) tm->begin(st, 1);
-    if (P.groups.size() == 1) {
-        const Group& G = P.groups[0];
-        e = launch_dp(st, G.K, G.W, G.tb, DP, d_jobs, d_order + goff[0], (int)G.order.size(),
-                      d_prot, (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, (uint8_t*)ws.tb.p,
-                      d_out);
-        if (e != hipSuccess) return MPG_E_DEVICE;
-    } else if (!P.groups.empty()) {
+    auto launch_group = [&](hipStream_t s2, size_t g) -> hipError_t {
+        const Group& G = P.groups[g];
+        const int nit = (int)G.items.size();
+        const int grid = std::max(1, std::min(nit, 2 * g_wave_slots));
+        return launch_dp(s2, G.K, G.tb, grid, DP, d_jobs, d_items + goff[g], nit,
+                         d_qhead + g, d_pst, d_prog, d_prot, (const uint8_t*)ws.desc.p,
+                         (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, d_out);
+    };
+    if (ngroups > 15) return MPG_E_INVAL;
+    if (ngroups == 1) {
+        if (launch_group(st, 0) != hipSuccess) return MPG_E_DEVICE;
+    } else if (ngroups > 1) {
         // fork: every variant's launch starts after the prepass, concurrently
         if ((rc = ws.ensure_streams()) != MPG_OK) return rc;
         if (hipEventRecord(ws.fork_ev, st) != hipSuccess) return MPG_E_DEVICE;
-        const int ng = (int)std::min<size_t>(P.groups.size(), kSideStreams);
+        const int ng = (int)std::min<size_t>(ngroups, kSideStreams);
         for (int k = 0; k < ng; ++k)
             if (hipStreamWaitEvent(ws.side[k], ws.fork_ev, 0) != hipSuccess) return MPG_E_DEVICE;
-        for (size_t g = 0; g < P.groups.size(); ++g) {
-            const Group& G = P.groups[g];
-            e = launch_dp(ws.side[g % kSideStreams], G.K, G.W, G.tb, DP, d_jobs,
-                          d_order + goff[g], (int)G.order.size(), d_prot,
-                          (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, d_out);
-            if (e != hipSuccess) return MPG_E_DEVICE;
-        }
+        for (size_t g = 0; g < ngroups; ++g)
+            if (launch_group(ws.side[g % kSideStreams], g) != hipSuccess) return MPG_E_DEVICE;
         // join
         for (int k = 0; k < ng; ++k) {
             if (hipEventRecord(ws.join_ev[k], ws.side[k]) != hipSuccess) return MPG_E_DEVICE;
@@ -524,8 +542,8 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     if (tm) tm->end(st, 1);
     if (!P.walk.empty()) {
         if (tm) tm->begin(st, 2);
-        e = launch_walk(st, d_jobs, d_order + walk_off, (int)P.walk.size(),
-                        (const uint8_t*)ws.tb.p, d_out, d_ops);
+        e = launch_walk(st, d_jobs, d_walk, (int)P.walk.size(), (const uint8_t*)ws.tb.p, d_out,
+                        d_ops);
         if (e != hipSuccess) return MPG_E_DEVICE;
         if (tm) tm->end(st, 2);
     }
@@ -553,10 +571,11 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
     std::vector<int32_t> idx;
     idx.reserve(n);
     int64_t acc = 0;
+    const Overrides ov;
     for (int32_t k = 0; k < n; ++k) {
         const mpg_seg& s = segs[k];
         const int64_t b = (seg_tb(s, p) && s.plen >= 0 && s.dlen >= 0)
-                              ? tb_bytes_of(s.dlen, s.plen, choose_K(s.plen))
+                              ? tb_bytes_of(s.dlen, s.plen, choose_K(s.plen, ov))
                               : 0;
         if (b <= (int64_t)tb_budget && acc + b > (int64_t)tb_budget && !idx.empty()) {
             int rc = run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(),
@@ -650,7 +669,7 @@ int mpg_ctx_create(mpg_ctx** out, int device, uint64_t tb_budget_bytes, uint32_t
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
             hipSuccess &&
         lds > 0)
-        g_max_lds = std::min(lds, 65536);
+        g_max_lds = lds;
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         ncu > 0)
@@ -709,7 +728,7 @@ int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot
     if (need > 0 && (!d_ops || ops_cap < need)) return MPG_E_RANGE;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
-    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool};
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host};
     ctx->n_calls++;
     return run_dev_waves(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, n, d_out, d_ops,
                          ctx->tb_budget, ctx->timing ? &tm : nullptr);
@@ -904,7 +923,7 @@ int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, in
     if (n == 0) return MPG_OK;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
-    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool};
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host};
     ctx->n_calls++;
     return align_host(ctx->stream, ctx->ws, p, pairs, n, out, ctx->tb_budget,
                       ctx->timing ? &tm : nullptr);
@@ -925,7 +944,7 @@ int mpg_submit(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pair, uint64_t
         return MPG_E_INVAL;
     }
     const bool tb = ((pair->flags | p->flags) & MPG_WANT_TB) != 0;
-    const int64_t tbb = tb ? tb_bytes_of(pair->dlen, pair->plen, choose_K(pair->plen)) : 0;
+    const int64_t tbb = tb ? tb_bytes_of(pair->dlen, pair->plen, choose_K(pair->plen, Overrides())) : 0;
     if (pair->dlen > MPG_MAX_DNA || pair->plen > MPG_MAX_PROT || (uint64_t)tbb > ctx->tb_budget ||
         !score_bound_ok(p, pair->dlen, pair->plen)) {
         ctx->stats.rejected_range++;
@@ -1031,8 +1050,9 @@ int mpg_get_timing(mpg_ctx* ctx, mpg_timing* t, int reset) {
     t->walk_ms = ctx->t_walk;
     t->dp_spans = ctx->n_dp;
     t->calls = ctx->n_calls;
+    t->host_ms = ctx->t_host;
     if (reset) {
-        ctx->t_pre = ctx->t_dp = ctx->t_walk = 0;
+        ctx->t_pre = ctx->t_dp = ctx->t_walk = ctx->t_host = 0;
         ctx->n_dp = ctx->n_calls = 0;
     }
     return MPG_OK;

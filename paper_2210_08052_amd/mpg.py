@@ -66,7 +66,7 @@ class mpg_stats(ctypes.Structure):
 class mpg_timing(ctypes.Structure):
     _fields_ = [("prepass_ms", ctypes.c_double), ("dp_ms", ctypes.c_double),
                 ("walk_ms", ctypes.c_double), ("dp_spans", ctypes.c_uint64),
-                ("calls", ctypes.c_uint64)]
+                ("calls", ctypes.c_uint64), ("host_ms", ctypes.c_double)]
 
 
 SEG_DTYPE = np.dtype([("prot_off", "<i8"), ("dna_off", "<i8"), ("plen", "<i4"),

@@ -47,19 +47,17 @@ def test_random_small_random_scoring(ctx, mode, tb):
 
 
 @pytest.mark.parametrize("K", [1, 2, 4])
-@pytest.mark.parametrize("Wv", [1, 2, 3])
-def test_kernel_variants(ctx, K, Wv, monkeypatch):
-    """Every columns-per-lane width and the multi-wavefront tiled schedule
-    (W waves per pair handing the boundary column over through LDS) give
-    identical results; proteins span several strips and ragged tails."""
+def test_kernel_variants(ctx, K, monkeypatch):
+    """Every columns-per-lane width gives identical results; proteins span
+    up to 11 strips whose boundary columns stream from strip to strip through
+    HBM while the strips run concurrently, with ragged last strips and tails."""
     monkeypatch.setenv("MPG_FORCE_K", str(K))
-    monkeypatch.setenv("MPG_FORCE_W", str(Wv))
-    pairs = _pairs(400 + K * 10 + Wv, n=24, max_prot=700, max_dna=900, min_prot=100)
+    pairs = _pairs(400 + K * 10, n=24, max_prot=700, max_dna=900, min_prot=100)
     for mode in (0, 1, 2):
         for tb in (False, True):
-            print("case K=%d W=%d mode=%d tb=%d" % (K, Wv, mode, tb), flush=True)
+            print("case K=%d mode=%d tb=%d" % (K, mode, tb), flush=True)
             g, o = scorings(mode, 0)
-            compare(ctx, pairs, g, o, tb, label="K%d W%d m%d" % (K, Wv, mode))
+            compare(ctx, pairs, g, o, tb, label="K%d m%d" % (K, mode))
 
 
 def test_edge_cases(ctx):
@@ -109,9 +107,10 @@ def test_batch_full_size_sampled(ctx):
         assert key_gpu(so[k], False) == key_orc(e, False), int(k)
 
 
-def test_long_pairs_tiled(ctx):
-    """Long proteins against long regions run in the multi-wavefront tiled
-    kernel; a few moderately long planted pairs are checked exactly."""
+def test_long_pairs_pipelined(ctx):
+    """Long proteins against long regions: their strips run as a pipeline
+    over many wavefronts; a few moderately long planted pairs are checked
+    exactly."""
     rng = np.random.default_rng(11)
     pairs = []
     for s in range(3):
@@ -122,12 +121,8 @@ def test_long_pairs_tiled(ctx):
         pad = W.BASES[gen.integers(0, 4, size=4000)].tobytes()
         pairs.append((prot, pad + gene.tobytes() + pad))
     g, o = scorings(0, 0)
-    os.environ["MPG_FORCE_W"] = "4"
-    try:
-        compare(ctx, pairs, g, o, True, label="long tb")
-        compare(ctx, pairs, g, o, False, label="long so")
-    finally:
-        del os.environ["MPG_FORCE_W"]
+    compare(ctx, pairs, g, o, True, label="long tb")
+    compare(ctx, pairs, g, o, False, label="long so")
 
 
 def test_batching_invariance(ctx):
