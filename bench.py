@@ -35,6 +35,14 @@ PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
 OPS_PER_CELL = {"score": 23, "traceback": 23}
 METRIC = "GCUPS batched spliced DP (bit-exact) + p50/p99 latency at fixed arrival rate"
 
+# Copy-calibrated HBM traffic of the dominant DP kernel, per workload, as
+# recorded by rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs in profiles/.  The
+# figure is reported only while the kernel sources still hash to the value
+# recorded beside it (otherwise the counters describe an older kernel).
+TRAFFIC_PROFILE = {"batch": "dp_kernel_k2_local_score__batch10k.md"}
+DP_SOURCES = ["paper_2210_08052_amd/csrc/mpg_dp.h", "paper_2210_08052_amd/csrc/mpg_internal.h",
+              "paper_2210_08052_amd/csrc/mpg_dp_k2.hip"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -61,6 +69,25 @@ def build_workload(config: str):
     else:
         raise SystemExit("unknown --config %s" % config)
     return pairs, tb, desc
+
+
+def recorded_traffic(config: str):
+    import hashlib
+    name = TRAFFIC_PROFILE.get(config)
+    if not name:
+        return None
+    try:
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+        h = hashlib.sha256()
+        for f in DP_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except OSError:
+        return None
+    fields = dict(ln.split(":", 1) for ln in text.splitlines()
+                  if ln.startswith(("traffic_bytes_per_launch:", "dp_source_sha256:")))
+    if fields.get("dp_source_sha256", "").strip() != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(pairs, tb: bool, budget_s: float):
@@ -192,7 +219,7 @@ def main():
                    "traceback": tb, "mode": "LOCAL"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                      "unit": "Tops/s (int32 lane-ops)", "frac": round(achieved / peak, 4),
-                     "traffic": None, "kernel_gcups": round(kernel_gcups, 2),
+                     "traffic": recorded_traffic(args.config), "kernel_gcups": round(kernel_gcups, 2),
                      "ops_per_cell": OPS_PER_CELL["traceback" if tb else "score"],
                      "dp_ms_per_step": round(dp_ms, 3)},
         "cpu_baseline": cpu,
