@@ -13,7 +13,11 @@ throughput on a bounded sample of the same batch (``cpu_baseline``).
 
 Other workloads (``--config``): ``single`` (one 3,000-nt pair with
 traceback), ``traceback`` (the same 10,000 pairs with traceback),
-``longtail`` (200 long + 2,000 short pairs with traceback).
+``longtail`` (200 long + 2,000 short pairs with traceback) and ``serving``
+(200,000 jobs submitted one by one at Poisson arrival times through
+``mpg_submit``/``mpg_poll``; reports p50/p99 latency from the scheduled
+arrival to the result, served GCUPS, the same jobs run one pair per launch,
+and a batched re-run of a sample of jobs compared with the served results).
 """
 from __future__ import annotations
 
@@ -121,6 +125,176 @@ def cpu_baseline(pairs, tb: bool, budget_s: float):
                 k, len(pairs), cells, dt, model)}
 
 
+# Arrival rate of the serving workload (jobs/s): 0.7 x the batched capacity
+# measured by ``--config serving --calibrate`` on the first 20,000 jobs of the
+# same stream, rounded to two significant digits and frozen here.
+SERVING_RATE = None
+LONG_REGION = 50000  # regions above this length come from the long-tail mixture
+
+
+def _percentiles(x):
+    if len(x) == 0:
+        return None
+    q = np.percentile(np.asarray(x, dtype=np.float64), [50, 99])
+    return {"p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3), "n": int(len(x))}
+
+
+def run_served(mpg, p, jobs, arrivals_s, log_every=20000):
+    """Open-loop submission of jobs at their arrival times (seconds from t0)
+    into a serving context; returns (t0_ns, done_ns per job, results)."""
+    import threading
+    srv = mpg.Context(0)
+    # warm-up: a few short jobs through the same context
+    for q in jobs[:64]:
+        srv.submit(p, q.prot, q.dna, want_tb=q.want_tb)
+    got = 0
+    while got < min(64, len(jobs)):
+        got += len(srv.poll(256, 100000))
+    n = len(jobs)
+    done_ns = np.zeros(n, dtype=np.int64)
+    results = [None] * n
+    id2k = {}
+    lock = threading.Lock()
+    t0 = time.monotonic_ns() + 20_000_000
+    due = t0 + np.round(np.asarray(arrivals_s) * 1e9).astype(np.int64)
+    finished = threading.Event()
+
+    def poller():
+        cnt = 0
+        while cnt < n:
+            for r in srv.poll(1024, 20000):
+                with lock:
+                    k = id2k.get(r["job_id"])
+                if k is None:
+                    continue
+                done_ns[k] = r["t_done_ns"]
+                results[k] = r
+                cnt += 1
+                if cnt % log_every == 0:
+                    log("served %d/%d" % (cnt, n))
+        finished.set()
+
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    for k, q in enumerate(jobs):
+        wait = int(due[k]) - time.monotonic_ns()
+        if wait > 300_000:
+            time.sleep((wait - 200_000) / 1e9)
+        while time.monotonic_ns() < due[k]:
+            pass
+        while True:
+            with lock:
+                jid = srv.submit(p, q.prot, q.dna, want_tb=q.want_tb)
+                if jid >= 0:
+                    id2k[jid] = k
+            if jid >= 0:
+                break
+            if jid != mpg.MPG_E_AGAIN:
+                raise RuntimeError("mpg_submit failed: %d" % jid)
+            time.sleep(1e-4)
+    finished.wait()
+    stats = srv.stats()
+    srv.close()
+    return t0, due, done_ns, results, stats
+
+
+def bench_serving(args):
+    import torch  # noqa: F401  (one HIP runtime for torch and the library)
+    from paper_2210_08052_amd import mpg
+    from paper_2210_08052_amd import workloads as W
+    n = args.jobs
+    t_gen = time.time()
+    jobs, arr1 = W.serving_jobs(n, rate_per_s=1.0, seed=5,
+                                progress=lambda k: log("generated %d jobs" % k))
+    log("serving workload: %d jobs generated in %.1f s" % (n, time.time() - t_gen))
+    cells = np.array([len(q.prot) * len(q.dna) for q in jobs], dtype=np.float64)
+    is_long = np.array([len(q.dna) > LONG_REGION for q in jobs])
+    is_tb = np.array([q.want_tb for q in jobs])
+    p = mpg.params()
+    if args.calibrate:
+        m = min(20000, n)
+        t0, due, done, res, st = run_served(mpg, p, jobs[:m], np.zeros(m))
+        span = (done.max() - t0) / 1e9
+        cap = m / span
+        rate = float("%.2g" % (0.7 * cap))
+        log("capacity %.1f jobs/s (%.1f GCUPS) on %d jobs; 0.7x = %.4g jobs/s" % (
+            cap, cells[:m].sum() / span / 1e9, m, rate))
+        print(json.dumps({"calibration": {"jobs": m, "span_s": round(span, 3),
+                                          "capacity_jobs_per_s": round(cap, 1),
+                                          "rate_jobs_per_s": rate}}), flush=True)
+        return
+    rate = args.rate or SERVING_RATE
+    if not rate:
+        raise SystemExit("no arrival rate: run --config serving --calibrate first or pass --rate")
+    arrivals = arr1 / rate
+    t0, due, done, res, st = run_served(mpg, p, jobs, arrivals)
+    lat = (done - due) / 1e6
+    bad = sum(1 for r in res if r is None or r["status"] != 0)
+    keep = np.arange(n) >= int(0.05 * n)  # drop the first 5% (warm-up)
+    span = (done.max() - t0) / 1e9
+    served = {
+        "all": _percentiles(lat[keep]),
+        "short": _percentiles(lat[keep & ~is_long]),
+        "long": _percentiles(lat[keep & is_long]),
+        "traceback": _percentiles(lat[keep & is_tb]),
+        "score_only": _percentiles(lat[keep & ~is_tb]),
+    }
+    gcups = cells.sum() / span / 1e9
+    log("served %d jobs in %.2f s: %.1f GCUPS, latency %s" % (n, span, gcups, served["all"]))
+
+    # the same jobs, one pair per launch, first come first served, on the
+    # same GPU and arrival times, for a bounded time
+    base = mpg.Context(0)
+    bl, bcells, bk = [], 0.0, 0
+    bt0 = time.monotonic_ns()
+    bdue = bt0 + np.round(arrivals * 1e9).astype(np.int64)
+    busy = 0.0
+    while bk < n and (time.monotonic_ns() - bt0) / 1e9 < args.baseline_budget:
+        now = time.monotonic_ns()
+        if now < bdue[bk]:
+            time.sleep((bdue[bk] - now) / 1e9)
+        q = jobs[bk]
+        ts = time.monotonic_ns()
+        r = base.align_batch([(q.prot, q.dna, q.want_tb)], p)[0]
+        te = time.monotonic_ns()
+        busy += (te - ts) / 1e9
+        if r["status"] != 0:
+            bad += 1
+        bl.append((te - bdue[bk]) / 1e6)
+        bcells += cells[bk]
+        bk += 1
+    base.close()
+    baseline = {"jobs": bk, "latency": _percentiles(bl),
+                "sustained_jobs_per_s": round(bk / busy, 1) if busy else None,
+                "sustained_gcups": round(bcells / busy / 1e9, 2) if busy else None,
+                "saturated": bool(bk < n and bdue[bk] < time.monotonic_ns())}
+    log("one-pair-per-launch: %s" % json.dumps(baseline))
+
+    # served results equal batched results for the same jobs (seeded sample)
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(n, size=min(args.check, n), replace=False))
+    with mpg.Context(0) as ctx:
+        ref = ctx.align_batch([(jobs[k].prot, jobs[k].dna, jobs[k].want_tb) for k in sample], p)
+    keys = ("status", "score", "g_beg", "g_end", "p_beg", "p_end", "ops")
+    mism = sum(1 for k, r in zip(sample, ref)
+               if res[k] is None or any(res[k][f] != r[f] for f in keys))
+    line = {
+        "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(span * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded planted genes)",
+        "config": {"workload": "serving: %d jobs, Poisson arrivals at %.4g jobs/s, 90/10 batch/"
+                               "long-tail mixture, 50%% traceback, LOCAL" % (n, rate),
+                   "jobs": n, "cells": float(cells.sum()), "rate_jobs_per_s": rate},
+        "latency": served,
+        "failed_jobs": bad,
+        "served_vs_batched_mismatches": {"checked": int(len(sample)), "mismatches": mism},
+        "one_pair_per_launch": baseline,
+        "serving_stats": st,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +306,14 @@ def main():
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--jobs", type=int, default=200000, help="serving: number of jobs")
+    ap.add_argument("--rate", type=float, default=0.0, help="serving: arrival rate override")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="serving: measure the batched capacity on the first 20,000 jobs")
+    ap.add_argument("--baseline-budget", type=float, default=20.0,
+                    help="serving: seconds of one-pair-per-launch baseline")
+    ap.add_argument("--check", type=int, default=500,
+                    help="serving: jobs re-run as a batch and compared")
     args = ap.parse_args()
     if args.copy_calibrate:
         import torch
@@ -147,6 +329,10 @@ def main():
               "measures one GPU's share (see the design notes for the sharded layout).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "serving":
+        bench_serving(args)
+        return
 
     import torch
     from paper_2210_08052_amd import mpg

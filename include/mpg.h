@@ -170,13 +170,16 @@ typedef struct {
 /* Device-side result record written by mpg_align_batch_dev (40 bytes). */
 typedef struct {
     int32_t status, score, g_beg, g_end, p_beg, p_end;
-    int64_t ops_off; /* byte offset of this pair's op string in the ops buffer */
+    int64_t ops_off; /* byte offset of this pair's NUL-terminated op string in the ops
+                        buffer; it lies inside the pair's slot (see mpg_ops_capacity) */
     int32_t ops_len;
     int32_t _pad;
 } mpg_dev_result;
 
-/* Bytes of op-string buffer that mpg_align_batch_dev needs for these pairs
- * (an upper bound: 2*(plen+dlen)+1 per traceback pair). */
+/* Bytes of op-string buffer that mpg_align_batch_dev needs for these pairs:
+ * pairs take consecutive slots in input order, 2*(plen+dlen)+1 bytes for a
+ * traceback pair (enough for any path: every token consumes at least one
+ * residue or nucleotide per two characters) and 1 byte otherwise. */
 int64_t mpg_ops_capacity(const mpg_seg *segs, int32_t n);
 
 /*

@@ -139,104 +139,180 @@ __device__ __forceinline__ int ndigits(int v) {
     return d;
 }
 
-// Walks back from (i, j) in state H.  Pass 0 returns the op-string length;
-// pass 1 writes the string backwards from txt[len].  Returns -1 on an
-// inconsistent path (never expected), and the start cell in (bi, bj).
-__device__ int walk_pair(const TbView& V, int i, int j, int n, int m, char* txt, int len,
-                         bool write, int& bi, int& bj) {
-    int st = 0;  // 0 H, 1 I, 2 D, 3 A, 4 B, 5 C
-    int kend = 0;
-    char pop = 0;
-    int plen = 0, total = 0, pos = len;
-    const int64_t guard = 4LL * (n + m) + 64;
-    auto flush = [&]() {
+// Op-string writer: tokens are produced last-to-first and written backwards
+// from the end of the pair's slot; lane 0 stores the bytes.  M, I and D runs
+// are merged into one token, F, G, N, U and V never.
+struct OpWriter {
+    char* txt;
+    int64_t pos;   // first byte written so far
+    char pop = 0;  // pending (not yet written) token
+    int plen = 0;
+    bool overflow = false;
+    __device__ void flush(int lane) {
         if (!pop) return;
-        total += ndigits(plen) + 1;
-        if (write) {
-            txt[--pos] = pop;
-            int v = plen;
-            do { txt[--pos] = (char)('0' + v % 10); v /= 10; } while (v);
+        const int nd = ndigits(plen);
+        if (pos < nd + 1) {
+            overflow = true;
+            pop = 0;
+            return;
         }
+        if (lane == 0) {
+            txt[pos - 1] = pop;
+            int v = plen;
+            for (int d = 2; d <= nd + 1; ++d) {
+                txt[pos - d] = (char)('0' + v % 10);
+                v /= 10;
+            }
+        }
+        pos -= nd + 1;
         pop = 0;
-    };
-    auto emit = [&](char op, int l, bool merge) {
-        if (merge && pop == op) { plen += l; return; }
-        flush();
+    }
+    __device__ void emit(char op, int l, bool merge, int lane) {
+        if (merge && pop == op) {
+            plen += l;
+            return;
+        }
+        flush(lane);
         pop = op;
         plen = l;
-        if (!merge) flush();
-    };
+        if (!merge) flush(lane);
+    }
+};
+
+// Walks one pair back from its end cell, one wavefront per pair.  The
+// choices along the path are read speculatively 64 at a time: in state H the
+// lanes read the H codes down the diagonal (a run of codon:residue steps),
+// in a gap state the extension bits along the gap, and in an intron state
+// the extension bits of 4 consecutive rows each (256 rows per round); a
+// ballot finds where the run ends.  Every round is then one memory round
+// trip for up to 64-256 steps of the path.  Returns the start cell in
+// (bi, bj), or false on an inconsistent path (never expected).
+__device__ bool walk_wave(const TbView& V, int i, int j, int n, int m, OpWriter& W, int lane,
+                          int& bi, int& bj) {
+    int st = 0;  // 0 H, 1 I, 2 D, 3 A, 4 B, 5 C
+    int kend = 0;
+    const int64_t guard = 4LL * (n + m) + 64;
     for (int64_t it = 0; it < guard; ++it) {
-        if (i < 0 || j < 0 || i > n || j > m) return -1;
+        if (i < 0 || j < 0 || i > n || j > m) return false;
         if (st == 0) {
-            const int hc = V.code(i, j);
-            if (hc == 0) {
-                flush();
-                bi = i;
-                bj = j;
-                return total;
+            const int ii = i - 3 * lane, jj = j - lane;
+            const bool ok = ii >= 0 && jj >= 0;
+            const int hc = ok ? V.code(ii, jj) : -1;
+            const uint64_t stop = __ballot(hc != 1);
+            if (stop == 0) {
+                W.emit('M', 64, true, lane);
+                i -= 192;
+                j -= 64;
+                continue;
             }
-            switch (hc) {
-                case 1: emit('M', 1, true); i -= 3; j -= 1; break;
+            const int l = __builtin_ctzll(stop);
+            if (l) W.emit('M', l, true, lane);
+            i -= 3 * l;
+            j -= l;
+            const int c = __builtin_amdgcn_readlane(hc, l);
+            switch (c) {
+                case 0:
+                    W.flush(lane);
+                    bi = i;
+                    bj = j;
+                    return true;
                 case 2: st = 1; break;
                 case 3: st = 2; break;
-                case 4: emit('F', 1, false); i -= 1; j -= 1; break;
-                case 5: emit('F', 2, false); i -= 2; j -= 1; break;
-                case 6: emit('G', 1, false); i -= 1; break;
-                case 7: emit('G', 2, false); i -= 2; break;
+                case 4: W.emit('F', 1, false, lane); i -= 1; j -= 1; break;
+                case 5: W.emit('F', 2, false, lane); i -= 2; j -= 1; break;
+                case 6: W.emit('G', 1, false, lane); i -= 1; break;
+                case 7: W.emit('G', 2, false, lane); i -= 2; break;
                 case 8: st = 3; kend = i; break;
                 case 9: st = 4; kend = i; break;
                 case 10: st = 5; kend = i; break;
-                default: return -1;
+                default: return false;
             }
-        } else if (st == 1) {
-            emit('I', 1, true);
-            if (!V.ext(0, i, j)) st = 0;
-            j -= 1;
-        } else if (st == 2) {
-            emit('D', 1, true);
-            if (!V.ext(1, i, j)) st = 0;
-            i -= 3;
+        } else if (st <= 2) {
+            // gap run: I moves left along the row, D up by one codon
+            const int ii = st == 1 ? i : i - 3 * lane;
+            const int jj = st == 1 ? j - lane : j;
+            const bool ok = ii >= 0 && jj >= 0;
+            const int bit = ok ? V.ext(st - 1, ii, jj) : 0;
+            const uint64_t endm = __ballot(!ok || !bit);
+            if (endm == 0) {
+                W.emit(st == 1 ? 'I' : 'D', 64, true, lane);
+                if (st == 1) j -= 64; else i -= 192;
+                continue;
+            }
+            const int l = __builtin_ctzll(endm);
+            if (!__builtin_amdgcn_readlane((int)ok, l)) return false;
+            W.emit(st == 1 ? 'I' : 'D', l + 1, true, lane);
+            if (st == 1) j -= l + 1; else i -= 3 * (l + 1);
+            st = 0;
         } else {
-            if (!V.ext(st - 1, i, j)) {
-                emit(st == 3 ? 'N' : st == 4 ? 'U' : 'V', kend - i + 1, false);
-                if (st != 3) j -= 1;
-                st = 0;
+            // intron run: rows i - (4*lane + r), r = 0..3
+            int first = 4;
+            bool bad = false;
+#pragma unroll
+            for (int r = 3; r >= 0; --r) {
+                const int ii = i - 4 * lane - r;
+                if (ii < 0) {
+                    first = r;
+                    bad = true;
+                } else if (!V.ext(st - 1, ii, j)) {
+                    first = r;
+                    bad = false;
+                }
             }
-            i -= 1;
+            const uint64_t endm = __ballot(first < 4);
+            if (endm == 0) {
+                i -= 256;
+                continue;
+            }
+            const int l = __builtin_ctzll(endm);
+            if (__builtin_amdgcn_readlane((int)bad, l)) return false;
+            const int f = 4 * l + __builtin_amdgcn_readlane(first, l);
+            const int k = i - f;
+            W.emit(st == 3 ? 'N' : st == 4 ? 'U' : 'V', kend - k + 1, false, lane);
+            if (st != 3) j -= 1;
+            i = k - 1;
+            st = 0;
         }
     }
-    return -1;
+    return false;
 }
 
+// One wavefront (block) per traced pair.  The op string ends at the last
+// byte but one of the pair's slot (2(n+m)+1 bytes, enough for any path) and
+// the record's ops_off points at its first byte.
 __global__ void __launch_bounds__(64) walk_kernel(const PairJob* __restrict__ jobs,
                                                   const int32_t* __restrict__ order, int count,
                                                   const uint8_t* __restrict__ tbbuf,
                                                   mpg_dev_result* __restrict__ out,
                                                   char* __restrict__ ops) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= count) return;
-    const PairJob J = jobs[order[k]];
+    const int w = blockIdx.x;
+    if (w >= count) return;
+    const int lane = threadIdx.x;
+    const PairJob J = jobs[order[w]];
     mpg_dev_result R = out[J.res];
     char* txt = ops + J.ops_off;
     if (J.status != MPG_OK || R.status != MPG_OK) {
-        txt[0] = 0;
+        if (lane == 0) txt[0] = 0;
         return;
     }
-    TbView V{tbbuf + J.tb_off, J.K, J.nchunks};
+    const TbView V{tbbuf + J.tb_off, J.K, J.nchunks};
+    const int64_t end = 2LL * (J.n + J.m);
+    OpWriter W{txt, end};
     int bi = -1, bj = -1;
-    const int len = walk_pair(V, R.g_end, R.p_end, J.n, J.m, txt, 0, false, bi, bj);
-    if (len < 0 || len > 2 * (J.n + J.m)) {
-        R.status = MPG_E_DEVICE;
-        txt[0] = 0;
-    } else {
-        walk_pair(V, R.g_end, R.p_end, J.n, J.m, txt, len, true, bi, bj);
-        txt[len] = 0;
-        R.g_beg = bi;
-        R.p_beg = bj;
-        R.ops_len = len;
+    const bool ok = walk_wave(V, R.g_end, R.p_end, J.n, J.m, W, lane, bi, bj);
+    if (lane == 0) {
+        if (!ok || W.overflow) {
+            R.status = MPG_E_DEVICE;
+            txt[0] = 0;
+        } else {
+            txt[end] = 0;
+            R.g_beg = bi;
+            R.p_beg = bj;
+            R.ops_off = J.ops_off + W.pos;
+            R.ops_len = (int32_t)(end - W.pos);
+        }
+        out[J.res] = R;
     }
-    out[J.res] = R;
 }
 
 // Records for pairs the host rejected before launch.
@@ -308,7 +384,7 @@ hipError_t launch_init(hipStream_t s, const PairJob* jobs, int npairs, void* pst
 hipError_t launch_walk(hipStream_t s, const PairJob* jobs, const int32_t* order, int count,
                        const uint8_t* tbbuf, mpg_dev_result* out, char* ops) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(walk_kernel, dim3((count + 63) / 64), dim3(64), 0, s, jobs, order, count,
+    hipLaunchKernelGGL(walk_kernel, dim3(count), dim3(64), 0, s, jobs, order, count,
                        tbbuf, out, ops);
     return hipGetLastError();
 }

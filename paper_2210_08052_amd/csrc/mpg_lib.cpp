@@ -467,7 +467,10 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     const size_t wk_b = sizeof(int32_t) * P.walk.size();
     int rc;
     // the staging buffer and workspace may still be in use by earlier work
+    // (the wait is device time, not host time)
+    const auto tw0 = std::chrono::steady_clock::now();
     if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    host_clock.t0 += std::chrono::steady_clock::now() - tw0;
     if ((rc = ws.jobs.ensure(jobs_b + pj_b + 256)) != MPG_OK) return rc;
     if ((rc = ws.row_start.ensure(ps_b + 64)) != MPG_OK) return rc;
     if ((rc = ws.order.ensure(it_b + wk_b + 64)) != MPG_OK) return rc;

@@ -310,13 +310,17 @@ def long_tail(n_long: int = 200, n_short: int = 2000, seed: int = 4) -> list:
 
 
 def serving_jobs(n_jobs: int = 200000, rate_per_s: float = 1000.0, seed: int = 5,
-                 p_long_mix: float = 0.1, p_tb: float = 0.5):
+                 p_long_mix: float = 0.1, p_tb: float = 0.5, progress=None):
     """Poisson job stream: each job is a batch-distribution pair w.p. 0.9, else
     a long-tail-mixture pair (long w.p. 200/2200); traceback w.p. 0.5.
-    Returns (pairs, arrival_times_s)."""
+    Returns (pairs, arrival_times_s).  The arrival times scale exactly as
+    1/rate_per_s (the same draws for every rate).  ``progress(k)`` is called
+    every 10,000 jobs if given."""
     rng = np.random.Generator(np.random.PCG64(seed))
     jobs = []
-    for _ in range(n_jobs):
+    for k in range(n_jobs):
+        if progress is not None and k and k % 10000 == 0:
+            progress(k)
         if rng.random() >= p_long_mix:
             p = None
             while p is None:
