@@ -203,8 +203,16 @@ int mpg_sync(mpg_ctx *ctx);
  * Submit one job.  The sequences are copied before the call returns.  All
  * jobs of one context must use the same params (the first submit fixes them;
  * a different set returns MPG_E_INVAL).  A job whose traceback bytes exceed
- * the whole traceback budget returns MPG_E_RANGE; a full queue returns
- * MPG_E_AGAIN.  *job_id receives the job's id.  Thread-safe against mpg_poll.
+ * the traceback budget returns MPG_E_RANGE (for a long job, more than 2e8
+ * cells, 7/8 of the budget: the rest is kept for short jobs); a full queue
+ * returns MPG_E_AGAIN.  *job_id receives the job's id.  Thread-safe against
+ * mpg_poll.
+ *
+ * Scheduling: short and long jobs, with and without traceback, wait in four
+ * queues.  Short jobs run in micro-batches (about 2e8 cells) on two streams;
+ * long jobs are gathered into batches of their own on two more streams, each
+ * held to about a third of the device, so short results never wait behind a
+ * long pair.  Results appear in mpg_poll as their batch completes.
  */
 int mpg_submit(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pair, uint64_t *job_id);
 

@@ -19,7 +19,7 @@
  *   H(i,j) = max{ H(i-3,j-1) + s(i,j), I, D, H(i-1,j-1)-f, H(i-2,j-1)-f,
  *                 H(i-1,j)-f, H(i-2,j)-f, A-a(i), B-a(i-2), C-a(i-1) }
  *
- * Readings of the paper that this file follows (all listed in the design notes):
+ * Readings of the paper that this file follows:
  *  - the printed match term H(i-3,j)+s(i,j) consumes no residue and would
  *    duplicate D at zero gap cost; the codon:residue step is H(i-3,j-1)+s(i,j)
  *    (the AE86 form, Eq. (ae86), uses H(i-1,j-1)+s, and the worked alignment

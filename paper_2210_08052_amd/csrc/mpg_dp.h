@@ -6,10 +6,14 @@
 
 #include "mpg_internal.h"
 
-// Minimum occupancy target of the DP kernels (waves per SIMD); 1 = no cap.
-#ifndef MPG_DP_WAVES_PER_EU
-#define MPG_DP_WAVES_PER_EU 1
-#endif
+// Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  The
+// score-only kernels with K <= 2 fit three waves per SIMD (168 VGPRs) with
+// spills only outside the step loop; K = 4 and the traceback kernels would
+// spill inside it, so they keep their registers.
+template <int K, bool TB>
+struct WavesPerEu {
+    static constexpr int value = (!TB && K <= 2) ? 3 : 1;
+};
 
 namespace mpg {
 namespace dev {
@@ -99,20 +103,6 @@ struct Sentinel {
     static constexpr int UNREACH = MODE == MPG_LOCAL ? NEG / 2 : -(1 << 29);
 };
 
-// Bounded wait for a workgroup-local progress counter.  Gives up (and tells
-// every other wave to give up) after about 2^22 polls, so no wave can spin
-// forever; the pair then reports MPG_E_DEVICE.
-__device__ __forceinline__ bool wait_at_least(int* flag, int target, int* dead) {
-    for (int it = 0; it < (1 << 22); ++it) {
-        if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target)
-            return true;
-        if (__hip_atomic_load(dead, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
-        __builtin_amdgcn_s_sleep(1);
-    }
-    __hip_atomic_store(dead, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    return false;
-}
-
 extern "C" __device__ int mpg_writelane_i32(int val, int lane, int old) __asm(
     "llvm.amdgcn.writelane.i32");
 
@@ -165,7 +155,8 @@ __device__ __forceinline__ bool wait_prog(const int* flag, int target) {
 // wavefront slot stays busy until the queue is empty.  Dependencies only point
 // to items taken earlier by running wavefronts, so the waits always end.
 template <int K, int MODE, bool TB, bool NOI, bool NOF>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MPG_DP_WAVES_PER_EU)))
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(WavesPerEu<K, TB>::value)))
 dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int nitems,
           int* __restrict__ qhead, PairState* __restrict__ pst, int* __restrict__ prog_g,
           const uint8_t* __restrict__ prot, const uint8_t* __restrict__ desc,
@@ -571,17 +562,28 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
 }
 
 template <int K, int MODE, bool TB>
-hipError_t launch_dp_t(hipStream_t s, int grid, const DevParams& P, const PairJob* jobs,
+hipError_t launch_dp_t(hipStream_t s, int ncu, const DevParams& P, const PairJob* jobs,
                        const int2* items, int nitems, int* qhead, PairState* pst, int* prog,
                        const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
                        mpg_dev_result* out) {
     const bool noi = (P.flags & MPG_NO_INTRON) != 0;
     const bool nof = (P.flags & MPG_NO_FRAMESHIFT) != 0;
     const size_t lds = (size_t)LdsLayout<K, TB>::WAVE;
-    dim3 g(grid), b(64);
+    dim3 b(64);
+    // persistent grid: as many waves as ncu compute units hold at once for
+    // this kernel, never more than there are items
 #define MPG_LAUNCH(NI, NF)                                                                      \
-    hipLaunchKernelGGL((dp_kernel<K, MODE, TB, NI, NF>), g, b, lds, s, jobs, items, nitems,    \
-                       qhead, pst, prog, prot, desc, bnd, tbbuf, out, P)
+    do {                                                                                        \
+        static int per_cu = 0;                                                                  \
+        if (per_cu <= 0 &&                                                                      \
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(                                       \
+                &per_cu, dp_kernel<K, MODE, TB, NI, NF>, 64, lds) != hipSuccess)                \
+            per_cu = 0;                                                                         \
+        const int waves = per_cu > 0 ? per_cu * ncu : 8 * ncu;                                \
+        dim3 g(nitems < waves ? nitems : waves);                                                \
+        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, NI, NF>), g, b, lds, s, jobs, items,        \
+                           nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out, P);           \
+    } while (0)
     if (!noi && !nof) MPG_LAUNCH(false, false);
     else if (noi && !nof) MPG_LAUNCH(true, false);
     else if (!noi && nof) MPG_LAUNCH(false, true);
@@ -591,14 +593,14 @@ hipError_t launch_dp_t(hipStream_t s, int grid, const DevParams& P, const PairJo
 }
 
 template <int K>
-hipError_t launch_dp_k(hipStream_t s, int grid, bool tb, const DevParams& P, const PairJob* jobs,
+hipError_t launch_dp_k(hipStream_t s, int ncu, bool tb, const DevParams& P, const PairJob* jobs,
                        const int2* items, int nitems, int* qhead, PairState* pst, int* prog,
                        const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
                        mpg_dev_result* out) {
 #define MPG_MODE(M)                                                                             \
-    return tb ? launch_dp_t<K, M, true>(s, grid, P, jobs, items, nitems, qhead, pst, prog, prot, \
+    return tb ? launch_dp_t<K, M, true>(s, ncu, P, jobs, items, nitems, qhead, pst, prog, prot, \
                                         desc, bnd, tbbuf, out)                                  \
-              : launch_dp_t<K, M, false>(s, grid, P, jobs, items, nitems, qhead, pst, prog,     \
+              : launch_dp_t<K, M, false>(s, ncu, P, jobs, items, nitems, qhead, pst, prog,     \
                                          prot, desc, bnd, tbbuf, out)
     switch (P.mode) {
         case MPG_LOCAL: MPG_MODE(MPG_LOCAL);

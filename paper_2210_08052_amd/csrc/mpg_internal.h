@@ -63,11 +63,12 @@ hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row
                           int npairs, int64_t total_rows, const uint8_t* dna, uint8_t* desc,
                           const DevParams& P);
 
-// One DP launch of `grid` persistent wavefronts over the work items
-// (job index, strip) of pairs that share K and traceback; all pairs of a
-// call share mode and flags.  qhead must be zero, pst and prog zeroed by
-// launch_init.
-hipError_t launch_dp(hipStream_t s, int K, bool tb, int grid, const DevParams& P,
+// One DP launch of persistent wavefronts over the work items (job index,
+// strip) of pairs that share K and traceback; all pairs of a call share mode
+// and flags.  The grid holds as many wavefronts as `ncu` compute units run at
+// once for this kernel, capped at the item count.  qhead must be zero, pst
+// and prog zeroed by launch_init.
+hipError_t launch_dp(hipStream_t s, int K, bool tb, int ncu, const DevParams& P,
                      const PairJob* jobs, const int2* items, int nitems, int* qhead, void* pst,
                      int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
                      uint8_t* tbbuf, mpg_dev_result* out);

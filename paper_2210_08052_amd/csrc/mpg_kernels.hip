@@ -7,7 +7,7 @@
 // H(i-3,j) consumes no residue), frameshift terms of Eq. (fs) and the splice
 // penalties of "Splice models" supplied as 3-mer tables.
 //
-// Data layout and schedule (see also the design notes):
+// Data layout and schedule:
 //  * prepass: one thread per genome row writes a row descriptor: the amino
 //    acid of the codon ending at the row, the start/floor value z(i) and the
 //    splice penalties the row needs (all rows -128 .. steps+64, with poison
@@ -17,17 +17,16 @@
 //    anti-diagonal order satisfies every dependency (rows i-1..i-3 of its own
 //    columns live in registers; the left neighbour's H and I of the same row
 //    arrive by a DPP wave_shr:1).  Lane 0 takes the left strip's last column
-//    from a 64-row shift register (DPP wave_shl:1), which at the same time
-//    collects lane 63's outputs for the next strip.  W wavefronts of a
-//    workgroup take W consecutive strips, each lagging the previous by two
-//    64-step chunks, handing the boundary column over through an LDS ring;
-//    the last wavefront hands it to the next pass through HBM;
+//    from HBM, where the wavefront running the left strip publishes it 64
+//    rows at a time behind a progress counter; the kernel is persistent and
+//    takes (pair, strip) items from one queue, longest pair first;
 //  * traceback variant: every value is kept as 16*v + nibble, where the
 //    nibble encodes the H winner (15 - code) so one max3 chain yields the
 //    value and the first-maximum tie-break together; gap/intron extension
 //    choices are wave ballots.  Both go to HBM as coalesced 256-512 B writes;
-//  * walk: one thread per pair follows the stored choices back from the end
-//    cell and writes the run-length op string.
+//  * walk: one wavefront per traced pair follows the stored choices back from
+//    the end cell, reading each run of the path in parallel, and writes the
+//    run-length op string.
 #include "mpg_dp.h"
 
 namespace mpg {
@@ -359,15 +358,15 @@ hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row
     return hipGetLastError();
 }
 
-hipError_t launch_dp(hipStream_t s, int K, bool tb, int grid, const DevParams& P,
+hipError_t launch_dp(hipStream_t s, int K, bool tb, int ncu, const DevParams& P,
                      const PairJob* jobs, const int2* items, int nitems, int* qhead, void* pst,
                      int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
                      uint8_t* tbbuf, mpg_dev_result* out) {
     if (nitems <= 0) return hipSuccess;
     switch (K) {
-        case 1: return launch_dp_k1(s, grid, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
-        case 2: return launch_dp_k2(s, grid, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
-        case 4: return launch_dp_k4(s, grid, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
+        case 1: return launch_dp_k1(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
+        case 2: return launch_dp_k2(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
+        case 4: return launch_dp_k4(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
         default: return hipErrorInvalidValue;
     }
 }

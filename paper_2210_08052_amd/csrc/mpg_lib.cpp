@@ -220,7 +220,7 @@ int choose_K(int m, const Overrides& ov) {
     return 2;
 }
 
-int g_wave_slots = 2048;  // concurrent DP wavefronts the device holds (CUs x 4 SIMDs x 2)
+int g_num_cu = 256;  // compute units of the device (the DP grid is sized per CU)
 
 int64_t tb_bytes_of(int n, int m, int K) {
     const int nsteps = ((n + 64 + 63) / 64) * 64;
@@ -372,15 +372,21 @@ struct mpg_ctx {
         int64_t tb_bytes;
         int64_t cells;
     };
-    std::deque<Job> pending;
+    // pending jobs by class: 2*long + traceback (long = more than kLongCells)
+    static constexpr int64_t kLongCells = 200000000LL;
+    std::deque<Job> pending[4];
+    size_t npending = 0;
     std::deque<mpg_result> done;
     uint64_t next_id = 1;
     bool stop = false;
     std::thread sched;
     bool sched_running = false;
     size_t max_pending = 1 << 20;
-    int nslots = 3;
-    int64_t slot_cells = 1500000000LL;
+    // slots 0..nshort-1 run short micro-batches, the rest long batches
+    int nshort = 2, nlong = 2;
+    int64_t short_cells = 200000000LL;    // cells per short micro-batch
+    int64_t long_cells = 60000000000LL;   // cells per long batch
+    double long_share = 0.35;             // device share of one long batch's grid
     int max_jobs_per_batch = 4096;
     mpg_stats stats{};
     uint64_t tb_in_use = 0;
@@ -425,7 +431,7 @@ struct Timer {
 int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
             const uint8_t* d_dna, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
             const std::vector<int64_t>& ops_off, mpg_dev_result* d_out, char* d_ops,
-            uint64_t tb_budget, Timer* tm) {
+            uint64_t tb_budget, Timer* tm, int ncu) {
     const auto th0 = std::chrono::steady_clock::now();
     struct HostClock {
         Timer* tm;
@@ -519,8 +525,7 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     auto launch_group = [&](hipStream_t s2, size_t g) -> hipError_t {
         const Group& G = P.groups[g];
         const int nit = (int)G.items.size();
-        const int grid = std::max(1, std::min(nit, 2 * g_wave_slots));
-        return launch_dp(s2, G.K, G.tb, grid, DP, d_jobs, d_items + goff[g], nit,
+        return launch_dp(s2, G.K, G.tb, ncu, DP, d_jobs, d_items + goff[g], nit,
                          d_qhead + g, d_pst, d_prog, d_prot, (const uint8_t*)ws.desc.p,
                          (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, d_out);
     };
@@ -562,7 +567,7 @@ bool seg_tb(const mpg_seg& s, const mpg_params* p) {
 // the stream; each wave writes straight into the caller's records and ops.
 int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
                   const uint8_t* d_dna, const mpg_seg* segs, int32_t n, mpg_dev_result* d_out,
-                  char* d_ops, uint64_t tb_budget, Timer* tm) {
+                  char* d_ops, uint64_t tb_budget, Timer* tm, int ncu) {
     std::vector<int64_t> ops_off(n);
     int64_t o = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -582,7 +587,7 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
                               : 0;
         if (b <= (int64_t)tb_budget && acc + b > (int64_t)tb_budget && !idx.empty()) {
             int rc = run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(),
-                             ops_off, d_out, d_ops, tb_budget, tm);
+                             ops_off, d_out, d_ops, tb_budget, tm, ncu);
             if (rc != MPG_OK) return rc;
             idx.clear();
             acc = 0;
@@ -592,7 +597,7 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
     }
     if (idx.empty()) return MPG_OK;
     return run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(), ops_off,
-                   d_out, d_ops, tb_budget, tm);
+                   d_out, d_ops, tb_budget, tm, ncu);
 }
 
 int params_check_impl(const mpg_params* p) {
@@ -676,7 +681,7 @@ int mpg_ctx_create(mpg_ctx** out, int device, uint64_t tb_budget_bytes, uint32_t
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         ncu > 0)
-        g_wave_slots = ncu * 4 * 2;
+        g_num_cu = ncu;
     mpg_ctx* c = new (std::nothrow) mpg_ctx();
     if (!c) return MPG_E_NOMEM;
     c->device = device;
@@ -734,7 +739,7 @@ int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host};
     ctx->n_calls++;
     return run_dev_waves(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, n, d_out, d_ops,
-                         ctx->tb_budget, ctx->timing ? &tm : nullptr);
+                         ctx->tb_budget, ctx->timing ? &tm : nullptr, g_num_cu);
 }
 
 }  // extern "C"
@@ -743,7 +748,7 @@ namespace {
 
 // Synchronous host-memory batch on a given stream/workspace; fills out[].
 int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pair* pairs,
-               int32_t n, mpg_result* out, uint64_t tb_budget, Timer* tm) {
+               int32_t n, mpg_result* out, uint64_t tb_budget, Timer* tm, int ncu) {
     std::vector<mpg_seg> segs(n);
     int64_t pbytes = 0, dbytes = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -778,7 +783,7 @@ int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pai
             hipSuccess)
         return MPG_E_DEVICE;
     rc = run_dev_waves(st, ws, p, d_seq, d_seq + pbytes, segs.data(), n,
-                       (mpg_dev_result*)ws.out.p, (char*)ws.ops.p, tb_budget, tm);
+                       (mpg_dev_result*)ws.out.p, (char*)ws.ops.p, tb_budget, tm, ncu);
     if (rc != MPG_OK) return rc;
     if (hipMemcpyAsync(ws.hout.p, ws.out.p, sizeof(mpg_dev_result) * (size_t)n,
                        hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -818,12 +823,18 @@ int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pai
 }
 
 // ------------------------------------------------------------------ serving
-// One scheduler thread admits pending jobs into micro-batches while a slot
-// (stream + workspace) and traceback budget are free; up to nslots batches
-// are on the device at once, so arrivals overlap running work.
+// One scheduler thread admits pending jobs into batches while a slot (stream
+// + workspace) and traceback budget are free.  Jobs are queued by class
+// (short/long x score-only/traceback); every batch holds one class, so it is
+// a single DP launch.  Short jobs go to small micro-batches on the short
+// slots; long jobs (whose serial strip pipeline runs for tens of ms) are
+// gathered into batches of their own on the long slots, so short results
+// never wait behind a long pair.  Batches on different slots overlap on the
+// device, and jobs that arrive meanwhile join the next batch of their class.
 void scheduler(mpg_ctx* c) {
     hipSetDevice(c->device);
-    const int ns = std::max(1, c->nslots);
+    const int nsh = std::max(1, c->nshort);
+    const int ns = nsh + std::max(1, c->nlong);
     std::vector<hipStream_t> streams(ns);
     std::vector<Workspace> wss(ns);
     std::vector<bool> busy(ns, false);
@@ -831,31 +842,46 @@ void scheduler(mpg_ctx* c) {
     for (int k = 0; k < ns; ++k) hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking);
     std::unique_lock<std::mutex> lk(c->mu);
     for (;;) {
-        // admit
-        int slot = -1;
-        for (int k = 0; k < ns; ++k)
-            if (!busy[k]) { slot = k; break; }
-        if (c->stop && c->pending.empty()) {
-            bool any = false;
-            for (int k = 0; k < ns; ++k) any |= busy[k];
-            if (!any) break;
+        bool any_busy = false;
+        for (int k = 0; k < ns; ++k) any_busy |= busy[k];
+        if (c->stop && c->npending == 0 && !any_busy) break;
+        int slot = -1, cls = -1;
+        for (int k = 0; k < ns && cls < 0; ++k) {
+            if (busy[k]) continue;
+            const int lane = k < nsh ? 0 : 2;
+            // the class of this lane whose oldest job arrived first
+            int best = -1;
+            for (int q = lane; q < lane + 2; ++q)
+                if (!c->pending[q].empty() &&
+                    (best < 0 || c->pending[q].front().t_arrive < c->pending[best].front().t_arrive))
+                    best = q;
+            if (best >= 0) {
+                slot = k;
+                cls = best;
+            }
         }
-        if (slot < 0 || c->pending.empty()) {
+        if (cls < 0) {
             c->cv_work.wait_for(lk, std::chrono::milliseconds(20));
             continue;
         }
+        std::deque<mpg_ctx::Job>& Q = c->pending[cls];
+        const int64_t cap_cells = cls >= 2 ? c->long_cells : c->short_cells;
         std::vector<mpg_ctx::Job> batch;
         int64_t cells = 0, tb = 0;
-        while (!c->pending.empty() && (int)batch.size() < c->max_jobs_per_batch) {
-            mpg_ctx::Job& j = c->pending.front();
-            if (!batch.empty() && cells + j.cells > c->slot_cells) break;
-            if (c->tb_in_use + tb + (uint64_t)j.tb_bytes > c->tb_budget) break;
+        while (!Q.empty() && (int)batch.size() < c->max_jobs_per_batch) {
+            mpg_ctx::Job& j = Q.front();
+            if (!batch.empty() && cells + j.cells > cap_cells) break;
+            // long batches leave a reserve of the budget to short jobs
+            const uint64_t limit = cls >= 2 ? c->tb_budget - c->tb_budget / 8 : c->tb_budget;
+            if (c->tb_in_use + tb + (uint64_t)j.tb_bytes > limit) break;
             cells += j.cells;
             tb += j.tb_bytes;
             batch.push_back(std::move(j));
-            c->pending.pop_front();
+            Q.pop_front();
         }
+        c->npending -= batch.size();
         if (batch.empty()) {
+            // traceback budget exhausted: wait for a batch to finish
             c->cv_work.wait_for(lk, std::chrono::milliseconds(5));
             continue;
         }
@@ -864,11 +890,14 @@ void scheduler(mpg_ctx* c) {
         c->stats.tb_bytes_in_use = c->tb_in_use;
         c->stats.tb_bytes_peak = std::max<uint64_t>(c->stats.tb_bytes_peak, c->tb_in_use);
         c->stats.in_flight += batch.size();
-        c->stats.queue_depth = c->pending.size();
+        c->stats.queue_depth = c->npending;
         c->stats.batches += 1;
         if (workers[slot].joinable()) workers[slot].join();
         mpg_params params = c->sparams;
-        workers[slot] = std::thread([c, slot, tb, params, &streams, &wss, &busy,
+        // a long batch's persistent grid is held to a share of the device, so
+        // short micro-batches always find free wavefront slots
+        const int ncu = cls >= 2 ? std::max(1, (int)(g_num_cu * c->long_share)) : g_num_cu;
+        workers[slot] = std::thread([c, slot, tb, ncu, params, &streams, &wss, &busy,
                                      b = std::move(batch)]() mutable {
             hipSetDevice(c->device);
             std::vector<mpg_pair> pairs(b.size());
@@ -882,7 +911,7 @@ void scheduler(mpg_ctx* c) {
             std::vector<mpg_result> res(b.size());
             params.flags &= ~(uint32_t)MPG_WANT_TB;
             int rc = align_host(streams[slot], wss[slot], &params, pairs.data(),
-                                (int32_t)pairs.size(), res.data(), (uint64_t)tb + 1, nullptr);
+                                (int32_t)pairs.size(), res.data(), (uint64_t)tb + 1, nullptr, ncu);
             const int64_t t = now_ns();
             std::lock_guard<std::mutex> g(c->mu);
             for (size_t k = 0; k < b.size(); ++k) {
@@ -929,7 +958,7 @@ int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, in
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host};
     ctx->n_calls++;
     return align_host(ctx->stream, ctx->ws, p, pairs, n, out, ctx->tb_budget,
-                      ctx->timing ? &tm : nullptr);
+                      ctx->timing ? &tm : nullptr, g_num_cu);
 }
 
 int mpg_submit(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pair, uint64_t* job_id) {
@@ -948,12 +977,16 @@ int mpg_submit(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pair, uint64_t
     }
     const bool tb = ((pair->flags | p->flags) & MPG_WANT_TB) != 0;
     const int64_t tbb = tb ? tb_bytes_of(pair->dlen, pair->plen, choose_K(pair->plen, Overrides())) : 0;
-    if (pair->dlen > MPG_MAX_DNA || pair->plen > MPG_MAX_PROT || (uint64_t)tbb > ctx->tb_budget ||
+    const int64_t cells = (int64_t)(pair->dlen + 64) * (pair->plen + 1);
+    // a long job must fit the part of the budget long batches may use
+    const uint64_t tb_limit = cells > mpg_ctx::kLongCells ? ctx->tb_budget - ctx->tb_budget / 8
+                                                          : ctx->tb_budget;
+    if (pair->dlen > MPG_MAX_DNA || pair->plen > MPG_MAX_PROT || (uint64_t)tbb > tb_limit ||
         !score_bound_ok(p, pair->dlen, pair->plen)) {
         ctx->stats.rejected_range++;
         return MPG_E_RANGE;
     }
-    if (ctx->pending.size() >= ctx->max_pending) {
+    if (ctx->npending >= ctx->max_pending) {
         ctx->stats.rejected_again++;
         return MPG_E_AGAIN;
     }
@@ -964,11 +997,13 @@ int mpg_submit(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pair, uint64_t
     j.flags = tb ? (uint32_t)MPG_WANT_TB : 0u;
     j.t_arrive = now_ns();
     j.tb_bytes = tbb;
-    j.cells = (int64_t)(pair->dlen + 64) * (pair->plen + 1);
+    j.cells = cells;
     *job_id = j.id;
-    ctx->pending.push_back(std::move(j));
+    const int cls = (j.cells > mpg_ctx::kLongCells ? 2 : 0) + (tb ? 1 : 0);
+    ctx->pending[cls].push_back(std::move(j));
+    ctx->npending++;
     ctx->stats.submitted++;
-    ctx->stats.queue_depth = ctx->pending.size();
+    ctx->stats.queue_depth = ctx->npending;
     if (!ctx->sched_running) {
         ctx->stop = false;
         ctx->sched = std::thread(scheduler, ctx);
@@ -999,8 +1034,9 @@ int mpg_poll(mpg_ctx* ctx, mpg_result* out, int32_t max_results, int32_t timeout
 int mpg_cancel(mpg_ctx* ctx, uint64_t job_id) {
     if (!ctx) return MPG_E_INVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    for (auto it = ctx->pending.begin(); it != ctx->pending.end(); ++it) {
-        if (it->id == job_id) {
+    for (auto& Q : ctx->pending) {
+        for (auto it = Q.begin(); it != Q.end(); ++it) {
+            if (it->id != job_id) continue;
             mpg_result r;
             std::memset(&r, 0, sizeof(r));
             r.status = MPG_E_CANCELLED;
@@ -1008,10 +1044,11 @@ int mpg_cancel(mpg_ctx* ctx, uint64_t job_id) {
             r.job_id = job_id;
             r.t_arrive_ns = it->t_arrive;
             r.t_done_ns = now_ns();
-            ctx->pending.erase(it);
+            Q.erase(it);
+            ctx->npending--;
             ctx->done.push_back(r);
             ctx->stats.cancelled++;
-            ctx->stats.queue_depth = ctx->pending.size();
+            ctx->stats.queue_depth = ctx->npending;
             ctx->cv_done.notify_all();
             return MPG_OK;
         }
