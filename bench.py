@@ -58,6 +58,10 @@ def build_workload(config: str):
         pairs = W.batch_pairs(10000, seed=2)
         tb = False
         desc = "planted-gene batch: 10,000 pairs, score-only, LOCAL"
+    elif config == "batch16":
+        pairs = W.batch_pairs(10000, seed=2)
+        tb = False
+        desc = "planted-gene batch: 10,000 pairs, score-only, LOCAL, int16 lanes"
     elif config == "traceback":
         pairs = W.batch_pairs(10000, seed=2)
         tb = True
@@ -366,7 +370,8 @@ def main():
     ctx = mpg.Context(0)
     stream = torch.cuda.Stream(device=dev)
     ctx.set_stream(stream.cuda_stream)
-    p = mpg.params()
+    i16 = args.config == "batch16"
+    p = mpg.params(flags=mpg.MPG_ALLOW_I16) if i16 else mpg.params()
 
     def step():
         ctx.align_batch_dev(p, d_prot.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
@@ -395,8 +400,20 @@ def main():
     ms_step = dt * 1e3 / args.steps
     gcups = cells / (dt / args.steps) / 1e9
     dp_ms = tim["dp_ms"] / max(1, args.steps)
-    achieved = cells * OPS_PER_CELL["traceback" if tb else "score"] / (dp_ms * 1e-3) / 1e12
-    peak = PEAK_INT_OPS / 1e12
+    if i16:
+        # 27 packed int16 operations advance two cells: 27 int16 lane-ops per
+        # cell against twice the int32 lane rate
+        ops = 27
+        peak = 2 * PEAK_INT_OPS / 1e12
+        runit = "Tops/s (int16 lane-ops)"
+        if tim["i16_pairs"] != len(pairs) * args.steps:
+            raise SystemExit("int16 kernel ran %d pairs, expected %d" % (
+                tim["i16_pairs"], len(pairs) * args.steps))
+    else:
+        ops = OPS_PER_CELL["traceback" if tb else "score"]
+        peak = PEAK_INT_OPS / 1e12
+        runit = "Tops/s (int32 lane-ops)"
+    achieved = cells * ops / (dp_ms * 1e-3) / 1e12
     kernel_gcups = cells / (dp_ms * 1e-3) / 1e9
     log("step %.3f ms, GCUPS %.1f; DP kernels %.3f ms/step (%.1f GCUPS), prepass %.3f ms, "
         "walk %.3f ms, host %.3f ms" % (ms_step, gcups, dp_ms, kernel_gcups,
@@ -412,14 +429,15 @@ def main():
     line = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int16" if i16 else "int32",
         "data": "synthetic (seeded planted genes)",
         "config": {"workload": desc, "pairs": len(pairs), "cells": cells,
                    "traceback": tb, "mode": "LOCAL"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                     "unit": "Tops/s (int32 lane-ops)", "frac": round(achieved / peak, 4),
+                     "unit": runit, "frac": round(achieved / peak, 4),
                      "traffic": recorded_traffic(args.config), "kernel_gcups": round(kernel_gcups, 2),
-                     "ops_per_cell": OPS_PER_CELL["traceback" if tb else "score"],
+                     "ops_per_cell": ops,
                      "dp_ms_per_step": round(dp_ms, 3)},
         "cpu_baseline": cpu,
     }

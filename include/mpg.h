@@ -210,9 +210,11 @@ int mpg_sync(mpg_ctx *ctx);
  *
  * Scheduling: short and long jobs, with and without traceback, wait in four
  * queues.  Short jobs run in micro-batches (about 2e8 cells) on two streams;
- * long jobs are gathered into batches of their own on two more streams, each
- * held to about a third of the device, so short results never wait behind a
- * long pair.  Results appear in mpg_poll as their batch completes.
+ * long jobs are gathered into batches of their own on a third stream, so a
+ * short job never shares a launch with a long pair.  Within a batch every
+ * pair completes on its own: the wavefront that finishes a pair's last strip
+ * walks its traceback and publishes the result to host-mapped memory, and
+ * the result is in mpg_poll at once, while the rest of the batch still runs.
  */
 int mpg_submit(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pair, uint64_t *job_id);
 
@@ -246,6 +248,7 @@ typedef struct {
     uint64_t dp_spans; /* number of timed DP spans (one per batch wave) */
     uint64_t calls;    /* batch calls since the last reset */
     double host_ms;    /* host wall time planning and enqueuing the device work */
+    uint64_t i16_pairs; /* pairs that ran in the lane-packed int16 kernel */
 } mpg_timing;
 
 /* Turn event timing of batch calls on (1) or off (0). */

@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpg.so")
-SOURCES = ["mpg_dp_k1.hip", "mpg_dp_k2.hip", "mpg_dp_k4.hip", "mpg_kernels.hip", "mpg_lib.cpp"]
+SOURCES = ["mpg_dp_k1.hip", "mpg_dp_k2.hip", "mpg_dp_k4.hip", "mpg_dp16.hip", "mpg_kernels.hip",
+           "mpg_lib.cpp"]
 ARCH = os.environ.get("MPG_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.
@@ -25,10 +26,13 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, extra=None) -> str:
-    """Compile every source into one shared library (always recompiles)."""
+def build(verbose: bool = False, extra=None, out: str | None = None) -> str:
+    """Compile every source into one shared library (always recompiles).
+    ``extra``: more compiler flags (e.g. -D tuning macros); ``out``: write the
+    library there instead of the in-tree libmpg.so (variant builds)."""
     objs, procs = [], []
-    build_dir = os.path.join(HERE, "_build")
+    lib = out or LIB
+    build_dir = os.path.join(HERE, "_build") if out is None else out + ".objs"
     os.makedirs(build_dir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(build_dir, src + ".o")
@@ -44,14 +48,14 @@ def build(verbose: bool = False, extra=None) -> str:
     for src, pr in procs:
         if pr.wait() != 0:
             raise RuntimeError("compiling %s failed" % src)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
         "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

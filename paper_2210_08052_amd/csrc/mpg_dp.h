@@ -5,14 +5,18 @@
 #include <climits>
 
 #include "mpg_internal.h"
+#include "mpg_walk.h"
 
 // Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  The
 // score-only kernels with K <= 2 fit three waves per SIMD (168 VGPRs) with
 // spills only outside the step loop; K = 4 and the traceback kernels would
 // spill inside it, so they keep their registers.
+#ifndef MPG_TB_WAVES
+#define MPG_TB_WAVES 1
+#endif
 template <int K, bool TB>
 struct WavesPerEu {
-    static constexpr int value = (!TB && K <= 2) ? 3 : 1;
+    static constexpr int value = K > 2 ? 1 : (TB ? MPG_TB_WAVES : 3);
 };
 
 namespace mpg {
@@ -103,8 +107,17 @@ struct Sentinel {
     static constexpr int UNREACH = MODE == MPG_LOCAL ? NEG / 2 : -(1 << 29);
 };
 
-extern "C" __device__ int mpg_writelane_i32(int val, int lane, int old) __asm(
-    "llvm.amdgcn.writelane.i32");
+// acc = 2*acc + (ext >= open) in every lane: the compare is a wave ballot
+// (one v_cmp into a scalar mask, placed by the compiler), the shift-in one
+// add-with-carry that reads the mask.  Collects a lane's extension decisions,
+// one bit per step, most recent step in bit 0.
+__device__ __forceinline__ uint32_t push_ge(uint32_t acc, int ext, int open) {
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(ext >= open);
+    uint32_t r;
+    unsigned long long co;
+    asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=&s"(co) : "v"(acc), "s"(m));
+    return r;
+}
 
 // Per-pair state shared by the waves that work on the pair's strips.
 struct PairState {
@@ -134,6 +147,32 @@ __device__ __forceinline__ void st_dev2(int2* p, int2 v) {
     __hip_atomic_store((unsigned long long*)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// s_waitcnt encoding (gfx9 family): vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8.  vmcnt(1) with the other counters left free: every
+// vector memory operation but the most recent one has completed (they retire
+// in issue order).
+constexpr int kWaitVm1 = 0x0F71;
+
+// Write a result record, its status last (after a system-scope fence when the
+// record lives in host memory that the host polls).
+__device__ __forceinline__ void publish(mpg_dev_result* rec, const mpg_dev_result& R, int system) {
+    rec->score = R.score;
+    rec->g_beg = R.g_beg;
+    rec->g_end = R.g_end;
+    rec->p_beg = R.p_beg;
+    rec->p_end = R.p_end;
+    rec->ops_off = R.ops_off;
+    rec->ops_len = R.ops_len;
+    rec->_pad = 0;
+    if (system) {
+        __threadfence_system();
+        __hip_atomic_store(&rec->status, R.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+        __threadfence();
+        rec->status = R.status;
+    }
+}
+
 // Bounded wait until the left strip has published `target` chunks.  Gives up
 // after about 2^18 polls (well under a second) so no wave can spin forever;
 // the pair then reports MPG_E_DEVICE.
@@ -160,8 +199,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<K, TB>::value)))
 dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int nitems,
           int* __restrict__ qhead, PairState* __restrict__ pst, int* __restrict__ prog_g,
           const uint8_t* __restrict__ prot, const uint8_t* __restrict__ desc,
-          int2* __restrict__ bnd, uint8_t* __restrict__ tbbuf,
-          mpg_dev_result* __restrict__ out, DevParams P) {
+          int2* __restrict__ bnd, uint8_t* __restrict__ tbbuf, DpSink sink, DevParams P) {
     using LY = LdsLayout<K, TB>;
     constexpr int NEG = Sentinel<MODE, TB>::NEG;
     constexpr int UNREACH = Sentinel<MODE, TB>::UNREACH;
@@ -226,7 +264,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         int h1[K], h2[K], h3[K], d1[K], d2[K], d3[K], a1[K], b1[K], c1[K];
         int zl[K], best[K], bstep[K], bk[K], bkt[K], hn[K];
         uint32_t nacc[K];
-        int xlo[5][K], xhi[5][K];
+        uint32_t xacc[5][K];  // extension decisions of the last steps, per lane
 #pragma unroll
         for (int c = 0; c < K; ++c) {
             h1[c] = h2[c] = h3[c] = NEG;
@@ -240,7 +278,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
             hn[c] = NEG;
             nacc[c] = 0;
 #pragma unroll
-            for (int x = 0; x < 5; ++x) xlo[x][c] = xhi[x][c] = 0;
+            for (int x = 0; x < 5; ++x) xacc[x][c] = 0;
         }
         int hl1 = NEG, hl2 = NEG, hl3 = NEG;
         int Hout = NEG, Iout = NEG;
@@ -263,11 +301,15 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         }
         int2 nb = make_int2(NEG, NEG);
         // the left strip's last column arrives from HBM as that strip
-        // publishes it; rows of chunk c need its chunks c and c+1
+        // publishes it; rows of chunk c need its chunks c and c+1.  Its
+        // progress counter is read one chunk ahead, so the check at a chunk
+        // start normally finds the value loaded long before and never waits.
         const bool from_left = strip > 0;
+        int seen = 0;
         if (from_left) {
             if (!wait_prog(&prog[strip - 1], nchunks < 2 ? nchunks : 2)) failed = true;
             nb = ld_dev2(&bnd_g[kBndLo + lane]);
+            seen = ld_dev(&prog[strip - 1]);
         }
 
         for (int ch = 0; ch < nchunks && !failed; ++ch) {
@@ -278,11 +320,14 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 if (from_left) {
                     inb[lane] = beyond ? make_int2(NEG, NEG) : nb;
                     if (ch + 1 < nchunks) {
-                        if (!wait_prog(&prog[strip - 1], ch + 3 < nchunks ? ch + 3 : nchunks)) {
+                        const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
+                        if (__builtin_amdgcn_readfirstlane(seen) < need &&
+                            !wait_prog(&prog[strip - 1], need)) {
                             failed = true;
                             break;
                         }
                         nb = ld_dev2(&bnd_g[kBndLo + (ch + 1) * 64 + lane]);
+                        seen = ld_dev(&prog[strip - 1]);
                     }
                 }
                 if (ch > 0) {
@@ -374,42 +419,32 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                             Hn[c] = H; In[c] = I; Dn[c] = D;
                         } else {
                             const int oD = h3[c] - cqD, xD = d3[c] - ce;
-                            const uint64_t mD = __builtin_amdgcn_ballot_w64(xD >= oD);
+                            xacc[1][c] = push_ge(xacc[1][c], xD, oD);
                             const int D = imax(oD, xD);
                             int Hk = D;
                             if (!NOI) {
                                 const int oA = h1[c] - ds0.z;
-                                const uint64_t mA = __builtin_amdgcn_ballot_w64(a1[c] >= oA);
+                                xacc[2][c] = push_ge(xacc[2][c], a1[c], oA);
                                 const int A = imax(oA, a1[c]);
                                 const int oB = L1 - ds0.w;
-                                const uint64_t mB = __builtin_amdgcn_ballot_w64(b1[c] >= oB);
+                                xacc[3][c] = push_ge(xacc[3][c], b1[c], oB);
                                 const int B = imax(oB, b1[c]);
                                 const int oC = L1 - ds1.x;
-                                const uint64_t mC = __builtin_amdgcn_ballot_w64(c1[c] >= oC);
+                                xacc[4][c] = push_ge(xacc[4][c], c1[c], oC);
                                 const int C = imax(oC, c1[c]);
                                 Hk = imax3(Hk, A - ds1.y, B - ds1.z);
                                 Hk = imax(Hk, C - ds1.w);
                                 An[c] = A; Bn[c] = B; Cn[c] = C;
-                                xlo[2][c] = mpg_writelane_i32((int)(uint32_t)mA, t, xlo[2][c]);
-                                xhi[2][c] = mpg_writelane_i32((int)(uint32_t)(mA >> 32), t, xhi[2][c]);
-                                xlo[3][c] = mpg_writelane_i32((int)(uint32_t)mB, t, xlo[3][c]);
-                                xhi[3][c] = mpg_writelane_i32((int)(uint32_t)(mB >> 32), t, xhi[3][c]);
-                                xlo[4][c] = mpg_writelane_i32((int)(uint32_t)mC, t, xlo[4][c]);
-                                xhi[4][c] = mpg_writelane_i32((int)(uint32_t)(mC >> 32), t, xhi[4][c]);
                             }
                             if (!NOF) {
                                 Hk = imax3(Hk, L1 - (cf - 11), L2 - (cf - 10));
                                 Hk = imax3(Hk, h1[c] - (cf - 9), h2[c] - (cf - 8));
                             }
                             const int oI = L0 - cq, xI = IL - ce;
-                            const uint64_t mI = __builtin_amdgcn_ballot_w64(xI >= oI);
+                            xacc[0][c] = push_ge(xacc[0][c], xI, oI);
                             const int I = imax(oI, xI);
                             Hk = imax3(Hk, z, L3 + csc[c]);
                             Hk = imax(Hk, I);
-                            xlo[0][c] = mpg_writelane_i32((int)(uint32_t)mI, t, xlo[0][c]);
-                            xhi[0][c] = mpg_writelane_i32((int)(uint32_t)(mI >> 32), t, xhi[0][c]);
-                            xlo[1][c] = mpg_writelane_i32((int)(uint32_t)mD, t, xlo[1][c]);
-                            xhi[1][c] = mpg_writelane_i32((int)(uint32_t)(mD >> 32), t, xhi[1][c]);
                             nacc[c] = __builtin_amdgcn_alignbit(Hk, nacc[c], 4);
                             Hn[c] = Hk & ~15;
                             In[c] = I; Dn[c] = D;
@@ -436,6 +471,19 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
 #pragma unroll
                         for (int c = 0; c < K; ++c)
                             *(uint32_t*)(tbblk + (((t >> 3) * K + c) * 64 + lane) * 4) = nacc[c];
+                    }
+                    if (TB && (t & 31) == 31) {
+                        // each lane's extension bits of the last 32 steps, bit
+                        // 31 - (t & 31) for step t
+#pragma unroll
+                        for (int x = 0; x < 5; ++x) {
+                            if (NOI && x >= 2) continue;
+#pragma unroll
+                            for (int c = 0; c < K; ++c)
+                                *(uint32_t*)(tbblk + 2048 * K +
+                                             (((x * K + c) * 2 + (t >> 5)) * 64 + lane) * 4) =
+                                    xacc[x][c];
+                        }
                     }
                     // shift histories
                     hl3 = hl2; hl2 = hl1; hl1 = hl0;
@@ -469,25 +517,23 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         bk[c] = INT_MIN;
                     }
                 }
-                if (TB) {
-#pragma unroll
-                    for (int x = 0; x < 5; ++x) {
-                        if (NOI && x >= 2) continue;
-#pragma unroll
-                        for (int c = 0; c < K; ++c)
-                            *(uint2*)(tbblk + 2048 * K + ((x * K + c) * 64 + lane) * 8) =
-                                make_uint2((uint32_t)xlo[x][c], (uint32_t)xhi[x][c]);
-                    }
-                }
-                // publish the strip's last column for rows ch*64-63+lane
+                // publish the strip's last column for rows ch*64-63+lane.  The
+                // counter lags one chunk: once every memory operation but this
+                // store has completed, the previous chunk's rows are at the
+                // coherence point, so chunks 0..ch-1 are announced without
+                // waiting for the store just issued.
                 if (has_next) {
                     const int orow = ch * 64 - 63 + lane;
                     st_dev2(&bnd_g[kBndLo + orow], outb[lane]);
-                    __builtin_amdgcn_s_waitcnt(0);  // rows reach the coherence point first
-                    if (lane == 0) st_dev(&prog[strip], ch + 1);
+                    __builtin_amdgcn_s_waitcnt(kWaitVm1);
+                    if (lane == 0 && ch > 0) st_dev(&prog[strip], ch);
                 }
             }
         }  // chunks
+        if (has_next && !failed) {
+            __builtin_amdgcn_s_waitcnt(0);  // the last chunk's rows, then the count
+            if (lane == 0) st_dev(&prog[strip], nchunks);
+        }
         if (failed) {
             // let the strips to the right drain quickly; the pair reports an error
             if (lane == 0) {
@@ -520,43 +566,75 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
             }
         }
         __builtin_amdgcn_s_waitcnt(0);
-        // the wave that finishes the pair's last strip writes the result
-        if (lane == 0) {
-            const int done = atomicAdd(&ps->done, 1);
-            if (done == nstrips - 1) {
-                mpg_dev_result R;
-                R.g_beg = -1;
-                R.p_beg = -1;
-                R.ops_off = J.ops_off;
-                R.ops_len = 0;
-                R._pad = 0;
-                const int gv = atomicAdd(&ps->gsc, 0);
-                const unsigned long long k = atomicAdd(&ps->key, 0ull);
-                if (atomicAdd(&ps->bad, 0)) {
-                    R.status = MPG_E_DEVICE;
+        // the wave that finishes the pair's last strip writes the result; the
+        // count is acquire-release, so that wave sees every other strip's end
+        // key and direction bits
+        int done = 0;
+        if (lane == 0)
+            done = __hip_atomic_fetch_add(&ps->done, 1, __ATOMIC_ACQ_REL,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        done = __builtin_amdgcn_readfirstlane(done);
+        if (done == nstrips - 1) {
+            const unsigned long long k = __hip_atomic_load(&ps->key, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            const int gv = __builtin_amdgcn_readfirstlane(ld_dev(&ps->gsc));
+            const int bad = __builtin_amdgcn_readfirstlane(ld_dev(&ps->bad));
+            mpg_dev_result R;
+            R.g_beg = -1;
+            R.p_beg = -1;
+            R.ops_off = J.ops_off;
+            R.ops_len = 0;
+            R._pad = 0;
+            if (bad) {
+                R.status = MPG_E_DEVICE;
+                R.score = 0;
+                R.g_end = -1;
+                R.p_end = -1;
+            } else if (MODE == MPG_GLOBAL) {
+                if (gv < UNREACH) {
+                    R.status = MPG_E_NOALN;
                     R.score = 0;
                     R.g_end = -1;
                     R.p_end = -1;
-                } else if (MODE == MPG_GLOBAL) {
-                    if (gv < UNREACH) {
-                        R.status = MPG_E_NOALN;
-                        R.score = 0;
-                        R.g_end = -1;
-                        R.p_end = -1;
-                    } else {
-                        R.status = MPG_OK;
-                        R.score = TB ? (gv >> 4) : gv;
-                        R.g_end = n;
-                        R.p_end = m;
-                    }
                 } else {
                     R.status = MPG_OK;
-                    R.score = (int)(k >> 36) - (1 << 27);
-                    R.g_end = (1 << 21) - 1 - (int)((k >> 15) & ((1u << 21) - 1));
-                    R.p_end = (1 << 15) - 1 - (int)(k & ((1u << 15) - 1));
+                    R.score = TB ? (gv >> 4) : gv;
+                    R.g_end = n;
+                    R.p_end = m;
                 }
-                out[J.res] = R;
+            } else {
+                const uint32_t khi = __builtin_amdgcn_readfirstlane((uint32_t)(k >> 32));
+                const uint32_t klo = __builtin_amdgcn_readfirstlane((uint32_t)k);
+                const unsigned long long ku = ((unsigned long long)khi << 32) | klo;
+                R.status = MPG_OK;
+                R.score = (int)(ku >> 36) - (1 << 27);
+                R.g_end = (1 << 21) - 1 - (int)((ku >> 15) & ((1u << 21) - 1));
+                R.p_end = (1 << 15) - 1 - (int)(ku & ((1u << 15) - 1));
             }
+            if (TB && sink.walk) {
+                // walk the traceback now: the pair completes without a second kernel
+                char* txt = sink.ops + J.ops_off;
+                if (R.status == MPG_OK) {
+                    const TbView V{tbbuf + J.tb_off, J.K, J.nchunks};
+                    const int64_t end = 2LL * (n + m);
+                    OpWriter W{txt, end};
+                    int bi = -1, bj = -1;
+                    const bool ok = walk_wave(V, R.g_end, R.p_end, n, m, W, lane, bi, bj);
+                    if (!ok || W.overflow) {
+                        R.status = MPG_E_DEVICE;
+                        if (lane == 0) txt[0] = 0;
+                    } else {
+                        if (lane == 0) txt[end] = 0;
+                        R.g_beg = bi;
+                        R.p_beg = bj;
+                        R.ops_off = J.ops_off + W.pos;
+                        R.ops_len = (int32_t)(end - W.pos);
+                    }
+                } else if (lane == 0) {
+                    txt[0] = 0;
+                }
+            }
+            if (lane == 0) publish(sink.out + J.res, R, sink.system);
         }
     }  // queue
 }
@@ -565,7 +643,7 @@ template <int K, int MODE, bool TB>
 hipError_t launch_dp_t(hipStream_t s, int ncu, const DevParams& P, const PairJob* jobs,
                        const int2* items, int nitems, int* qhead, PairState* pst, int* prog,
                        const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
-                       mpg_dev_result* out) {
+                       const DpSink& sink) {
     const bool noi = (P.flags & MPG_NO_INTRON) != 0;
     const bool nof = (P.flags & MPG_NO_FRAMESHIFT) != 0;
     const size_t lds = (size_t)LdsLayout<K, TB>::WAVE;
@@ -582,7 +660,7 @@ hipError_t launch_dp_t(hipStream_t s, int ncu, const DevParams& P, const PairJob
         const int waves = per_cu > 0 ? per_cu * ncu : 8 * ncu;                                \
         dim3 g(nitems < waves ? nitems : waves);                                                \
         hipLaunchKernelGGL((dp_kernel<K, MODE, TB, NI, NF>), g, b, lds, s, jobs, items,        \
-                           nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out, P);           \
+                           nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink, P);          \
     } while (0)
     if (!noi && !nof) MPG_LAUNCH(false, false);
     else if (noi && !nof) MPG_LAUNCH(true, false);
@@ -596,12 +674,12 @@ template <int K>
 hipError_t launch_dp_k(hipStream_t s, int ncu, bool tb, const DevParams& P, const PairJob* jobs,
                        const int2* items, int nitems, int* qhead, PairState* pst, int* prog,
                        const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
-                       mpg_dev_result* out) {
+                       const DpSink& sink) {
 #define MPG_MODE(M)                                                                             \
     return tb ? launch_dp_t<K, M, true>(s, ncu, P, jobs, items, nitems, qhead, pst, prog, prot, \
-                                        desc, bnd, tbbuf, out)                                  \
+                                        desc, bnd, tbbuf, sink)                                 \
               : launch_dp_t<K, M, false>(s, ncu, P, jobs, items, nitems, qhead, pst, prog,     \
-                                         prot, desc, bnd, tbbuf, out)
+                                         prot, desc, bnd, tbbuf, sink)
     switch (P.mode) {
         case MPG_LOCAL: MPG_MODE(MPG_LOCAL);
         case MPG_EXTEND: MPG_MODE(MPG_EXTEND);

@@ -23,7 +23,8 @@ constexpr int kDescHi = 64;
 constexpr int kBndLo = 64;
 constexpr int kBndHi = 128;
 // Bytes of traceback storage per 64-step block and per column-in-lane:
-// 8 nibble dwords x 64 lanes (2048 B) + 5 states x 64 steps x 8 B (2560 B).
+// 8 nibble dwords x 64 lanes (2048 B: the H winner of 8 steps per dword) +
+// 5 states x 2 halves x 64 lanes x 4 B (2560 B: one extension bit per step).
 constexpr int kTbBlockBytes = 4608;
 
 // Scoring parameters passed by value to the kernels.
@@ -52,11 +53,44 @@ struct PairJob {
     int32_t K;           // columns per lane
     int32_t status;      // host pre-check status (MPG_OK or MPG_E_RANGE)
     int32_t prog_off;    // index of strip 0's progress counter
+    int32_t i16;         // 1: runs in a packed int16 job (see PackJob)
+};
+
+// Two LOCAL score-only pairs run together by the lane-packed int16 kernel:
+// pair a in the low 16 bits of every lane value, pair b in the high 16 bits
+// (b < 0: the high half idles).  Both follow one schedule of nchunks steps
+// per strip and nstrips strips (the larger of the two pairs').
+struct PackJob {
+    int32_t a, b;        // job indices
+    int32_t n;           // rows: the larger region
+    int32_t nchunks;     // 64-step chunks per strip
+    int32_t nstrips;     // strips of 64*K columns
+    int32_t K;           // columns per lane
+    int32_t prog_off;    // index of strip 0's progress counter
     int32_t _pad;
+    int64_t desc_off;    // byte offset of packed descriptor row -kDescLo (16 B per row)
+    int64_t bnd_off;     // int2 index of boundary row -kBndLo
 };
 
 // Bytes of per-pair shared state of the DP launch (end-cell key, counters).
 constexpr int kPairStateBytes = 24;
+
+// Where the DP kernels leave their results.  A record's status field is
+// written last; with `system` set the fields reach host memory before it
+// (records and op strings may then live in host-mapped memory that the host
+// polls while the kernel runs).  With `walk` set, the wavefront that finishes
+// a traceback pair walks it at once (results complete pair by pair);
+// otherwise the walk kernel runs after the DP.
+struct DpSink {
+    mpg_dev_result* out;  // result records, indexed by PairJob::res
+    char* ops;            // op-string buffer, slots at PairJob::ops_off
+    int32_t walk;
+    int32_t system;
+};
+
+// Status of a record not yet written (records are preset to it when the host
+// polls them); never a value of MPG_OK or an MPG_E_* code.
+constexpr int32_t kPending = 1;
 
 // Kernel launch helpers implemented in mpg_kernels.hip.
 hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row_start,
@@ -71,7 +105,7 @@ hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row
 hipError_t launch_dp(hipStream_t s, int K, bool tb, int ncu, const DevParams& P,
                      const PairJob* jobs, const int2* items, int nitems, int* qhead, void* pst,
                      int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
-                     uint8_t* tbbuf, mpg_dev_result* out);
+                     uint8_t* tbbuf, const DpSink& sink);
 
 // Zero the per-pair state, the strips' progress counters and the queue heads.
 hipError_t launch_init(hipStream_t s, const PairJob* jobs, int npairs, void* pst, int* prog,
@@ -80,9 +114,22 @@ hipError_t launch_init(hipStream_t s, const PairJob* jobs, int npairs, void* pst
 hipError_t launch_walk(hipStream_t s, const PairJob* jobs, const int32_t* order, int count,
                        const uint8_t* tbbuf, mpg_dev_result* out, char* ops);
 
-hipError_t launch_status(hipStream_t s, const PairJob* jobs, int npairs, mpg_dev_result* out);
+hipError_t launch_status(hipStream_t s, const PairJob* jobs, int npairs, const DpSink& sink);
 
 // Dynamic LDS bytes of one DP wavefront.
 int dp_lds_bytes(int K, bool tb);
+
+// Lane-packed int16 path (mpg_dp16.hip): packed row descriptors of every
+// PackJob (rows [-kDescLo, 64*nchunks + kDescHi), pack k's first row at
+// global row row_start[k]; also zeroes the packs' progress counters), and the
+// DP launch over (pack, strip) items.
+hipError_t launch_prepass16(hipStream_t s, const PairJob* jobs, const PackJob* packs,
+                            const int64_t* row_start, int npacks, int64_t total_rows,
+                            const uint8_t* dna, uint8_t* desc, int* prog, const DevParams& P);
+hipError_t launch_dp16(hipStream_t s, int K, int ncu, const DevParams& P, const PairJob* jobs,
+                       const PackJob* packs, const int2* items, int nitems, int* qhead, void* pst,
+                       int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
+                       const DpSink& sink);
+int dp16_lds_bytes(int K);
 
 }  // namespace mpg

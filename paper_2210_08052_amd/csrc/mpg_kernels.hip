@@ -23,7 +23,8 @@
 //  * traceback variant: every value is kept as 16*v + nibble, where the
 //    nibble encodes the H winner (15 - code) so one max3 chain yields the
 //    value and the first-maximum tie-break together; gap/intron extension
-//    choices are wave ballots.  Both go to HBM as coalesced 256-512 B writes;
+//    choices are shifted into a per-lane bit register (compare + add with
+//    carry).  Both go to HBM as coalesced 256 B writes;
 //  * walk: one wavefront per traced pair follows the stored choices back from
 //    the end cell, reading each run of the path in parallel, and writes the
 //    run-length op string.
@@ -98,183 +99,11 @@ __global__ void init_kernel(const PairJob* __restrict__ jobs, int npairs, PairSt
     pst[k].gsc = gsc_init;
     pst[k].bad = 0;
     pst[k].pad = 0;
-    if (J.status != MPG_OK) return;
+    if (J.status != MPG_OK || J.i16) return;
     for (int s = 0; s < J.nstrips; ++s) prog[J.prog_off + s] = 0;
 }
 
 // ------------------------------------------------------------------- walk
-
-struct TbView {
-    const uint8_t* base;
-    int K, nchunks;
-    __device__ __forceinline__ const uint8_t* blk(int i, int j, int& k, int& c, int& t) const {
-        const int SW = 64 * K;
-        const int S = j / SW;
-        const int jj = j - S * SW;
-        k = jj / K;
-        c = jj - k * K;
-        const int s = i + k;
-        t = s & 63;
-        return base + ((int64_t)S * nchunks + (s >> 6)) * (kTbBlockBytes * K);
-    }
-    __device__ __forceinline__ int code(int i, int j) const {
-        int k, c, t;
-        const uint8_t* b = blk(i, j, k, c, t);
-        const uint32_t w = *(const uint32_t*)(b + (((t >> 3) * K + c) * 64 + k) * 4);
-        return 15 - (int)((w >> ((t & 7) * 4)) & 15u);
-    }
-    __device__ __forceinline__ int ext(int x, int i, int j) const {
-        int k, c, t;
-        const uint8_t* b = blk(i, j, k, c, t);
-        const uint2 v = *(const uint2*)(b + 2048 * K + ((x * K + c) * 64 + t) * 8);
-        const uint32_t w = k < 32 ? v.x : v.y;
-        return (int)((w >> (k & 31)) & 1u);
-    }
-};
-
-__device__ __forceinline__ int ndigits(int v) {
-    int d = 1;
-    while (v >= 10) { v /= 10; ++d; }
-    return d;
-}
-
-// Op-string writer: tokens are produced last-to-first and written backwards
-// from the end of the pair's slot; lane 0 stores the bytes.  M, I and D runs
-// are merged into one token, F, G, N, U and V never.
-struct OpWriter {
-    char* txt;
-    int64_t pos;   // first byte written so far
-    char pop = 0;  // pending (not yet written) token
-    int plen = 0;
-    bool overflow = false;
-    __device__ void flush(int lane) {
-        if (!pop) return;
-        const int nd = ndigits(plen);
-        if (pos < nd + 1) {
-            overflow = true;
-            pop = 0;
-            return;
-        }
-        if (lane == 0) {
-            txt[pos - 1] = pop;
-            int v = plen;
-            for (int d = 2; d <= nd + 1; ++d) {
-                txt[pos - d] = (char)('0' + v % 10);
-                v /= 10;
-            }
-        }
-        pos -= nd + 1;
-        pop = 0;
-    }
-    __device__ void emit(char op, int l, bool merge, int lane) {
-        if (merge && pop == op) {
-            plen += l;
-            return;
-        }
-        flush(lane);
-        pop = op;
-        plen = l;
-        if (!merge) flush(lane);
-    }
-};
-
-// Walks one pair back from its end cell, one wavefront per pair.  The
-// choices along the path are read speculatively 64 at a time: in state H the
-// lanes read the H codes down the diagonal (a run of codon:residue steps),
-// in a gap state the extension bits along the gap, and in an intron state
-// the extension bits of 4 consecutive rows each (256 rows per round); a
-// ballot finds where the run ends.  Every round is then one memory round
-// trip for up to 64-256 steps of the path.  Returns the start cell in
-// (bi, bj), or false on an inconsistent path (never expected).
-__device__ bool walk_wave(const TbView& V, int i, int j, int n, int m, OpWriter& W, int lane,
-                          int& bi, int& bj) {
-    int st = 0;  // 0 H, 1 I, 2 D, 3 A, 4 B, 5 C
-    int kend = 0;
-    const int64_t guard = 4LL * (n + m) + 64;
-    for (int64_t it = 0; it < guard; ++it) {
-        if (i < 0 || j < 0 || i > n || j > m) return false;
-        if (st == 0) {
-            const int ii = i - 3 * lane, jj = j - lane;
-            const bool ok = ii >= 0 && jj >= 0;
-            const int hc = ok ? V.code(ii, jj) : -1;
-            const uint64_t stop = __ballot(hc != 1);
-            if (stop == 0) {
-                W.emit('M', 64, true, lane);
-                i -= 192;
-                j -= 64;
-                continue;
-            }
-            const int l = __builtin_ctzll(stop);
-            if (l) W.emit('M', l, true, lane);
-            i -= 3 * l;
-            j -= l;
-            const int c = __builtin_amdgcn_readlane(hc, l);
-            switch (c) {
-                case 0:
-                    W.flush(lane);
-                    bi = i;
-                    bj = j;
-                    return true;
-                case 2: st = 1; break;
-                case 3: st = 2; break;
-                case 4: W.emit('F', 1, false, lane); i -= 1; j -= 1; break;
-                case 5: W.emit('F', 2, false, lane); i -= 2; j -= 1; break;
-                case 6: W.emit('G', 1, false, lane); i -= 1; break;
-                case 7: W.emit('G', 2, false, lane); i -= 2; break;
-                case 8: st = 3; kend = i; break;
-                case 9: st = 4; kend = i; break;
-                case 10: st = 5; kend = i; break;
-                default: return false;
-            }
-        } else if (st <= 2) {
-            // gap run: I moves left along the row, D up by one codon
-            const int ii = st == 1 ? i : i - 3 * lane;
-            const int jj = st == 1 ? j - lane : j;
-            const bool ok = ii >= 0 && jj >= 0;
-            const int bit = ok ? V.ext(st - 1, ii, jj) : 0;
-            const uint64_t endm = __ballot(!ok || !bit);
-            if (endm == 0) {
-                W.emit(st == 1 ? 'I' : 'D', 64, true, lane);
-                if (st == 1) j -= 64; else i -= 192;
-                continue;
-            }
-            const int l = __builtin_ctzll(endm);
-            if (!__builtin_amdgcn_readlane((int)ok, l)) return false;
-            W.emit(st == 1 ? 'I' : 'D', l + 1, true, lane);
-            if (st == 1) j -= l + 1; else i -= 3 * (l + 1);
-            st = 0;
-        } else {
-            // intron run: rows i - (4*lane + r), r = 0..3
-            int first = 4;
-            bool bad = false;
-#pragma unroll
-            for (int r = 3; r >= 0; --r) {
-                const int ii = i - 4 * lane - r;
-                if (ii < 0) {
-                    first = r;
-                    bad = true;
-                } else if (!V.ext(st - 1, ii, j)) {
-                    first = r;
-                    bad = false;
-                }
-            }
-            const uint64_t endm = __ballot(first < 4);
-            if (endm == 0) {
-                i -= 256;
-                continue;
-            }
-            const int l = __builtin_ctzll(endm);
-            if (__builtin_amdgcn_readlane((int)bad, l)) return false;
-            const int f = 4 * l + __builtin_amdgcn_readlane(first, l);
-            const int k = i - f;
-            W.emit(st == 3 ? 'N' : st == 4 ? 'U' : 'V', kend - k + 1, false, lane);
-            if (st != 3) j -= 1;
-            i = k - 1;
-            st = 0;
-        }
-    }
-    return false;
-}
 
 // One wavefront (block) per traced pair.  The op string ends at the last
 // byte but one of the pair's slot (2(n+m)+1 bytes, enough for any path) and
@@ -315,8 +144,7 @@ __global__ void __launch_bounds__(64) walk_kernel(const PairJob* __restrict__ jo
 }
 
 // Records for pairs the host rejected before launch.
-__global__ void status_kernel(const PairJob* __restrict__ jobs, int npairs,
-                              mpg_dev_result* __restrict__ out) {
+__global__ void status_kernel(const PairJob* __restrict__ jobs, int npairs, DpSink sink) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= npairs) return;
     const PairJob J = jobs[k];
@@ -328,20 +156,20 @@ __global__ void status_kernel(const PairJob* __restrict__ jobs, int npairs,
     R.ops_off = J.ops_off;
     R.ops_len = 0;
     R._pad = 0;
-    out[J.res] = R;
+    publish(sink.out + J.res, R, sink.system);
 }
 
 }  // namespace dev
 
 hipError_t launch_dp_k1(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
                         int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
-                        mpg_dev_result*);
+                        const DpSink&);
 hipError_t launch_dp_k2(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
                         int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
-                        mpg_dev_result*);
+                        const DpSink&);
 hipError_t launch_dp_k4(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
                         int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
-                        mpg_dev_result*);
+                        const DpSink&);
 
 int dp_lds_bytes(int K, bool tb) {
     if (K == 1) return tb ? LdsLayout<1, true>::WAVE : LdsLayout<1, false>::WAVE;
@@ -361,12 +189,12 @@ hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row
 hipError_t launch_dp(hipStream_t s, int K, bool tb, int ncu, const DevParams& P,
                      const PairJob* jobs, const int2* items, int nitems, int* qhead, void* pst,
                      int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
-                     uint8_t* tbbuf, mpg_dev_result* out) {
+                     uint8_t* tbbuf, const DpSink& sink) {
     if (nitems <= 0) return hipSuccess;
     switch (K) {
-        case 1: return launch_dp_k1(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
-        case 2: return launch_dp_k2(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
-        case 4: return launch_dp_k4(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, out);
+        case 1: return launch_dp_k1(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink);
+        case 2: return launch_dp_k2(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink);
+        case 4: return launch_dp_k4(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink);
         default: return hipErrorInvalidValue;
     }
 }
@@ -388,9 +216,10 @@ hipError_t launch_walk(hipStream_t s, const PairJob* jobs, const int32_t* order,
     return hipGetLastError();
 }
 
-hipError_t launch_status(hipStream_t s, const PairJob* jobs, int npairs, mpg_dev_result* out) {
+hipError_t launch_status(hipStream_t s, const PairJob* jobs, int npairs, const DpSink& sink) {
     if (npairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(status_kernel, dim3((npairs + 255) / 256), dim3(256), 0, s, jobs, npairs, out);
+    hipLaunchKernelGGL(status_kernel, dim3((npairs + 255) / 256), dim3(256), 0, s, jobs, npairs,
+                       sink);
     return hipGetLastError();
 }
 

@@ -115,9 +115,12 @@ struct DevBuf {
     }
 };
 
-struct HostBuf {  // pinned host staging
+struct HostBuf {  // pinned host memory
     void* p = nullptr;
     size_t cap = 0;
+    // coherent: device writes become visible to the host while a kernel runs
+    // (result records and op strings that the host polls)
+    unsigned flags = hipHostMallocDefault;
     int ensure(size_t bytes) {
         if (bytes <= cap) return MPG_OK;
         if (p) hipHostFree(p);
@@ -125,7 +128,7 @@ struct HostBuf {  // pinned host staging
         cap = 0;
         size_t want = std::max<size_t>(bytes, 4096);
         want = want + want / 4;
-        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc(&p, want, flags) != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
             return MPG_E_NOMEM;
@@ -147,6 +150,7 @@ constexpr int kSideStreams = 8;
 struct Workspace {
     DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops, state;
     HostBuf hplan, hseq, hout, hops;
+    HostBuf prec, pops;  // serving: host-mapped records and op strings the host polls
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork_ev = nullptr, join_ev[kSideStreams] = {};
     bool streams_ready = false;
@@ -166,7 +170,7 @@ struct Workspace {
     void release() {
         DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state};
         for (auto* b : d) b->release();
-        HostBuf* h[] = {&hplan, &hseq, &hout, &hops};
+        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops};
         for (auto* b : h) b->release();
         if (streams_ready) {
             for (int k = 0; k < kSideStreams; ++k) {
@@ -182,10 +186,12 @@ struct Workspace {
 
 // ------------------------------------------------------------------ planning
 // One DP launch: the strips of every pair sharing (K, traceback), as a
-// queue of (job, strip) items, longest pair first, strips in order.
+// queue of (job, strip) items, longest pair first, strips in order.  The
+// int16 group's items are (pack, strip).
 struct Group {
     int K;
     bool tb;
+    bool i16;
     std::vector<int2> items;
 };
 
@@ -194,8 +200,10 @@ struct Plan {
     std::vector<int64_t> row_start;
     std::vector<Group> groups;
     std::vector<int32_t> walk;
+    std::vector<PackJob> packs;
+    std::vector<int64_t> pack_row_start;
     int64_t desc_bytes = 0, bnd_elems = 0, tb_bytes = 0;
-    int64_t total_rows = 0;
+    int64_t total_rows = 0, pack_rows = 0;
     int64_t nprog = 0;
 };
 
@@ -210,9 +218,12 @@ int env_int(const char* name) {
 
 // Debug overrides are read once per call (getenv per pair is too slow).
 struct Overrides {
-    int K = 0;
-    Overrides() : K(env_int("MPG_FORCE_K")) {}
+    int K = 0, K16 = 0;
+    Overrides() : K(env_int("MPG_FORCE_K")), K16(env_int("MPG_FORCE_K16")) {}
 };
+
+// Columns per lane of the int16 kernel.
+int choose_K16(const Overrides& ov) { return ov.K16 == 1 ? 1 : 2; }
 
 int choose_K(int m, const Overrides& ov) {
     (void)m;
@@ -257,6 +268,13 @@ struct BoundInfo {
         if (mode == MPG_LOCAL) return pmax * 4 < lim;
         return (n + m + 4) * pmax < lim;
     }
+    // int16 lanes (LOCAL only): H >= 0 everywhere, so reachable values lie in
+    // [-(the largest penalty sum), the best score]; the best score of a
+    // protein of m residues is at most m times the largest matrix entry.
+    // Both must stay clear of the int16 range with room to spare.
+    bool ok16(int64_t m) const {
+        return mode == MPG_LOCAL && maxpos * m <= 32767 - 256 && pmax <= 8192;
+    }
 };
 
 bool score_bound_ok(const mpg_params* p, int64_t n, int64_t m) { return BoundInfo(p).ok(n, m); }
@@ -278,7 +296,8 @@ void make_dev_params(const mpg_params* p, DevParams* d) {
 // Build the plan for the pairs idx[0..cnt) of a call with n pairs.  Each
 // job writes result record idx[k] and its op string at ops_off[idx[k]].
 void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
-                const std::vector<int64_t>& ops_off, Plan& P, uint64_t tb_budget) {
+                const std::vector<int64_t>& ops_off, Plan& P, uint64_t tb_budget,
+                bool shortest_first) {
     P.jobs.assign(cnt, PairJob{});
     P.row_start.assign(cnt, 0);
     P.groups.clear();
@@ -288,6 +307,9 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     bysize.reserve(cnt);
     const Overrides ov;
     const BoundInfo bound(p);
+    const bool allow16 = (p->flags & MPG_ALLOW_I16) != 0 && p->mode == MPG_LOCAL;
+    const int K16 = choose_K16(ov);
+    std::vector<std::pair<int64_t, int32_t>> e16;
     for (int32_t k = 0; k < cnt; ++k) {
         const mpg_seg& s = segs[idx[k]];
         PairJob& J = P.jobs[k];
@@ -310,7 +332,16 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         if (J.tb && J.status == MPG_OK && (uint64_t)tb_bytes_of(nn, mm, K) > tb_budget)
             J.status = MPG_E_RANGE;
         J.ops_off = ops_off[idx[k]];
+        J.i16 = 0;
         if (J.status != MPG_OK) continue;
+        if (allow16 && !J.tb && bound.ok16(mm)) {
+            J.i16 = 1;
+            J.K = K16;
+            J.nstrips = (mm + 1 + 64 * K16 - 1) / (64 * K16);
+            // pairs are matched by shape: strips first, then chunks
+            e16.push_back({(int64_t)J.nstrips * (1LL << 32) + J.nchunks, k});
+            continue;
+        }
         J.desc_off = P.desc_bytes;
         const int64_t rows = (int64_t)nsteps + kDescLo + kDescHi;
         P.row_start[k] = P.total_rows;
@@ -324,21 +355,65 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         P.nprog += J.nstrips;
         bysize.push_back({(int64_t)J.nstrips * J.nchunks, k});
     }
+    // batches: longest pair first (the last pairs to finish are the short
+    // ones); serving: shortest first (short results are out early)
     std::sort(bysize.begin(), bysize.end(),
-              [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
-                  return a.first > b.first || (a.first == b.first && a.second < b.second);
+              [shortest_first](const std::pair<int64_t, int32_t>& a,
+                               const std::pair<int64_t, int32_t>& b) {
+                  if (a.first != b.first) return shortest_first ? a.first < b.first : a.first > b.first;
+                  return a.second < b.second;
               });
     for (auto& e : bysize) {
         const PairJob& J = P.jobs[e.second];
         Group* g = nullptr;
         for (auto& gg : P.groups)
-            if (gg.K == J.K && gg.tb == (J.tb != 0)) g = &gg;
+            if (gg.K == J.K && gg.tb == (J.tb != 0) && !gg.i16) g = &gg;
         if (!g) {
-            P.groups.push_back(Group{J.K, J.tb != 0, {}});
+            P.groups.push_back(Group{J.K, J.tb != 0, false, {}});
             g = &P.groups.back();
         }
         for (int st = 0; st < J.nstrips; ++st) g->items.push_back(make_int2(e.second, st));
         if (J.tb) P.walk.push_back(e.second);
+    }
+    // int16 pairs: neighbours in size order share a pack
+    if (!e16.empty()) {
+        std::sort(e16.begin(), e16.end(),
+                  [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
+                      return a.first > b.first || (a.first == b.first && a.second < b.second);
+                  });
+        P.groups.push_back(Group{K16, false, true, {}});
+        Group& g = P.groups.back();
+        for (size_t q = 0; q < e16.size(); q += 2) {
+            const PairJob& A = P.jobs[e16[q].second];
+            const bool hasB = q + 1 < e16.size();
+            const PairJob& B = P.jobs[hasB ? e16[q + 1].second : e16[q].second];
+            PackJob X{};
+            X.a = e16[q].second;
+            X.b = hasB ? e16[q + 1].second : -1;
+            X.n = std::max(A.n, hasB ? B.n : 0);
+            X.nchunks = std::max(A.nchunks, hasB ? B.nchunks : 0);
+            X.nstrips = std::max(A.nstrips, hasB ? B.nstrips : 0);
+            X.K = K16;
+            const int64_t nsteps = (int64_t)X.nchunks * 64;
+            X.desc_off = P.desc_bytes;
+            P.pack_row_start.push_back(P.pack_rows);
+            P.pack_rows += nsteps + kDescLo + kDescHi;
+            P.desc_bytes += (nsteps + kDescLo + kDescHi) * 16;
+            X.bnd_off = P.bnd_elems;
+            P.bnd_elems += nsteps + kBndLo + kBndHi;
+            X.prog_off = (int32_t)P.nprog;
+            P.nprog += X.nstrips;
+            P.packs.push_back(X);
+        }
+        // queue order: longest pack first
+        std::vector<int32_t> ord(P.packs.size());
+        for (size_t q = 0; q < ord.size(); ++q) ord[q] = (int32_t)q;
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+            return (int64_t)P.packs[a].nstrips * P.packs[a].nchunks >
+                   (int64_t)P.packs[b].nstrips * P.packs[b].nchunks;
+        });
+        for (int32_t xi : ord)
+            for (int st = 0; st < P.packs[xi].nstrips; ++st) g.items.push_back(make_int2(xi, st));
     }
 }
 
@@ -357,7 +432,7 @@ struct mpg_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pre, ev_dp, ev_walk;
     std::vector<hipEvent_t> ev_pool;
     double t_pre = 0, t_dp = 0, t_walk = 0, t_host = 0;
-    uint64_t n_dp = 0, n_calls = 0;
+    uint64_t n_dp = 0, n_calls = 0, n_i16 = 0;
 
     // ---- serving
     std::mutex mu;
@@ -383,10 +458,10 @@ struct mpg_ctx {
     bool sched_running = false;
     size_t max_pending = 1 << 20;
     // slots 0..nshort-1 run short micro-batches, the rest long batches
-    int nshort = 2, nlong = 2;
+    int nshort = 2, nlong = 1;
     int64_t short_cells = 200000000LL;    // cells per short micro-batch
     int64_t long_cells = 60000000000LL;   // cells per long batch
-    double long_share = 0.35;             // device share of one long batch's grid
+    double long_share = 1.0;              // device share of one long batch's grid
     int max_jobs_per_batch = 4096;
     mpg_stats stats{};
     uint64_t tb_in_use = 0;
@@ -402,6 +477,7 @@ struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>>* ev[3];
     std::vector<hipEvent_t>* pool;
     double* host_ms;  // wall time spent planning and enqueuing on the host
+    uint64_t* i16 = nullptr;  // pairs run in the int16 kernel
     hipEvent_t open[3] = {nullptr, nullptr, nullptr};
     hipEvent_t get() {
         hipEvent_t e = nullptr;
@@ -427,11 +503,24 @@ struct Timer {
     }
 };
 
+// How a call runs on the device.
+struct RunCfg {
+    uint64_t tb_budget = 0;
+    Timer* tm = nullptr;
+    int ncu = 256;      // compute units the DP grid may fill
+    bool serve = false; // results pair by pair: the finishing wavefront walks
+                        // the traceback and publishes the record (status
+                        // last) to memory the host polls; shortest pairs first
+};
+
 // Enqueue the pairs idx[0..cnt) of a call whose letters are on the device.
 int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
             const uint8_t* d_dna, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
             const std::vector<int64_t>& ops_off, mpg_dev_result* d_out, char* d_ops,
-            uint64_t tb_budget, Timer* tm, int ncu) {
+            const RunCfg& cfg) {
+    Timer* tm = cfg.tm;
+    const int ncu = cfg.ncu;
+    const uint64_t tb_budget = cfg.tb_budget;
     const auto th0 = std::chrono::steady_clock::now();
     struct HostClock {
         Timer* tm;
@@ -444,7 +533,7 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
         }
     } host_clock{tm, th0};
     Plan P;
-    plan_pairs(p, segs, idx, cnt, ops_off, P, tb_budget);
+    plan_pairs(p, segs, idx, cnt, ops_off, P, tb_budget, cfg.serve);
     DevParams DP;
     make_dev_params(p, &DP);
     // prepass list: planned pairs only, row_start ascending
@@ -453,10 +542,13 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     pjobs.reserve(cnt);
     pstarts.reserve(cnt);
     for (int32_t k = 0; k < cnt; ++k)
-        if (P.jobs[k].status == MPG_OK) {
+        if (P.jobs[k].status == MPG_OK && !P.jobs[k].i16) {
             pjobs.push_back(P.jobs[k]);
             pstarts.push_back(P.row_start[k]);
         }
+    const size_t npacks = P.packs.size();
+    if (tm && tm->i16)
+        for (const PackJob& X : P.packs) *tm->i16 += X.b >= 0 ? 2 : 1;
     // work items of every launch, then the walk order (local job indices)
     std::vector<int2> items;
     std::vector<size_t> goff;
@@ -471,14 +563,16 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     const size_t ps_b = sizeof(int64_t) * pstarts.size();
     const size_t it_b = sizeof(int2) * items.size();
     const size_t wk_b = sizeof(int32_t) * P.walk.size();
+    const size_t pk_b = sizeof(PackJob) * npacks;
+    const size_t pks_b = sizeof(int64_t) * npacks;
     int rc;
     // the staging buffer and workspace may still be in use by earlier work
     // (the wait is device time, not host time)
     const auto tw0 = std::chrono::steady_clock::now();
     if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
     host_clock.t0 += std::chrono::steady_clock::now() - tw0;
-    if ((rc = ws.jobs.ensure(jobs_b + pj_b + 256)) != MPG_OK) return rc;
-    if ((rc = ws.row_start.ensure(ps_b + 64)) != MPG_OK) return rc;
+    if ((rc = ws.jobs.ensure(jobs_b + pj_b + pk_b + 256)) != MPG_OK) return rc;
+    if ((rc = ws.row_start.ensure(ps_b + pks_b + 64)) != MPG_OK) return rc;
     if ((rc = ws.order.ensure(it_b + wk_b + 64)) != MPG_OK) return rc;
     if ((rc = ws.desc.ensure((size_t)P.desc_bytes + 64)) != MPG_OK) return rc;
     if ((rc = ws.bnd.ensure(sizeof(int2) * (size_t)P.bnd_elems + 64)) != MPG_OK) return rc;
@@ -486,17 +580,25 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     if ((rc = ws.state.ensure((size_t)kPairStateBytes * cnt + sizeof(int) * (P.nprog + 64))) !=
         MPG_OK)
         return rc;
-    const size_t plan_b = jobs_b + pj_b + ps_b + it_b + wk_b + 1024;
+    // staging layout: jobs, prepass jobs, packs | row starts, pack row
+    // starts | items, walk list
+    const size_t plan_b = jobs_b + pj_b + pk_b + ps_b + pks_b + it_b + wk_b + 1024;
     if ((rc = ws.hplan.ensure(plan_b)) != MPG_OK) return rc;
     uint8_t* h = (uint8_t*)ws.hplan.p;
     std::memcpy(h, P.jobs.data(), jobs_b);
     std::memcpy(h + jobs_b, pjobs.data(), pj_b);
-    std::memcpy(h + jobs_b + pj_b, pstarts.data(), ps_b);
-    std::memcpy(h + jobs_b + pj_b + ps_b, items.data(), it_b);
-    std::memcpy(h + jobs_b + pj_b + ps_b + it_b, P.walk.data(), wk_b);
+    std::memcpy(h + jobs_b + pj_b, P.packs.data(), pk_b);
+    uint8_t* h2 = h + jobs_b + pj_b + pk_b;
+    std::memcpy(h2, pstarts.data(), ps_b);
+    std::memcpy(h2 + ps_b, P.pack_row_start.data(), pks_b);
+    uint8_t* h3 = h2 + ps_b + pks_b;
+    std::memcpy(h3, items.data(), it_b);
+    std::memcpy(h3 + it_b, P.walk.data(), wk_b);
     PairJob* d_jobs = (PairJob*)ws.jobs.p;
     PairJob* d_pjobs = (PairJob*)((uint8_t*)ws.jobs.p + jobs_b);
+    PackJob* d_packs = (PackJob*)((uint8_t*)ws.jobs.p + jobs_b + pj_b);
     int64_t* d_starts = (int64_t*)ws.row_start.p;
+    int64_t* d_pkstarts = (int64_t*)((uint8_t*)ws.row_start.p + ps_b);
     int2* d_items = (int2*)ws.order.p;
     int32_t* d_walk = (int32_t*)((uint8_t*)ws.order.p + it_b);
     uint8_t* d_state = (uint8_t*)ws.state.p;
@@ -504,15 +606,16 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     int* d_qhead = (int*)(d_state + (size_t)kPairStateBytes * cnt);  // one per launch
     int* d_prog = d_qhead + 16;
     hipError_t e = hipSuccess;
-    if (jobs_b + pj_b) e = hipMemcpyAsync(ws.jobs.p, h, jobs_b + pj_b, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && ps_b)
-        e = hipMemcpyAsync(d_starts, h + jobs_b + pj_b, ps_b, hipMemcpyHostToDevice, st);
+    if (jobs_b + pj_b + pk_b)
+        e = hipMemcpyAsync(ws.jobs.p, h, jobs_b + pj_b + pk_b, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && ps_b + pks_b)
+        e = hipMemcpyAsync(d_starts, h2, ps_b + pks_b, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && it_b + wk_b)
-        e = hipMemcpyAsync(ws.order.p, h + jobs_b + pj_b + ps_b, it_b + wk_b,
-                           hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(ws.order.p, h3, it_b + wk_b, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return MPG_E_DEVICE;
 
-    if (launch_status(st, d_jobs, cnt, d_out) != hipSuccess) return MPG_E_DEVICE;
+    const DpSink sink{d_out, d_ops, cfg.serve ? 1 : 0, cfg.serve ? 1 : 0};
+    if (launch_status(st, d_jobs, cnt, sink) != hipSuccess) return MPG_E_DEVICE;
     const int neg_init = -(1 << 30);
     if (launch_init(st, d_jobs, cnt, d_pst, d_prog, d_qhead, 16, neg_init) != hipSuccess)
         return MPG_E_DEVICE;
@@ -520,14 +623,21 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     if (launch_prepass(st, d_pjobs, d_starts, (int)pjobs.size(), P.total_rows, d_dna,
                        (uint8_t*)ws.desc.p, DP) != hipSuccess)
         return MPG_E_DEVICE;
+    if (npacks && launch_prepass16(st, d_jobs, d_packs, d_pkstarts, (int)npacks, P.pack_rows,
+                                   d_dna, (uint8_t*)ws.desc.p, d_prog, DP) != hipSuccess)
+        return MPG_E_DEVICE;
     if (tm) tm->end(st, 0);
     if (tm) tm->begin(st, 1);
     auto launch_group = [&](hipStream_t s2, size_t g) -> hipError_t {
         const Group& G = P.groups[g];
         const int nit = (int)G.items.size();
+        if (G.i16)
+            return launch_dp16(s2, G.K, ncu, DP, d_jobs, d_packs, d_items + goff[g], nit,
+                               d_qhead + g, d_pst, d_prog, d_prot, (const uint8_t*)ws.desc.p,
+                               (int2*)ws.bnd.p, sink);
         return launch_dp(s2, G.K, G.tb, ncu, DP, d_jobs, d_items + goff[g], nit,
                          d_qhead + g, d_pst, d_prog, d_prot, (const uint8_t*)ws.desc.p,
-                         (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, d_out);
+                         (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, sink);
     };
     if (ngroups > 15) return MPG_E_INVAL;
     if (ngroups == 1) {
@@ -548,7 +658,7 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
         }
     }
     if (tm) tm->end(st, 1);
-    if (!P.walk.empty()) {
+    if (!P.walk.empty() && !cfg.serve) {
         if (tm) tm->begin(st, 2);
         e = launch_walk(st, d_jobs, d_walk, (int)P.walk.size(), (const uint8_t*)ws.tb.p, d_out,
                         d_ops);
@@ -567,7 +677,8 @@ bool seg_tb(const mpg_seg& s, const mpg_params* p) {
 // the stream; each wave writes straight into the caller's records and ops.
 int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
                   const uint8_t* d_dna, const mpg_seg* segs, int32_t n, mpg_dev_result* d_out,
-                  char* d_ops, uint64_t tb_budget, Timer* tm, int ncu) {
+                  char* d_ops, const RunCfg& cfg) {
+    const uint64_t tb_budget = cfg.tb_budget;
     std::vector<int64_t> ops_off(n);
     int64_t o = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -587,7 +698,7 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
                               : 0;
         if (b <= (int64_t)tb_budget && acc + b > (int64_t)tb_budget && !idx.empty()) {
             int rc = run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(),
-                             ops_off, d_out, d_ops, tb_budget, tm, ncu);
+                             ops_off, d_out, d_ops, cfg);
             if (rc != MPG_OK) return rc;
             idx.clear();
             acc = 0;
@@ -597,7 +708,7 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
     }
     if (idx.empty()) return MPG_OK;
     return run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(), ops_off,
-                   d_out, d_ops, tb_budget, tm, ncu);
+                   d_out, d_ops, cfg);
 }
 
 int params_check_impl(const mpg_params* p) {
@@ -686,6 +797,12 @@ int mpg_ctx_create(mpg_ctx** out, int device, uint64_t tb_budget_bytes, uint32_t
     if (!c) return MPG_E_NOMEM;
     c->device = device;
     if (tb_budget_bytes) c->tb_budget = tb_budget_bytes;
+    // serving knobs (tuning only): lanes, micro-batch size, long-batch share
+    if (const int v = env_int("MPG_SRV_NSHORT")) c->nshort = std::max(1, std::min(v, 4));
+    if (const int v = env_int("MPG_SRV_NLONG")) c->nlong = std::max(1, std::min(v, 4));
+    if (const int v = env_int("MPG_SRV_SHORT_MCELLS")) c->short_cells = (int64_t)v * 1000000;
+    if (const int v = env_int("MPG_SRV_LONG_SHARE_PCT")) c->long_share = std::min(v, 100) / 100.0;
+    if (const int v = env_int("MPG_SRV_MAX_JOBS")) c->max_jobs_per_batch = std::max(1, v);
     if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return MPG_E_DEVICE;
@@ -736,10 +853,13 @@ int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot
     if (need > 0 && (!d_ops || ops_cap < need)) return MPG_E_RANGE;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
-    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host};
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16};
     ctx->n_calls++;
-    return run_dev_waves(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, n, d_out, d_ops,
-                         ctx->tb_budget, ctx->timing ? &tm : nullptr, g_num_cu);
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.tm = ctx->timing ? &tm : nullptr;
+    cfg.ncu = g_num_cu;
+    return run_dev_waves(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, n, d_out, d_ops, cfg);
 }
 
 }  // extern "C"
@@ -748,7 +868,7 @@ namespace {
 
 // Synchronous host-memory batch on a given stream/workspace; fills out[].
 int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pair* pairs,
-               int32_t n, mpg_result* out, uint64_t tb_budget, Timer* tm, int ncu) {
+               int32_t n, mpg_result* out, const RunCfg& cfg) {
     std::vector<mpg_seg> segs(n);
     int64_t pbytes = 0, dbytes = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -783,7 +903,7 @@ int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pai
             hipSuccess)
         return MPG_E_DEVICE;
     rc = run_dev_waves(st, ws, p, d_seq, d_seq + pbytes, segs.data(), n,
-                       (mpg_dev_result*)ws.out.p, (char*)ws.ops.p, tb_budget, tm, ncu);
+                       (mpg_dev_result*)ws.out.p, (char*)ws.ops.p, cfg);
     if (rc != MPG_OK) return rc;
     if (hipMemcpyAsync(ws.hout.p, ws.out.p, sizeof(mpg_dev_result) * (size_t)n,
                        hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -823,6 +943,111 @@ int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pai
 }
 
 // ------------------------------------------------------------------ serving
+// One serving batch: stage the sequences, launch with per-pair publication
+// into host-mapped records, and deliver every result as soon as its pair's
+// record is published.  Returns once all pairs are delivered (or the stream
+// failed; then the rest complete with MPG_E_DEVICE).
+template <typename Deliver>
+int serve_batch(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pair* pairs,
+                int32_t n, uint64_t tb_budget, int ncu, Deliver deliver) {
+    std::vector<mpg_seg> segs(n);
+    int64_t pbytes = 0, dbytes = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        segs[k].prot_off = pbytes;
+        segs[k].plen = pairs[k].plen;
+        segs[k].dna_off = dbytes;
+        segs[k].dlen = pairs[k].dlen;
+        segs[k].flags = pairs[k].flags | (p->flags & MPG_WANT_TB);
+        segs[k]._pad = 0;
+        pbytes += pairs[k].plen;
+        dbytes += pairs[k].dlen;
+    }
+    const int64_t ops_cap = mpg_ops_capacity(segs.data(), n);
+    int rc;
+    ws.prec.flags = ws.pops.flags = hipHostMallocMapped | hipHostMallocCoherent;
+    if ((rc = ws.seq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hseq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return rc;
+    if ((rc = ws.prec.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return rc;
+    if ((rc = ws.pops.ensure((size_t)ops_cap + 64)) != MPG_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    uint8_t* hs = (uint8_t*)ws.hseq.p;
+    for (int32_t k = 0; k < n; ++k) {
+        if (pairs[k].plen) std::memcpy(hs + segs[k].prot_off, pairs[k].prot, pairs[k].plen);
+        if (pairs[k].dlen) std::memcpy(hs + pbytes + segs[k].dna_off, pairs[k].dna, pairs[k].dlen);
+    }
+    volatile mpg_dev_result* rec = (volatile mpg_dev_result*)ws.prec.p;
+    for (int32_t k = 0; k < n; ++k) rec[k].status = kPending;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    uint8_t* d_seq = (uint8_t*)ws.seq.p;
+    if (pbytes + dbytes > 0 &&
+        hipMemcpyAsync(d_seq, hs, (size_t)(pbytes + dbytes), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        return MPG_E_DEVICE;
+    RunCfg cfg;
+    cfg.tb_budget = tb_budget;
+    cfg.ncu = ncu;
+    cfg.serve = true;
+    rc = run_dev_waves(st, ws, p, d_seq, d_seq + pbytes, segs.data(), n,
+                       (mpg_dev_result*)ws.prec.p, (char*)ws.pops.p, cfg);
+    std::vector<char> got(n, 0);
+    int32_t left = n;
+    auto harvest = [&]() {
+        int32_t found = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            if (got[k] || rec[k].status == kPending) continue;
+            std::atomic_thread_fence(std::memory_order_acquire);
+            mpg_dev_result R;
+            R.status = rec[k].status;
+            R.score = rec[k].score;
+            R.g_beg = rec[k].g_beg;
+            R.g_end = rec[k].g_end;
+            R.p_beg = rec[k].p_beg;
+            R.p_end = rec[k].p_end;
+            R.ops_off = rec[k].ops_off;
+            R.ops_len = rec[k].ops_len;
+            const char* ops = (segs[k].flags & MPG_WANT_TB) && R.status == MPG_OK
+                                  ? (const char*)ws.pops.p + R.ops_off
+                                  : nullptr;
+            deliver(k, R, ops);
+            got[k] = 1;
+            --left;
+            ++found;
+        }
+        return found;
+    };
+    if (rc == MPG_OK) {
+        // poll the records while the device works; the stream's state tells
+        // when nothing more can arrive
+        for (;;) {
+            const int32_t f = harvest();
+            if (!left) break;
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipSuccess) {
+                harvest();
+                break;
+            }
+            if (q != hipErrorNotReady) {
+                rc = MPG_E_DEVICE;
+                break;
+            }
+            if (!f) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+    }
+    if (left) {
+        // the device failed, or a record was never published
+        if (rc == MPG_OK) rc = MPG_E_DEVICE;
+        for (int32_t k = 0; k < n; ++k) {
+            if (got[k]) continue;
+            mpg_dev_result R{};
+            R.status = rc;
+            R.g_beg = R.g_end = R.p_beg = R.p_end = -1;
+            deliver(k, R, nullptr);
+        }
+    }
+    hipStreamSynchronize(st);
+    return rc;
+}
+
 // One scheduler thread admits pending jobs into batches while a slot (stream
 // + workspace) and traceback budget are free.  Jobs are queued by class
 // (short/long x score-only/traceback); every batch holds one class, so it is
@@ -908,31 +1133,44 @@ void scheduler(mpg_ctx* c) {
                 pairs[k].dlen = (int32_t)b[k].dna.size();
                 pairs[k].flags = b[k].flags;
             }
-            std::vector<mpg_result> res(b.size());
             params.flags &= ~(uint32_t)MPG_WANT_TB;
-            int rc = align_host(streams[slot], wss[slot], &params, pairs.data(),
-                                (int32_t)pairs.size(), res.data(), (uint64_t)tb + 1, nullptr, ncu);
-            const int64_t t = now_ns();
-            std::lock_guard<std::mutex> g(c->mu);
-            for (size_t k = 0; k < b.size(); ++k) {
-                mpg_result r = res[k];
-                if (rc != MPG_OK) {
-                    std::memset(&r, 0, sizeof(r));
-                    r.status = rc;
-                    r.g_beg = r.g_end = r.p_beg = r.p_end = -1;
+            // every result goes to the poll queue the moment its pair is done
+            auto deliver = [&](int32_t k, const mpg_dev_result& R, const char* ops) {
+                mpg_result r;
+                std::memset(&r, 0, sizeof(r));
+                r.status = R.status;
+                r.score = R.score;
+                r.g_beg = R.g_beg;
+                r.g_end = R.g_end;
+                r.p_beg = R.p_beg;
+                r.p_end = R.p_end;
+                if (ops) {
+                    char* d = (char*)std::malloc((size_t)R.ops_len + 1);
+                    if (d) {
+                        std::memcpy(d, ops, (size_t)R.ops_len);
+                        d[R.ops_len] = 0;
+                        r.ops = d;
+                        r.ops_len = R.ops_len;
+                    } else {
+                        r.status = MPG_E_NOMEM;
+                    }
                 }
                 r.job_id = b[k].id;
                 r.t_arrive_ns = b[k].t_arrive;
-                r.t_done_ns = t;
+                r.t_done_ns = now_ns();
+                std::lock_guard<std::mutex> g(c->mu);
                 c->done.push_back(r);
                 c->stats.cells += (uint64_t)b[k].cells;
-            }
-            c->stats.completed += b.size();
-            c->stats.in_flight -= b.size();
+                c->stats.completed += 1;
+                c->stats.in_flight -= 1;
+                c->cv_done.notify_all();
+            };
+            serve_batch(streams[slot], wss[slot], &params, pairs.data(), (int32_t)pairs.size(),
+                        (uint64_t)tb + 1, ncu, deliver);
+            std::lock_guard<std::mutex> g(c->mu);
             c->tb_in_use -= (uint64_t)tb;
             c->stats.tb_bytes_in_use = c->tb_in_use;
             busy[slot] = false;
-            c->cv_done.notify_all();
             c->cv_work.notify_all();
         });
     }
@@ -955,10 +1193,13 @@ int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, in
     if (n == 0) return MPG_OK;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
-    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host};
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16};
     ctx->n_calls++;
-    return align_host(ctx->stream, ctx->ws, p, pairs, n, out, ctx->tb_budget,
-                      ctx->timing ? &tm : nullptr, g_num_cu);
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.tm = ctx->timing ? &tm : nullptr;
+    cfg.ncu = g_num_cu;
+    return align_host(ctx->stream, ctx->ws, p, pairs, n, out, cfg);
 }
 
 int mpg_submit(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pair, uint64_t* job_id) {
@@ -1091,9 +1332,10 @@ int mpg_get_timing(mpg_ctx* ctx, mpg_timing* t, int reset) {
     t->dp_spans = ctx->n_dp;
     t->calls = ctx->n_calls;
     t->host_ms = ctx->t_host;
+    t->i16_pairs = ctx->n_i16;
     if (reset) {
         ctx->t_pre = ctx->t_dp = ctx->t_walk = ctx->t_host = 0;
-        ctx->n_dp = ctx->n_calls = 0;
+        ctx->n_dp = ctx->n_calls = ctx->n_i16 = 0;
     }
     return MPG_OK;
 }

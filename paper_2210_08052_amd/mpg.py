@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmpg.so")
+# The in-tree build; MPG_LIBRARY may name another build of the same sources
+# (tuning variants).
+LIB_PATH = os.environ.get("MPG_LIBRARY") or os.path.join(HERE, "libmpg.so")
 
 MPG_OK, MPG_E_INVAL, MPG_E_RANGE, MPG_E_NOMEM = 0, -1, -2, -3
 MPG_E_AGAIN, MPG_E_DEVICE, MPG_E_NOALN, MPG_E_CANCELLED = -4, -5, -6, -7
@@ -66,7 +68,8 @@ class mpg_stats(ctypes.Structure):
 class mpg_timing(ctypes.Structure):
     _fields_ = [("prepass_ms", ctypes.c_double), ("dp_ms", ctypes.c_double),
                 ("walk_ms", ctypes.c_double), ("dp_spans", ctypes.c_uint64),
-                ("calls", ctypes.c_uint64), ("host_ms", ctypes.c_double)]
+                ("calls", ctypes.c_uint64), ("host_ms", ctypes.c_double),
+                ("i16_pairs", ctypes.c_uint64)]
 
 
 SEG_DTYPE = np.dtype([("prot_off", "<i8"), ("dna_off", "<i8"), ("plen", "<i4"),

@@ -16,13 +16,14 @@ from paper_2210_08052_amd import workloads as W
 
 def scorings(mode=0, flags=0, rand_seed=None):
     """(gpu params, oracle Scoring) for the same scoring inputs."""
+    oflags = flags & 3  # the oracle knows only NO_INTRON and NO_FRAMESHIFT
     if rand_seed is None:
         return (mpg.params(mode=mode, flags=flags),
-                oparams.default_scoring(mode=mode, flags=flags))
+                oparams.default_scoring(mode=mode, flags=oflags))
     r = W.random_scoring(rand_seed)
     g = mpg.params(mode=mode, flags=flags, q=r["q"], e=r["e"], f=r["f"], r=r["r"],
                    mat=r["mat"], donor=r["donor"], acceptor=r["acceptor"])
-    o = oparams.default_scoring(mode=mode, flags=flags, q=r["q"], e=r["e"], f=r["f"],
+    o = oparams.default_scoring(mode=mode, flags=oflags, q=r["q"], e=r["e"], f=r["f"],
                                 r=r["r"], mat=r["mat"], donor=r["donor"],
                                 acceptor=r["acceptor"])
     return g, o

@@ -213,3 +213,116 @@ def test_serving_matches_batch(ctx):
         tb = k % 2 == 0
         assert key_gpu(got[k], tb) == key_gpu(ref[k], tb)
         assert got[k]["t_done_ns"] >= got[k]["t_arrive_ns"] > 0
+
+
+# ---- lane-packed int16 kernel (LOCAL, score-only, two pairs per wavefront)
+
+def _i16_run(ctx, pairs, g, o, expect_i16):
+    ctx.enable_timing(True)
+    ctx.timing(reset=True)
+    got = compare(ctx, pairs, g, o, False, label="i16")
+    n16 = ctx.timing(reset=True)["i16_pairs"]
+    ctx.enable_timing(False)
+    assert n16 == expect_i16, "int16 kernel ran %d pairs, expected %d" % (n16, expect_i16)
+    return got
+
+
+@pytest.mark.parametrize("K16", [1, 2])
+def test_int16_lanes(ctx, K16, monkeypatch):
+    """Every LOCAL score-only pair runs in the int16 kernel and equals the
+    oracle; 37 pairs leave one upper half idle; proteins span several strips
+    whose boundaries stream through HBM."""
+    monkeypatch.setenv("MPG_FORCE_K16", str(K16))
+    pairs = _pairs(500 + K16, n=37, max_prot=400, max_dna=1500)
+    for flags in (0, 1, 2, 3):
+        print("case K16=%d flags=%d" % (K16, flags), flush=True)
+        g, o = scorings(0, flags)
+        g.flags |= mpg.MPG_ALLOW_I16
+        _i16_run(ctx, pairs, g, o, len(pairs))
+
+
+@pytest.mark.parametrize("K16", [1, 2])
+def test_int16_random_scoring(ctx, K16, monkeypatch):
+    """Random penalties, splice tables and matrices; pairs whose bound does
+    not fit 16 bits fall back to the int32 kernel in the same call."""
+    monkeypatch.setenv("MPG_FORCE_K16", str(K16))
+    for rs in range(4):
+        g, o = scorings(0, rs % 4, rand_seed=600 + rs)
+        g.flags |= mpg.MPG_ALLOW_I16
+        pairs = _pairs(700 + rs, n=30, max_prot=300, max_dna=1200)
+        maxpos = max(0, int(np.ctypeslib.as_array(g.mat).max()))
+        pen = max(g.q + g.e, g.f, g.r + max(g.donor) + max(g.acceptor),
+                  -int(np.ctypeslib.as_array(g.mat).min()))
+        expect = sum(1 for p, _ in pairs if maxpos * len(p) <= 32767 - 256) if pen <= 8192 else 0
+        print("case K16=%d rs=%d expect_i16=%d" % (K16, rs, expect), flush=True)
+        _i16_run(ctx, pairs, g, o, expect)
+
+
+def test_int16_mixed_call(ctx):
+    """One call mixing int16 pairs, traceback pairs (int32 kernel) and pairs
+    beyond the int16 bound; every result equals the oracle's."""
+    g, o = scorings(0, 0)
+    g.flags |= mpg.MPG_ALLOW_I16
+    pairs = _pairs(800, n=25, max_prot=200, max_dna=900)
+    pairs += [("W" * 3100, "TGG" * 3100)]  # 11 * 3100 > 32767: int32 path
+    tbs = [k % 3 == 0 for k in range(len(pairs) - 1)] + [False]
+    got = ctx.align_batch([(p, d, tb) for (p, d), tb in zip(pairs, tbs)], g)
+    for k, ((p, d), tb) in enumerate(zip(pairs, tbs)):
+        e = oracle.align(p, d, o, want_tb=tb)
+        assert key_gpu(got[k], tb) == key_orc(e, tb), (k, len(p), len(d))
+    # the GLOBAL/EXTEND modes never use int16 lanes
+    for mode in (1, 2):
+        g2, o2 = scorings(mode, 0)
+        g2.flags |= mpg.MPG_ALLOW_I16
+        _i16_run(ctx, pairs[:8], g2, o2, 0)
+
+
+def test_int16_batch_equals_int32(ctx):
+    """The 10,000-pair planted-gene batch: int16 lanes give the same score and
+    end cell as the int32 kernel on every pair; a seeded sample also equals
+    the oracle."""
+    pairs = [(p.prot, p.dna) for p in W.batch_pairs(10000, seed=2)]
+    g32 = mpg.params()
+    g16 = mpg.params(flags=mpg.MPG_ALLOW_I16)
+    r32 = ctx.align_batch([(p, d, False) for p, d in pairs], g32)
+    ctx.enable_timing(True)
+    ctx.timing(reset=True)
+    r16 = ctx.align_batch([(p, d, False) for p, d in pairs], g16)
+    n16 = ctx.timing(reset=True)["i16_pairs"]
+    ctx.enable_timing(False)
+    assert n16 == len(pairs)
+    diff = [k for k in range(len(pairs)) if key_gpu(r16[k], False) != key_gpu(r32[k], False)]
+    assert not diff, "%d pairs differ, first %s" % (len(diff), diff[:5])
+    rng = np.random.default_rng(11)
+    sample = rng.choice(len(pairs), size=24, replace=False)
+    exp = oracle.align_many([pairs[k] for k in sample], oracle.default_scoring(), want_tb=False)
+    for k, e in zip(sample, exp):
+        assert key_gpu(r16[k], False) == key_orc(e, False), k
+
+
+def test_serving_results_arrive_per_pair():
+    """A long job submitted first and short jobs after it: results are handed
+    out pair by pair, so short results arrive while the long pair still runs,
+    and every served result equals the batch result for the same pair."""
+    g, _ = scorings(0, 0)
+    rng = np.random.default_rng(31)
+    long_p = "".join(rng.choice(list("ACDEFGHIKLMNPQRSTVWY"), size=3000)).encode()
+    long_d = "".join(rng.choice(list("ACGT"), size=90000)).encode()
+    shorts = _pairs(1234, n=40, max_prot=200, max_dna=2000)
+    jobs = [(long_p, long_d, True)] + [(p, d, k % 2 == 0) for k, (p, d) in enumerate(shorts)]
+    with mpg.Context(0) as ref_ctx:
+        ref = ref_ctx.align_batch(jobs, g)
+    with mpg.Context(0) as srv:
+        ids = [srv.submit(g, p, d, want_tb=tb) for p, d, tb in jobs]
+        assert all(i > 0 for i in ids)
+        order, got = [], {}
+        while len(got) < len(jobs):
+            for r in srv.poll(64, 200000):
+                got[r["job_id"]] = r
+                order.append(r["job_id"])
+    keys = ("status", "score", "g_beg", "g_end", "p_beg", "p_end", "ops")
+    for k, jid in enumerate(ids):
+        assert all(got[jid][f] == ref[k][f] for f in keys), k
+    # the long job (first submitted) is not the first result out
+    assert order.index(ids[0]) > 0
+    assert got[ids[0]]["t_done_ns"] > min(got[i]["t_done_ns"] for i in ids[1:])
