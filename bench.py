@@ -145,22 +145,27 @@ def _percentiles(x):
     return {"p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3), "n": int(len(x))}
 
 
-def run_served(mpg, p, jobs, arrivals_s, log_every=20000):
+def run_served(mpg, p, jobs, arrivals_s, keep=(), log_every=20000):
     """Open-loop submission of jobs at their arrival times (seconds from t0)
-    into a serving context; returns (t0_ns, done_ns per job, results)."""
+    into a serving context.  Returns (t0_ns, due_ns, done_ns, submit_ns,
+    status, kept results, stats); kept results are the full results of the
+    job indices in `keep`."""
     import threading
     srv = mpg.Context(0, tb_budget_bytes=SERVING_TB_BUDGET)
     # warm-up: a few short jobs through the same context
-    for q in jobs[:64]:
+    nw = min(64, len(jobs))
+    for q in jobs[:nw]:
         srv.submit(p, q.prot, q.dna, want_tb=q.want_tb)
     got = 0
-    while got < min(64, len(jobs)):
+    while got < nw:
         got += len(srv.poll(256, 100000))
+    base = nw + 1  # job ids are consecutive from 1 in a fresh context
     n = len(jobs)
     done_ns = np.zeros(n, dtype=np.int64)
-    results = [None] * n
-    id2k = {}
-    lock = threading.Lock()
+    sub_ns = np.zeros(n, dtype=np.int64)
+    status = np.zeros(n, dtype=np.int32)
+    kept = {}
+    keep_ids = set(int(k) + base for k in keep)
     t0 = time.monotonic_ns() + 20_000_000
     due = t0 + np.round(np.asarray(arrivals_s) * 1e9).astype(np.int64)
     finished = threading.Event()
@@ -168,16 +173,17 @@ def run_served(mpg, p, jobs, arrivals_s, log_every=20000):
     def poller():
         cnt = 0
         while cnt < n:
-            for r in srv.poll(1024, 20000):
-                with lock:
-                    k = id2k.get(r["job_id"])
-                if k is None:
-                    continue
-                done_ns[k] = r["t_done_ns"]
-                results[k] = r
+            res, full = srv.poll_raw(4096, 20000, keep_ids)
+            for jid, ta, td, st in res:
+                k = jid - base
+                done_ns[k] = td
+                sub_ns[k] = ta
+                status[k] = st
                 cnt += 1
                 if cnt % log_every == 0:
                     log("served %d/%d" % (cnt, n))
+            for jid, r in full.items():
+                kept[jid - base] = r
         finished.set()
 
     th = threading.Thread(target=poller, daemon=True)
@@ -189,11 +195,10 @@ def run_served(mpg, p, jobs, arrivals_s, log_every=20000):
         while time.monotonic_ns() < due[k]:
             pass
         while True:
-            with lock:
-                jid = srv.submit(p, q.prot, q.dna, want_tb=q.want_tb)
-                if jid >= 0:
-                    id2k[jid] = k
+            jid = srv.submit(p, q.prot, q.dna, want_tb=q.want_tb)
             if jid >= 0:
+                if jid != base + k:
+                    raise RuntimeError("unexpected job id %d for job %d" % (jid, k))
                 break
             if jid != mpg.MPG_E_AGAIN:
                 raise RuntimeError("mpg_submit failed: %d" % jid)
@@ -201,7 +206,7 @@ def run_served(mpg, p, jobs, arrivals_s, log_every=20000):
     finished.wait()
     stats = srv.stats()
     srv.close()
-    return t0, due, done_ns, results, stats
+    return t0, due, done_ns, sub_ns, status, kept, stats
 
 
 def bench_serving(args):
@@ -231,7 +236,7 @@ def bench_serving(args):
         log("batched capacity %.1f jobs/s (%.1f GCUPS) on %d jobs; 0.7x = %.4g jobs/s" % (
             cap, cells[:m].sum() / span_b / 1e9, m, rate))
         # for comparison: the same jobs submitted at once through the serving path
-        t0, due, done, res, st = run_served(mpg, p, jobs[:m], np.zeros(m))
+        t0, due, done, _, _, _, st = run_served(mpg, p, jobs[:m], np.zeros(m))
         span_s = (done.max() - t0) / 1e9
         log("serving drain %.1f jobs/s (%.1f GCUPS)" % (m / span_s, cells[:m].sum() / span_s / 1e9))
         print(json.dumps({"calibration": {"jobs": m, "batched_s": round(span_b, 3),
@@ -243,9 +248,12 @@ def bench_serving(args):
     if not rate:
         raise SystemExit("no arrival rate: run --config serving --calibrate first or pass --rate")
     arrivals = arr1 / rate
-    t0, due, done, res, st = run_served(mpg, p, jobs, arrivals)
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(n, size=min(args.check, n), replace=False))
+    t0, due, done, subm, status, kept, st = run_served(mpg, p, jobs, arrivals, keep=sample)
     lat = (done - due) / 1e6
-    bad = sum(1 for r in res if r is None or r["status"] != 0)
+    lag = (subm - due) / 1e6
+    bad = int((status != 0).sum())
     keep = np.arange(n) >= int(0.05 * n)  # drop the first 5% (warm-up)
     span = (done.max() - t0) / 1e9
     served = {
@@ -287,13 +295,11 @@ def bench_serving(args):
     log("one-pair-per-launch: %s" % json.dumps(baseline))
 
     # served results equal batched results for the same jobs (seeded sample)
-    rng = np.random.default_rng(7)
-    sample = np.sort(rng.choice(n, size=min(args.check, n), replace=False))
     with mpg.Context(0) as ctx:
         ref = ctx.align_batch([(jobs[k].prot, jobs[k].dna, jobs[k].want_tb) for k in sample], p)
     keys = ("status", "score", "g_beg", "g_end", "p_beg", "p_end", "ops")
     mism = sum(1 for k, r in zip(sample, ref)
-               if res[k] is None or any(res[k][f] != r[f] for f in keys))
+               if k not in kept or any(kept[k][f] != r[f] for f in keys))
     line = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": round(span * 1e3, 3),
@@ -304,6 +310,7 @@ def bench_serving(args):
                    "jobs": n, "cells": float(cells.sum()), "rate_jobs_per_s": rate,
                    "tb_budget_bytes": SERVING_TB_BUDGET},
         "latency": served,
+        "submit_lag_ms": _percentiles(lag[keep]),
         "failed_jobs": bad,
         "served_vs_batched_mismatches": {"checked": int(len(sample)), "mismatches": mism},
         "one_pair_per_launch": baseline,
@@ -372,6 +379,9 @@ def main():
     ctx.set_stream(stream.cuda_stream)
     i16 = args.config == "batch16"
     p = mpg.params(flags=mpg.MPG_ALLOW_I16) if i16 else mpg.params()
+    # kernel width from timed runs of this very workload
+    tuning = ctx.autotune(p, d_prot.data_ptr(), d_dna.data_ptr(), segs)
+    log("autotune: %s" % json.dumps(tuning))
 
     def step():
         ctx.align_batch_dev(p, d_prot.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
@@ -440,6 +450,7 @@ def main():
                      "ops_per_cell": ops,
                      "dp_ms_per_step": round(dp_ms, 3)},
         "cpu_baseline": cpu,
+        "autotune": tuning,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

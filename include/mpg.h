@@ -209,8 +209,8 @@ int mpg_sync(mpg_ctx *ctx);
  * mpg_poll.
  *
  * Scheduling: short and long jobs, with and without traceback, wait in four
- * queues.  Short jobs run in micro-batches (about 2e8 cells) on two streams;
- * long jobs are gathered into batches of their own on a third stream, so a
+ * queues.  Short jobs run in batches of up to 2e9 cells on three streams;
+ * long jobs are gathered into batches of their own on a fourth stream, so a
  * short job never shares a launch with a long pair.  Within a batch every
  * pair completes on its own: the wavefront that finishes a pair's last strip
  * walks its traceback and publishes the result to host-mapped memory, and
@@ -256,6 +256,32 @@ int mpg_enable_timing(mpg_ctx *ctx, int on);
 
 /* Wait for the timed work, fill *t, and zero the counters if reset != 0. */
 int mpg_get_timing(mpg_ctx *ctx, mpg_timing *t, int reset);
+
+/* ---- autotuning ----------------------------------------------------------- */
+
+/* DP rates (GCUPS) of a sample batch at each kernel width, and the widths
+ * chosen. */
+typedef struct {
+    double gcups[3];     /* int32 kernels at 1, 2, 4 columns per lane */
+    double i16_gcups[2]; /* int16 lanes at 1, 2 columns per lane (0 if not tried) */
+    int32_t K, K16;      /* the widths this context uses from now on */
+    int32_t _pad[2];
+} mpg_tuning;
+
+/*
+ * Run a sample of the caller's workload at every kernel width and keep the
+ * fastest for the batch calls of this context.  The sample is given like
+ * mpg_align_batch_dev's input (letters in device memory, n segments, params
+ * p; MPG_ALLOW_I16 in p also tunes the int16 width); with n = 0 a built-in
+ * sample is used (1,024 pairs of 511 residues x 4,096 nucleotides, half with
+ * traceback; p, d_prot, d_dna and segs may then be NULL).  Each width runs
+ * twice and the second run's DP time counts.  Results never depend on the
+ * width.  Serving uses its own width (the narrowest, for the shortest per-pair
+ * critical path).  Call it while no other work of the context is in flight.
+ * out may be NULL.
+ */
+int mpg_autotune(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot, const uint8_t *d_dna,
+                 const mpg_seg *segs, int32_t n, mpg_tuning *out);
 
 /* Release the ops strings of n results returned by this context. */
 void mpg_result_release(mpg_ctx *ctx, mpg_result *r, int32_t n);

@@ -222,12 +222,37 @@ struct Overrides {
     Overrides() : K(env_int("MPG_FORCE_K")), K16(env_int("MPG_FORCE_K16")) {}
 };
 
-// Columns per lane of the int16 kernel.
-int choose_K16(const Overrides& ov) { return ov.K16 == 1 ? 1 : 2; }
+// Strip widths chosen by mpg_autotune from timed runs (0: not tuned).
+struct Tuning {
+    int K = 0;    // int32 kernels
+    int K16 = 0;  // int16 kernel
+};
 
-int choose_K(int m, const Overrides& ov) {
-    (void)m;
-    if (ov.K == 1 || ov.K == 2 || ov.K == 4) return ov.K;
+int strip_cols(int m, int K) { return ((m + 1 + 64 * K - 1) / (64 * K)) * 64 * K; }
+
+// Columns per lane: one width for all pairs of a call (pairs of one width
+// share a launch; mixed widths would split the device between concurrent
+// persistent launches): a forced width, else the tuned one, else 2.
+struct KChoice {
+    int K[2] = {2, 2};  // [traceback]
+};
+
+KChoice choose_widths(const Overrides& ov, const Tuning* tu, int force) {
+    KChoice kc;
+    int K = 2;
+    if (ov.K == 1 || ov.K == 2 || ov.K == 4) K = ov.K;
+    else if (force) K = force;
+    else if (tu && tu->K) K = tu->K;
+    kc.K[0] = kc.K[1] = K;
+    return kc;
+}
+
+// Columns per lane of the int16 kernel (one width for a whole call: pairs of
+// a pack share it).
+int choose_K16(const Overrides& ov, const Tuning* tu, int force = 0) {
+    if (ov.K16 == 1 || ov.K16 == 2) return ov.K16;
+    if (force) return force;
+    if (tu && tu->K16) return tu->K16;
     return 2;
 }
 
@@ -237,6 +262,11 @@ int64_t tb_bytes_of(int n, int m, int K) {
     const int nsteps = ((n + 64 + 63) / 64) * 64;
     const int nstrips = (m + 1 + 64 * K - 1) / (64 * K);
     return (int64_t)nstrips * (nsteps / 64) * kTbBlockBytes * K;
+}
+
+// Direction-bit bytes of a pair at the width that needs most.
+int64_t tb_bytes_max(int n, int m) {
+    return std::max({tb_bytes_of(n, m, 1), tb_bytes_of(n, m, 2), tb_bytes_of(n, m, 4)});
 }
 
 // Bound on |value| of reachable cells (see the public header): the largest
@@ -293,11 +323,26 @@ void make_dev_params(const mpg_params* p, DevParams* d) {
     std::memcpy(d->acceptor, p->acceptor, 125);
 }
 
+struct Timer;
+
+// How a call runs on the device.
+struct RunCfg {
+    uint64_t tb_budget = 0;
+    Timer* tm = nullptr;
+    int ncu = 256;      // compute units the DP grid may fill
+    bool serve = false; // results pair by pair: the finishing wavefront walks
+                        // the traceback and publishes the record (status
+                        // last) to memory the host polls; shortest pairs first
+    const Tuning* tune = nullptr;  // measured costs for choosing K
+    int force_K = 0, force_K16 = 0;  // calibration runs: one width for all
+};
+
 // Build the plan for the pairs idx[0..cnt) of a call with n pairs.  Each
 // job writes result record idx[k] and its op string at ops_off[idx[k]].
 void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
-                const std::vector<int64_t>& ops_off, Plan& P, uint64_t tb_budget,
-                bool shortest_first) {
+                const std::vector<int64_t>& ops_off, Plan& P, const RunCfg& cfg) {
+    const uint64_t tb_budget = cfg.tb_budget;
+    const bool shortest_first = cfg.serve;
     P.jobs.assign(cnt, PairJob{});
     P.row_start.assign(cnt, 0);
     P.groups.clear();
@@ -308,7 +353,8 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     const Overrides ov;
     const BoundInfo bound(p);
     const bool allow16 = (p->flags & MPG_ALLOW_I16) != 0 && p->mode == MPG_LOCAL;
-    const int K16 = choose_K16(ov);
+    const int K16 = choose_K16(ov, cfg.tune, cfg.force_K16);
+    const KChoice kc = choose_widths(ov, cfg.tune, cfg.force_K);
     std::vector<std::pair<int64_t, int32_t>> e16;
     for (int32_t k = 0; k < cnt; ++k) {
         const mpg_seg& s = segs[idx[k]];
@@ -323,7 +369,8 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         if (s.dlen < 0 || s.plen < 0 || s.dlen > MPG_MAX_DNA || s.plen > MPG_MAX_PROT ||
             !bound.ok(s.dlen, s.plen))
             J.status = MPG_E_RANGE;
-        const int K = choose_K(std::max(0, s.plen), ov);
+        const bool want_tb = ((s.flags | p->flags) & MPG_WANT_TB) != 0;
+        const int K = kc.K[want_tb ? 1 : 0];
         J.K = K;
         const int nn = std::max(0, J.n), mm = std::max(0, J.m);
         const int nsteps = ((nn + 64 + 63) / 64) * 64;
@@ -458,13 +505,17 @@ struct mpg_ctx {
     bool sched_running = false;
     size_t max_pending = 1 << 20;
     // slots 0..nshort-1 run short micro-batches, the rest long batches
-    int nshort = 2, nlong = 1;
-    int64_t short_cells = 200000000LL;    // cells per short micro-batch
+    int nshort = 3, nlong = 1;
+    int64_t short_cells = 2000000000LL;   // cells per short batch
     int64_t long_cells = 60000000000LL;   // cells per long batch
     double long_share = 1.0;              // device share of one long batch's grid
+    // serving strip widths: short jobs take the narrowest strips (shortest
+    // critical path per pair), long jobs the widest efficient ones
+    int serve_K_short = 1, serve_K_long = 2;
     int max_jobs_per_batch = 4096;
     mpg_stats stats{};
     uint64_t tb_in_use = 0;
+    Tuning tune;  // measured kernel costs (mpg_autotune)
 };
 
 namespace {
@@ -503,15 +554,6 @@ struct Timer {
     }
 };
 
-// How a call runs on the device.
-struct RunCfg {
-    uint64_t tb_budget = 0;
-    Timer* tm = nullptr;
-    int ncu = 256;      // compute units the DP grid may fill
-    bool serve = false; // results pair by pair: the finishing wavefront walks
-                        // the traceback and publishes the record (status
-                        // last) to memory the host polls; shortest pairs first
-};
 
 // Enqueue the pairs idx[0..cnt) of a call whose letters are on the device.
 int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
@@ -533,7 +575,7 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
         }
     } host_clock{tm, th0};
     Plan P;
-    plan_pairs(p, segs, idx, cnt, ops_off, P, tb_budget, cfg.serve);
+    plan_pairs(p, segs, idx, cnt, ops_off, P, cfg);
     DevParams DP;
     make_dev_params(p, &DP);
     // prepass list: planned pairs only, row_start ascending
@@ -690,11 +732,12 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
     std::vector<int32_t> idx;
     idx.reserve(n);
     int64_t acc = 0;
-    const Overrides ov;
+    // waves are sized with each pair's largest direction-bit need over the
+    // widths (the width is chosen per wave and cannot make it larger)
     for (int32_t k = 0; k < n; ++k) {
         const mpg_seg& s = segs[k];
         const int64_t b = (seg_tb(s, p) && s.plen >= 0 && s.dlen >= 0)
-                              ? tb_bytes_of(s.dlen, s.plen, choose_K(s.plen, ov))
+                              ? tb_bytes_max(s.dlen, s.plen)
                               : 0;
         if (b <= (int64_t)tb_budget && acc + b > (int64_t)tb_budget && !idx.empty()) {
             int rc = run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(),
@@ -803,6 +846,8 @@ int mpg_ctx_create(mpg_ctx** out, int device, uint64_t tb_budget_bytes, uint32_t
     if (const int v = env_int("MPG_SRV_SHORT_MCELLS")) c->short_cells = (int64_t)v * 1000000;
     if (const int v = env_int("MPG_SRV_LONG_SHARE_PCT")) c->long_share = std::min(v, 100) / 100.0;
     if (const int v = env_int("MPG_SRV_MAX_JOBS")) c->max_jobs_per_batch = std::max(1, v);
+    if (const int v = env_int("MPG_SRV_K_SHORT")) c->serve_K_short = (v == 1 || v == 2 || v == 4) ? v : 1;
+    if (const int v = env_int("MPG_SRV_K_LONG")) c->serve_K_long = (v == 1 || v == 2 || v == 4) ? v : 2;
     if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return MPG_E_DEVICE;
@@ -859,6 +904,7 @@ int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot
     cfg.tb_budget = ctx->tb_budget;
     cfg.tm = ctx->timing ? &tm : nullptr;
     cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
     return run_dev_waves(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, n, d_out, d_ops, cfg);
 }
 
@@ -949,7 +995,8 @@ int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pai
 // failed; then the rest complete with MPG_E_DEVICE).
 template <typename Deliver>
 int serve_batch(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pair* pairs,
-                int32_t n, uint64_t tb_budget, int ncu, Deliver deliver) {
+                int32_t n, uint64_t tb_budget, int ncu, const Tuning* tune, int force_K,
+                Deliver deliver) {
     std::vector<mpg_seg> segs(n);
     int64_t pbytes = 0, dbytes = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -987,6 +1034,8 @@ int serve_batch(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pa
     cfg.tb_budget = tb_budget;
     cfg.ncu = ncu;
     cfg.serve = true;
+    cfg.tune = tune;
+    cfg.force_K = force_K;
     rc = run_dev_waves(st, ws, p, d_seq, d_seq + pbytes, segs.data(), n,
                        (mpg_dev_result*)ws.prec.p, (char*)ws.pops.p, cfg);
     std::vector<char> got(n, 0);
@@ -1122,7 +1171,8 @@ void scheduler(mpg_ctx* c) {
         // a long batch's persistent grid is held to a share of the device, so
         // short micro-batches always find free wavefront slots
         const int ncu = cls >= 2 ? std::max(1, (int)(g_num_cu * c->long_share)) : g_num_cu;
-        workers[slot] = std::thread([c, slot, tb, ncu, params, &streams, &wss, &busy,
+        const int K = cls >= 2 ? c->serve_K_long : c->serve_K_short;
+        workers[slot] = std::thread([c, slot, tb, ncu, K, params, &streams, &wss, &busy,
                                      b = std::move(batch)]() mutable {
             hipSetDevice(c->device);
             std::vector<mpg_pair> pairs(b.size());
@@ -1166,7 +1216,7 @@ void scheduler(mpg_ctx* c) {
                 c->cv_done.notify_all();
             };
             serve_batch(streams[slot], wss[slot], &params, pairs.data(), (int32_t)pairs.size(),
-                        (uint64_t)tb + 1, ncu, deliver);
+                        (uint64_t)tb + 1, ncu, &c->tune, K, deliver);
             std::lock_guard<std::mutex> g(c->mu);
             c->tb_in_use -= (uint64_t)tb;
             c->stats.tb_bytes_in_use = c->tb_in_use;
@@ -1199,6 +1249,7 @@ int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, in
     cfg.tb_budget = ctx->tb_budget;
     cfg.tm = ctx->timing ? &tm : nullptr;
     cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
     return align_host(ctx->stream, ctx->ws, p, pairs, n, out, cfg);
 }
 
@@ -1217,7 +1268,7 @@ int mpg_submit(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pair, uint64_t
         return MPG_E_INVAL;
     }
     const bool tb = ((pair->flags | p->flags) & MPG_WANT_TB) != 0;
-    const int64_t tbb = tb ? tb_bytes_of(pair->dlen, pair->plen, choose_K(pair->plen, Overrides())) : 0;
+    const int64_t tbb = tb ? tb_bytes_max(pair->dlen, pair->plen) : 0;
     const int64_t cells = (int64_t)(pair->dlen + 64) * (pair->plen + 1);
     // a long job must fit the part of the budget long batches may use
     const uint64_t tb_limit = cells > mpg_ctx::kLongCells ? ctx->tb_budget - ctx->tb_budget / 8
@@ -1301,6 +1352,135 @@ int mpg_enable_timing(mpg_ctx* ctx, int on) {
     if (!ctx) return MPG_E_INVAL;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     ctx->timing = on != 0;
+    return MPG_OK;
+}
+
+int mpg_autotune(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot, const uint8_t* d_dna,
+                 const mpg_seg* segs, int32_t n, mpg_tuning* out) {
+    if (!ctx || n < 0 || (n > 0 && (!p || !segs))) return MPG_E_INVAL;
+    if (p && params_check_impl(p) != MPG_OK) return MPG_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Workspace ws;
+    int rc = MPG_OK;
+    hipStream_t st = ctx->stream;
+    mpg_params prm;
+    std::vector<mpg_seg> sg;
+    if (n > 0) {
+        prm = *p;
+        sg.assign(segs, segs + n);
+    } else {
+        // built-in sample: 1,024 pairs of 511 residues (no column padding at
+        // any width) against 4,096 nucleotides, half of them with traceback,
+        // letters from a fixed linear congruential sequence
+        const int32_t np = 1024, m = 511, len = 4096;
+        std::vector<uint8_t> seq((size_t)np * (m + len));
+        uint32_t x = 12345u;
+        const char* aa = "ARNDCQEGHILKMFPSTWYV";
+        for (size_t k = 0; k < (size_t)np * m; ++k) {
+            x = x * 1664525u + 1013904223u;
+            seq[k] = (uint8_t)aa[(x >> 16) % 20];
+        }
+        for (size_t k = (size_t)np * m; k < seq.size(); ++k) {
+            x = x * 1664525u + 1013904223u;
+            seq[k] = (uint8_t)"ACGT"[(x >> 16) & 3];
+        }
+        if ((rc = ws.seq.ensure(seq.size())) != MPG_OK) return rc;
+        if (hipMemcpyAsync(ws.seq.p, seq.data(), seq.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess) {
+            ws.release();
+            return MPG_E_DEVICE;
+        }
+        d_prot = (const uint8_t*)ws.seq.p;
+        d_dna = d_prot + (size_t)np * m;
+        sg.resize(np);
+        for (int32_t k = 0; k < np; ++k) {
+            sg[k].prot_off = (int64_t)k * m;
+            sg[k].dna_off = (int64_t)k * len;
+            sg[k].plen = m;
+            sg[k].dlen = len;
+            sg[k].flags = (k & 1) ? MPG_WANT_TB : 0;
+            sg[k]._pad = 0;
+        }
+        mpg_params_default(&prm);
+        n = np;
+    }
+    double cells = 0;
+    for (const auto& q : sg) cells += (double)std::max(0, q.plen) * std::max(0, q.dlen);
+    const int64_t ops_cap = mpg_ops_capacity(sg.data(), n);
+    if ((rc = ws.out.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK ||
+        (rc = ws.ops.ensure((size_t)ops_cap + 64)) != MPG_OK) {
+        ws.release();
+        return rc;
+    }
+    // DP time of the sample at one width (the second of two runs)
+    auto run = [&](int K, int K16, double& ms_out) -> int {
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> e3[3];
+        std::vector<hipEvent_t> pool;
+        double host = 0;
+        uint64_t i16 = 0;
+        Timer tm{{&e3[0], &e3[1], &e3[2]}, &pool, &host, &i16};
+        RunCfg cfg;
+        cfg.tb_budget = ctx->tb_budget;
+        cfg.ncu = g_num_cu;
+        cfg.force_K = K;
+        cfg.force_K16 = K16;
+        for (int rep = 0; rep < 2; ++rep) {
+            cfg.tm = rep ? &tm : nullptr;
+            const int r = run_dev_waves(st, ws, &prm, d_prot, d_dna, sg.data(), n,
+                                        (mpg_dev_result*)ws.out.p, (char*)ws.ops.p, cfg);
+            if (r != MPG_OK) return r;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+        double ms = 0;
+        for (auto& pr : e3[1]) {
+            float f = 0.f;
+            if (hipEventElapsedTime(&f, pr.first, pr.second) != hipSuccess) return MPG_E_DEVICE;
+            ms += f;
+        }
+        for (auto& v : e3)
+            for (auto& pr : v) {
+                hipEventDestroy(pr.first);
+                hipEventDestroy(pr.second);
+            }
+        for (auto e : pool) hipEventDestroy(e);
+        ms_out = ms;
+        return MPG_OK;
+    };
+    Tuning tu;
+    mpg_tuning res{};
+    const int Ks[3] = {1, 2, 4};
+    double best = 0;
+    for (int q = 0; q < 3 && rc == MPG_OK; ++q) {
+        double ms = 0;
+        rc = run(Ks[q], 2, ms);
+        if (rc != MPG_OK || ms <= 0) break;
+        res.gcups[q] = cells / (ms * 1e-3) / 1e9;
+        if (best == 0 || ms < best) {
+            best = ms;
+            tu.K = Ks[q];
+        }
+    }
+    if (rc == MPG_OK && (prm.flags & MPG_ALLOW_I16)) {
+        double b16 = 0;
+        for (int q = 0; q < 2 && rc == MPG_OK; ++q) {
+            double ms = 0;
+            rc = run(tu.K, q + 1, ms);
+            if (rc != MPG_OK || ms <= 0) break;
+            res.i16_gcups[q] = cells / (ms * 1e-3) / 1e9;
+            if (b16 == 0 || ms < b16) {
+                b16 = ms;
+                tu.K16 = q + 1;
+            }
+        }
+    }
+    hipStreamSynchronize(st);
+    ws.release();
+    if (rc != MPG_OK) return rc;
+    ctx->tune = tu;
+    res.K = tu.K;
+    res.K16 = tu.K16;
+    if (out) *out = res;
     return MPG_OK;
 }
 

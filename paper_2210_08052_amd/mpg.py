@@ -72,6 +72,11 @@ class mpg_timing(ctypes.Structure):
                 ("i16_pairs", ctypes.c_uint64)]
 
 
+class mpg_tuning(ctypes.Structure):
+    _fields_ = [("gcups", ctypes.c_double * 3), ("i16_gcups", ctypes.c_double * 2),
+                ("K", ctypes.c_int32), ("K16", ctypes.c_int32), ("_pad", ctypes.c_int32 * 2)]
+
+
 SEG_DTYPE = np.dtype([("prot_off", "<i8"), ("dna_off", "<i8"), ("plen", "<i4"),
                       ("dlen", "<i4"), ("flags", "<u4"), ("_pad", "<i4")])
 DEV_RESULT_DTYPE = np.dtype([("status", "<i4"), ("score", "<i4"), ("g_beg", "<i4"),
@@ -81,7 +86,8 @@ DEV_RESULT_DTYPE = np.dtype([("status", "<i4"), ("score", "<i4"), ("g_beg", "<i4
 EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_default",
            "mpg_params_check", "mpg_align_batch", "mpg_ops_capacity", "mpg_align_batch_dev",
            "mpg_sync", "mpg_submit", "mpg_poll", "mpg_cancel", "mpg_get_stats",
-           "mpg_result_release", "mpg_strerror", "mpg_enable_timing", "mpg_get_timing"]
+           "mpg_result_release", "mpg_strerror", "mpg_enable_timing", "mpg_get_timing",
+           "mpg_autotune"]
 
 _lib = None
 
@@ -126,6 +132,9 @@ def lib():
         L.mpg_result_release.restype = None
         L.mpg_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.mpg_get_timing.argtypes = [ctypes.c_void_p, P(mpg_timing), ctypes.c_int]
+        L.mpg_autotune.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                   P(mpg_tuning)]
         L.mpg_strerror.argtypes = [ctypes.c_int]
         L.mpg_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -259,6 +268,35 @@ class Context:
         res = [_result_dict(out[i]) for i in range(k)]
         lib().mpg_result_release(self.ptr, out, k)
         return res
+
+    def poll_raw(self, max_results: int = 4096, timeout_us: int = 0, keep=None):
+        """Like poll, but returns (job_id, t_arrive_ns, t_done_ns, status)
+        tuples, plus the full result dicts of the job ids in `keep` (fast path
+        for latency measurements)."""
+        out = (mpg_result * max_results)()
+        k = check(lib().mpg_poll(self.ptr, out, max_results, timeout_us), "mpg_poll")
+        res, full = [], {}
+        for i in range(k):
+            jid = int(out[i].job_id)
+            res.append((jid, int(out[i].t_arrive_ns), int(out[i].t_done_ns), out[i].status))
+            if keep is not None and jid in keep:
+                full[jid] = _result_dict(out[i])
+        lib().mpg_result_release(self.ptr, out, k)
+        return res, full
+
+    def autotune(self, p: mpg_params = None, d_prot=0, d_dna=0, segs=None) -> dict:
+        """mpg_autotune on a device-resident sample (segs: SEG_DTYPE array) or,
+        without one, on the built-in sample; returns rates and chosen widths."""
+        t = mpg_tuning()
+        if segs is None:
+            st = lib().mpg_autotune(self.ptr, None, None, None, None, 0, ctypes.byref(t))
+        else:
+            segs = np.ascontiguousarray(segs, dtype=SEG_DTYPE)
+            st = lib().mpg_autotune(self.ptr, ctypes.byref(p), ctypes.c_void_p(d_prot),
+                                    ctypes.c_void_p(d_dna), segs.ctypes.data_as(ctypes.c_void_p),
+                                    len(segs), ctypes.byref(t))
+        check(st, "mpg_autotune")
+        return {"gcups": list(t.gcups), "i16_gcups": list(t.i16_gcups), "K": t.K, "K16": t.K16}
 
     def cancel(self, job_id: int) -> int:
         return lib().mpg_cancel(self.ptr, ctypes.c_uint64(job_id))

@@ -326,3 +326,27 @@ def test_serving_results_arrive_per_pair():
     # the long job (first submitted) is not the first result out
     assert order.index(ids[0]) > 0
     assert got[ids[0]]["t_done_ns"] > min(got[i]["t_done_ns"] for i in ids[1:])
+
+
+def test_autotune_keeps_results():
+    """mpg_autotune times every kernel width (built-in sample, then a sample of
+    the caller's pairs); the width it keeps changes only speed: results still
+    equal the oracle's."""
+    import torch
+    pairs = _pairs(4321, n=30, max_prot=600, max_dna=1500)
+    with mpg.Context(0) as c:
+        rates = c.autotune()
+        print("autotune built-in", rates, flush=True)
+        assert all(v > 0 for v in rates["gcups"]) and rates["K"] in (1, 2, 4)
+        g, o = scorings(0, 0)
+        g.flags |= mpg.MPG_ALLOW_I16
+        pb, db, segs = mpg.pack_pairs([(p, d, k % 2 == 0) for k, (p, d) in enumerate(pairs)])
+        d_prot = torch.frombuffer(bytearray(pb), dtype=torch.uint8).to("cuda:0")
+        d_dna = torch.frombuffer(bytearray(db), dtype=torch.uint8).to("cuda:0")
+        rates = c.autotune(g, d_prot.data_ptr(), d_dna.data_ptr(), segs)
+        print("autotune sample", rates, flush=True)
+        assert rates["K"] in (1, 2, 4) and rates["K16"] in (1, 2)
+        for tb in (False, True):
+            gg, oo = scorings(0, 0)
+            compare(c, pairs, gg, oo, tb, label="autotuned tb=%d" % tb)
+        _i16_run(c, pairs, g, o, len(pairs))
