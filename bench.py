@@ -355,6 +355,10 @@ def main():
         sys.exit(2)
 
     if args.config == "serving":
+        # the serving scheduler runs seven streams (three short, four long
+        # lanes); give them hardware queues of their own (read when the HIP
+        # runtime starts, which is after this point: torch is imported later)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
         bench_serving(args)
         return
 

@@ -210,11 +210,14 @@ int mpg_sync(mpg_ctx *ctx);
  *
  * Scheduling: short and long jobs, with and without traceback, wait in four
  * queues.  Short jobs run in batches of up to 2e9 cells on three streams;
- * long jobs are gathered into batches of their own on a fourth stream, so a
- * short job never shares a launch with a long pair.  Within a batch every
- * pair completes on its own: the wavefront that finishes a pair's last strip
- * walks its traceback and publishes the result to host-mapped memory, and
- * the result is in mpg_poll at once, while the rest of the batch still runs.
+ * long jobs are gathered into batches of their own on four more streams, so
+ * a short job never shares a launch with a long pair, and new long pairs
+ * start while earlier ones still run.  Within a batch every pair completes on
+ * its own: the wavefront that finishes a pair's last strip walks its
+ * traceback and publishes the result to host-mapped memory, and the result
+ * is in mpg_poll at once, while the rest of the batch still runs.  The seven
+ * streams run concurrently only with as many hardware queues: start the
+ * process with GPU_MAX_HW_QUEUES of at least 8.
  */
 int mpg_submit(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pair, uint64_t *job_id);
 
@@ -256,6 +259,38 @@ int mpg_enable_timing(mpg_ctx *ctx, int on);
 
 /* Wait for the timed work, fill *t, and zero the counters if reset != 0. */
 int mpg_get_timing(mpg_ctx *ctx, mpg_timing *t, int reset);
+
+/* ---- planned batches: graph capture and replay ------------------------------ */
+
+typedef struct mpg_plan mpg_plan;
+
+/*
+ * Plan a device-resident batch once (as mpg_align_batch_dev, and bound to the
+ * same buffers: d_prot, d_dna, d_out, d_ops), so that it can be run many
+ * times with no host work.  All planning, allocation and uploads happen
+ * here; the plan owns its device workspace.  The direction bits of all
+ * traceback pairs must fit the context's traceback budget at once
+ * (MPG_E_RANGE otherwise).  Each run recomputes everything from the bound
+ * inputs, so the caller may change the letters in d_prot/d_dna between runs
+ * as long as the lengths stay the same.
+ */
+int mpg_plan_create(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot, const uint8_t *d_dna,
+                    const mpg_seg *segs, int32_t n, mpg_dev_result *d_out, char *d_ops,
+                    int64_t ops_cap, mpg_plan **plan);
+
+/* Run a plan on hip_stream (NULL = the context's stream): kernel launches
+ * only, no host synchronisation, allocation or memset, so the call may
+ * itself be captured into a caller's graph.  Once mpg_plan_graph has
+ * succeeded, the captured graph is replayed instead. */
+int mpg_plan_launch(mpg_plan *plan, void *hip_stream);
+
+/* Capture one run of the plan on hip_stream (a stream the caller created;
+ * not the null stream) into a hipGraph and instantiate it; later
+ * mpg_plan_launch calls replay it with one hipGraphLaunch. */
+int mpg_plan_graph(mpg_plan *plan, void *hip_stream);
+
+/* Wait for the plan's work and free it. */
+void mpg_plan_destroy(mpg_plan *plan);
 
 /* ---- autotuning ----------------------------------------------------------- */
 

@@ -85,12 +85,34 @@ int64_t now_ns() {
 }
 
 // ------------------------------------------------------------- device memory
+// Buffers outgrown while other work may be running.  hipFree and hipHostFree
+// wait for the whole device, so a serving workspace must not free while
+// batches run on other streams: it parks outgrown buffers here, and the
+// scheduler frees them when no batch is on the device.
+struct Retired {
+    std::mutex mu;
+    std::vector<void*> dev, host;
+    void flush() {
+        std::lock_guard<std::mutex> g(mu);
+        for (void* q : dev) hipFree(q);
+        for (void* q : host) hipHostFree(q);
+        dev.clear();
+        host.clear();
+    }
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    Retired* later = nullptr;  // set: park outgrown buffers instead of freeing
     int ensure(size_t bytes) {
         if (bytes <= cap) return MPG_OK;
-        if (p) hipFree(p);
+        if (p && later) {
+            std::lock_guard<std::mutex> g(later->mu);
+            later->dev.push_back(p);
+        } else if (p) {
+            hipFree(p);
+        }
         p = nullptr;
         cap = 0;
         size_t want = std::max<size_t>(bytes, 256);
@@ -121,9 +143,15 @@ struct HostBuf {  // pinned host memory
     // coherent: device writes become visible to the host while a kernel runs
     // (result records and op strings that the host polls)
     unsigned flags = hipHostMallocDefault;
+    Retired* later = nullptr;  // set: park outgrown buffers instead of freeing
     int ensure(size_t bytes) {
         if (bytes <= cap) return MPG_OK;
-        if (p) hipHostFree(p);
+        if (p && later) {
+            std::lock_guard<std::mutex> g(later->mu);
+            later->host.push_back(p);
+        } else if (p) {
+            hipHostFree(p);
+        }
         p = nullptr;
         cap = 0;
         size_t want = std::max<size_t>(bytes, 4096);
@@ -151,6 +179,12 @@ struct Workspace {
     DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops, state;
     HostBuf hplan, hseq, hout, hops;
     HostBuf prec, pops;  // serving: host-mapped records and op strings the host polls
+    void defer_frees(Retired* r) {
+        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state};
+        for (auto* b : d) b->later = r;
+        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops};
+        for (auto* b : h) b->later = r;
+    }
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork_ev = nullptr, join_ev[kSideStreams] = {};
     bool streams_ready = false;
@@ -505,13 +539,14 @@ struct mpg_ctx {
     bool sched_running = false;
     size_t max_pending = 1 << 20;
     // slots 0..nshort-1 run short micro-batches, the rest long batches
-    int nshort = 3, nlong = 1;
+    int nshort = 3, nlong = 4;
     int64_t short_cells = 2000000000LL;   // cells per short batch
     int64_t long_cells = 60000000000LL;   // cells per long batch
     double long_share = 1.0;              // device share of one long batch's grid
-    // serving strip widths: short jobs take the narrowest strips (shortest
-    // critical path per pair), long jobs the widest efficient ones
-    int serve_K_short = 1, serve_K_long = 2;
+    // serving strip widths: the narrowest strips give the shortest critical
+    // path per pair and, with long pairs split into more strips, the best
+    // overlap of long pairs in flight
+    int serve_K_short = 1, serve_K_long = 1;
     int max_jobs_per_batch = 4096;
     mpg_stats stats{};
     uint64_t tb_in_use = 0;
@@ -555,14 +590,33 @@ struct Timer {
 };
 
 
-// Enqueue the pairs idx[0..cnt) of a call whose letters are on the device.
-int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
+// A planned call: the plan, its device copies and where everything lives.
+struct Prepared {
+    Plan P;
+    DevParams DP;
+    int32_t cnt = 0;
+    size_t npjobs = 0, npacks = 0;
+    std::vector<size_t> goff;  // first item of each group
+    PairJob *d_jobs = nullptr, *d_pjobs = nullptr;
+    PackJob* d_packs = nullptr;
+    int64_t *d_starts = nullptr, *d_pkstarts = nullptr;
+    int2* d_items = nullptr;
+    int32_t* d_walk = nullptr;
+    void* d_pst = nullptr;
+    int *d_qhead = nullptr, *d_prog = nullptr;
+    const uint8_t *d_prot = nullptr, *d_dna = nullptr;
+    mpg_dev_result* d_out = nullptr;
+    char* d_ops = nullptr;
+};
+
+// Host part of a call: plan the pairs idx[0..cnt), size the workspace and
+// upload the plan (asynchronously on st).  Waits for earlier work on st,
+// since the staging buffer and workspace may still be in use.
+int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
             const uint8_t* d_dna, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
             const std::vector<int64_t>& ops_off, mpg_dev_result* d_out, char* d_ops,
-            const RunCfg& cfg) {
+            const RunCfg& cfg, Prepared& X) {
     Timer* tm = cfg.tm;
-    const int ncu = cfg.ncu;
-    const uint64_t tb_budget = cfg.tb_budget;
     const auto th0 = std::chrono::steady_clock::now();
     struct HostClock {
         Timer* tm;
@@ -574,10 +628,14 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
                                     .count();
         }
     } host_clock{tm, th0};
-    Plan P;
+    Plan& P = X.P;
     plan_pairs(p, segs, idx, cnt, ops_off, P, cfg);
-    DevParams DP;
-    make_dev_params(p, &DP);
+    make_dev_params(p, &X.DP);
+    X.cnt = cnt;
+    X.d_prot = d_prot;
+    X.d_dna = d_dna;
+    X.d_out = d_out;
+    X.d_ops = d_ops;
     // prepass list: planned pairs only, row_start ascending
     std::vector<PairJob> pjobs;
     std::vector<int64_t> pstarts;
@@ -588,17 +646,19 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
             pjobs.push_back(P.jobs[k]);
             pstarts.push_back(P.row_start[k]);
         }
+    X.npjobs = pjobs.size();
     const size_t npacks = P.packs.size();
+    X.npacks = npacks;
     if (tm && tm->i16)
-        for (const PackJob& X : P.packs) *tm->i16 += X.b >= 0 ? 2 : 1;
+        for (const PackJob& Q : P.packs) *tm->i16 += Q.b >= 0 ? 2 : 1;
     // work items of every launch, then the walk order (local job indices)
     std::vector<int2> items;
-    std::vector<size_t> goff;
+    X.goff.clear();
     for (auto& g : P.groups) {
-        goff.push_back(items.size());
+        X.goff.push_back(items.size());
         items.insert(items.end(), g.items.begin(), g.items.end());
     }
-    const size_t ngroups = P.groups.size();
+    if (P.groups.size() > 15) return MPG_E_INVAL;
 
     const size_t jobs_b = sizeof(PairJob) * (size_t)cnt;
     const size_t pj_b = sizeof(PairJob) * pjobs.size();
@@ -608,8 +668,7 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     const size_t pk_b = sizeof(PackJob) * npacks;
     const size_t pks_b = sizeof(int64_t) * npacks;
     int rc;
-    // the staging buffer and workspace may still be in use by earlier work
-    // (the wait is device time, not host time)
+    // the wait is device time, not host time
     const auto tw0 = std::chrono::steady_clock::now();
     if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
     host_clock.t0 += std::chrono::steady_clock::now() - tw0;
@@ -636,37 +695,51 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     uint8_t* h3 = h2 + ps_b + pks_b;
     std::memcpy(h3, items.data(), it_b);
     std::memcpy(h3 + it_b, P.walk.data(), wk_b);
-    PairJob* d_jobs = (PairJob*)ws.jobs.p;
-    PairJob* d_pjobs = (PairJob*)((uint8_t*)ws.jobs.p + jobs_b);
-    PackJob* d_packs = (PackJob*)((uint8_t*)ws.jobs.p + jobs_b + pj_b);
-    int64_t* d_starts = (int64_t*)ws.row_start.p;
-    int64_t* d_pkstarts = (int64_t*)((uint8_t*)ws.row_start.p + ps_b);
-    int2* d_items = (int2*)ws.order.p;
-    int32_t* d_walk = (int32_t*)((uint8_t*)ws.order.p + it_b);
+    X.d_jobs = (PairJob*)ws.jobs.p;
+    X.d_pjobs = (PairJob*)((uint8_t*)ws.jobs.p + jobs_b);
+    X.d_packs = (PackJob*)((uint8_t*)ws.jobs.p + jobs_b + pj_b);
+    X.d_starts = (int64_t*)ws.row_start.p;
+    X.d_pkstarts = (int64_t*)((uint8_t*)ws.row_start.p + ps_b);
+    X.d_items = (int2*)ws.order.p;
+    X.d_walk = (int32_t*)((uint8_t*)ws.order.p + it_b);
     uint8_t* d_state = (uint8_t*)ws.state.p;
-    void* d_pst = d_state;
-    int* d_qhead = (int*)(d_state + (size_t)kPairStateBytes * cnt);  // one per launch
-    int* d_prog = d_qhead + 16;
+    X.d_pst = d_state;
+    X.d_qhead = (int*)(d_state + (size_t)kPairStateBytes * cnt);  // one per launch
+    X.d_prog = X.d_qhead + 16;
     hipError_t e = hipSuccess;
     if (jobs_b + pj_b + pk_b)
         e = hipMemcpyAsync(ws.jobs.p, h, jobs_b + pj_b + pk_b, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && ps_b + pks_b)
-        e = hipMemcpyAsync(d_starts, h2, ps_b + pks_b, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(X.d_starts, h2, ps_b + pks_b, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && it_b + wk_b)
         e = hipMemcpyAsync(ws.order.p, h3, it_b + wk_b, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return MPG_E_DEVICE;
+    return MPG_OK;
+}
 
-    const DpSink sink{d_out, d_ops, cfg.serve ? 1 : 0, cfg.serve ? 1 : 0};
-    if (launch_status(st, d_jobs, cnt, sink) != hipSuccess) return MPG_E_DEVICE;
+// Device part of a call: only kernel launches (and, with `fork`, event
+// record/wait to run the kernel variants concurrently on side streams), no
+// host synchronisation, allocation or memset, so it may be captured into a
+// graph (with fork = false).
+int enqueue(hipStream_t st, Workspace& ws, const Prepared& X, const RunCfg& cfg, bool fork) {
+    Timer* tm = cfg.tm;
+    const Plan& P = X.P;
+    const DevParams& DP = X.DP;
+    const size_t ngroups = P.groups.size();
+    int rc;
+    const DpSink sink{X.d_out, X.d_ops, cfg.serve ? 1 : 0, cfg.serve ? 1 : 0};
+    if (launch_status(st, X.d_jobs, X.cnt, sink) != hipSuccess) return MPG_E_DEVICE;
     const int neg_init = -(1 << 30);
-    if (launch_init(st, d_jobs, cnt, d_pst, d_prog, d_qhead, 16, neg_init) != hipSuccess)
+    if (launch_init(st, X.d_jobs, X.cnt, X.d_pst, X.d_prog, X.d_qhead, 16, neg_init) !=
+        hipSuccess)
         return MPG_E_DEVICE;
     if (tm) tm->begin(st, 0);
-    if (launch_prepass(st, d_pjobs, d_starts, (int)pjobs.size(), P.total_rows, d_dna,
+    if (launch_prepass(st, X.d_pjobs, X.d_starts, (int)X.npjobs, P.total_rows, X.d_dna,
                        (uint8_t*)ws.desc.p, DP) != hipSuccess)
         return MPG_E_DEVICE;
-    if (npacks && launch_prepass16(st, d_jobs, d_packs, d_pkstarts, (int)npacks, P.pack_rows,
-                                   d_dna, (uint8_t*)ws.desc.p, d_prog, DP) != hipSuccess)
+    if (X.npacks &&
+        launch_prepass16(st, X.d_jobs, X.d_packs, X.d_pkstarts, (int)X.npacks, P.pack_rows,
+                         X.d_dna, (uint8_t*)ws.desc.p, X.d_prog, DP) != hipSuccess)
         return MPG_E_DEVICE;
     if (tm) tm->end(st, 0);
     if (tm) tm->begin(st, 1);
@@ -674,16 +747,16 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
         const Group& G = P.groups[g];
         const int nit = (int)G.items.size();
         if (G.i16)
-            return launch_dp16(s2, G.K, ncu, DP, d_jobs, d_packs, d_items + goff[g], nit,
-                               d_qhead + g, d_pst, d_prog, d_prot, (const uint8_t*)ws.desc.p,
-                               (int2*)ws.bnd.p, sink);
-        return launch_dp(s2, G.K, G.tb, ncu, DP, d_jobs, d_items + goff[g], nit,
-                         d_qhead + g, d_pst, d_prog, d_prot, (const uint8_t*)ws.desc.p,
+            return launch_dp16(s2, G.K, cfg.ncu, DP, X.d_jobs, X.d_packs, X.d_items + X.goff[g],
+                               nit, X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot,
+                               (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, sink);
+        return launch_dp(s2, G.K, G.tb, cfg.ncu, DP, X.d_jobs, X.d_items + X.goff[g], nit,
+                         X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot, (const uint8_t*)ws.desc.p,
                          (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, sink);
     };
-    if (ngroups > 15) return MPG_E_INVAL;
-    if (ngroups == 1) {
-        if (launch_group(st, 0) != hipSuccess) return MPG_E_DEVICE;
+    if (ngroups == 1 || (ngroups > 1 && !fork)) {
+        for (size_t g = 0; g < ngroups; ++g)
+            if (launch_group(st, g) != hipSuccess) return MPG_E_DEVICE;
     } else if (ngroups > 1) {
         // fork: every variant's launch starts after the prepass, concurrently
         if ((rc = ws.ensure_streams()) != MPG_OK) return rc;
@@ -702,12 +775,23 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     if (tm) tm->end(st, 1);
     if (!P.walk.empty() && !cfg.serve) {
         if (tm) tm->begin(st, 2);
-        e = launch_walk(st, d_jobs, d_walk, (int)P.walk.size(), (const uint8_t*)ws.tb.p, d_out,
-                        d_ops);
-        if (e != hipSuccess) return MPG_E_DEVICE;
+        if (launch_walk(st, X.d_jobs, X.d_walk, (int)P.walk.size(), (const uint8_t*)ws.tb.p,
+                        X.d_out, X.d_ops) != hipSuccess)
+            return MPG_E_DEVICE;
         if (tm) tm->end(st, 2);
     }
     return MPG_OK;
+}
+
+// Enqueue the pairs idx[0..cnt) of a call whose letters are on the device.
+int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
+            const uint8_t* d_dna, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
+            const std::vector<int64_t>& ops_off, mpg_dev_result* d_out, char* d_ops,
+            const RunCfg& cfg) {
+    Prepared X;
+    int rc = prepare(st, ws, p, d_prot, d_dna, segs, idx, cnt, ops_off, d_out, d_ops, cfg, X);
+    if (rc != MPG_OK) return rc;
+    return enqueue(st, ws, X, cfg, true);
 }
 
 bool seg_tb(const mpg_seg& s, const mpg_params* p) {
@@ -1113,12 +1197,22 @@ void scheduler(mpg_ctx* c) {
     std::vector<Workspace> wss(ns);
     std::vector<bool> busy(ns, false);
     std::vector<std::thread> workers(ns);
-    for (int k = 0; k < ns; ++k) hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking);
+    Retired retired;
+    for (int k = 0; k < ns; ++k) {
+        hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking);
+        wss[k].defer_frees(&retired);
+    }
     std::unique_lock<std::mutex> lk(c->mu);
     for (;;) {
         bool any_busy = false;
         for (int k = 0; k < ns; ++k) any_busy |= busy[k];
         if (c->stop && c->npending == 0 && !any_busy) break;
+        if (!any_busy) {
+            // nothing on the device: outgrown buffers can go now
+            lk.unlock();
+            retired.flush();
+            lk.lock();
+        }
         int slot = -1, cls = -1;
         for (int k = 0; k < ns && cls < 0; ++k) {
             if (busy[k]) continue;
@@ -1227,7 +1321,11 @@ void scheduler(mpg_ctx* c) {
     lk.unlock();
     for (auto& w : workers)
         if (w.joinable()) w.join();
-    for (auto& w : wss) w.release();
+    retired.flush();
+    for (auto& w : wss) {
+        w.defer_frees(nullptr);
+        w.release();
+    }
     for (auto& s : streams) hipStreamDestroy(s);
 }
 
@@ -1482,6 +1580,104 @@ int mpg_autotune(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot, const
     res.K16 = tu.K16;
     if (out) *out = res;
     return MPG_OK;
+}
+
+// ---- planned batches (graph capture and replay)
+}  // extern "C"
+
+struct mpg_plan {
+    mpg_ctx* ctx = nullptr;
+    Workspace ws;
+    Prepared X;
+    RunCfg cfg;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int mpg_plan_create(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot,
+                    const uint8_t* d_dna, const mpg_seg* segs, int32_t n, mpg_dev_result* d_out,
+                    char* d_ops, int64_t ops_cap, mpg_plan** plan) {
+    if (!ctx || !p || !plan || n < 0 || (n > 0 && (!segs || !d_out))) return MPG_E_INVAL;
+    *plan = nullptr;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    const int64_t need = mpg_ops_capacity(segs, n);
+    if (need > 0 && (!d_ops || ops_cap < need)) return MPG_E_RANGE;
+    std::vector<int64_t> ops_off(n);
+    int64_t o = 0, tbb = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        ops_off[k] = o;
+        const bool tb = seg_tb(segs[k], p);
+        o += tb ? 2 * ((int64_t)std::max(0, segs[k].dlen) + std::max(0, segs[k].plen)) + 1 : 1;
+        if (tb && segs[k].plen >= 0 && segs[k].dlen >= 0) tbb += tb_bytes_max(segs[k].dlen, segs[k].plen);
+    }
+    // one launch sequence: all direction bits must fit the budget at once
+    if ((uint64_t)tbb > ctx->tb_budget) return MPG_E_RANGE;
+    mpg_plan* pl = new (std::nothrow) mpg_plan();
+    if (!pl) return MPG_E_NOMEM;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    pl->ctx = ctx;
+    pl->cfg.tb_budget = ctx->tb_budget;
+    pl->cfg.ncu = g_num_cu;
+    pl->cfg.tune = &ctx->tune;
+    std::vector<int32_t> idx(n);
+    for (int32_t k = 0; k < n; ++k) idx[k] = k;
+    rc = prepare(ctx->stream, pl->ws, p, d_prot, d_dna, segs, idx.data(), n, ops_off, d_out,
+                 d_ops, pl->cfg, pl->X);
+    if (rc == MPG_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = MPG_E_DEVICE;
+    if (rc != MPG_OK) {
+        pl->ws.release();
+        delete pl;
+        return rc;
+    }
+    *plan = pl;
+    return MPG_OK;
+}
+
+int mpg_plan_launch(mpg_plan* plan, void* hip_stream) {
+    if (!plan) return MPG_E_INVAL;
+    hipSetDevice(plan->ctx->device);
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : plan->ctx->stream;
+    if (plan->exec) return hipGraphLaunch(plan->exec, st) == hipSuccess ? MPG_OK : MPG_E_DEVICE;
+    return enqueue(st, plan->ws, plan->X, plan->cfg, false);
+}
+
+int mpg_plan_graph(mpg_plan* plan, void* hip_stream) {
+    if (!plan || !hip_stream) return MPG_E_INVAL;
+    if (plan->exec) return MPG_OK;
+    hipSetDevice(plan->ctx->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return MPG_E_DEVICE;
+    const int rc = enqueue(st, plan->ws, plan->X, plan->cfg, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != MPG_OK || e != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return rc != MPG_OK ? rc : MPG_E_DEVICE;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return MPG_E_DEVICE;
+    }
+    plan->graph = g;
+    plan->exec = x;
+    return MPG_OK;
+}
+
+void mpg_plan_destroy(mpg_plan* plan) {
+    if (!plan) return;
+    hipSetDevice(plan->ctx->device);
+    hipStreamSynchronize(plan->ctx->stream);
+    if (plan->exec) hipGraphExecDestroy(plan->exec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    hipDeviceSynchronize();
+    plan->ws.release();
+    delete plan;
 }
 
 int mpg_get_timing(mpg_ctx* ctx, mpg_timing* t, int reset) {

@@ -87,7 +87,8 @@ EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_de
            "mpg_params_check", "mpg_align_batch", "mpg_ops_capacity", "mpg_align_batch_dev",
            "mpg_sync", "mpg_submit", "mpg_poll", "mpg_cancel", "mpg_get_stats",
            "mpg_result_release", "mpg_strerror", "mpg_enable_timing", "mpg_get_timing",
-           "mpg_autotune"]
+           "mpg_autotune", "mpg_plan_create", "mpg_plan_launch", "mpg_plan_graph",
+           "mpg_plan_destroy"]
 
 _lib = None
 
@@ -135,6 +136,14 @@ def lib():
         L.mpg_autotune.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    P(mpg_tuning)]
+        L.mpg_plan_create.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      P(ctypes.c_void_p)]
+        L.mpg_plan_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.mpg_plan_graph.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.mpg_plan_destroy.argtypes = [ctypes.c_void_p]
+        L.mpg_plan_destroy.restype = None
         L.mpg_strerror.argtypes = [ctypes.c_int]
         L.mpg_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -298,6 +307,16 @@ class Context:
         check(st, "mpg_autotune")
         return {"gcups": list(t.gcups), "i16_gcups": list(t.i16_gcups), "K": t.K, "K16": t.K16}
 
+    def plan(self, p: mpg_params, d_prot, d_dna, segs: np.ndarray, d_out, d_ops, ops_cap: int):
+        """mpg_plan_create: a Plan bound to these device buffers."""
+        segs = np.ascontiguousarray(segs, dtype=SEG_DTYPE)
+        h = ctypes.c_void_p()
+        check(lib().mpg_plan_create(self.ptr, ctypes.byref(p), ctypes.c_void_p(d_prot),
+                                    ctypes.c_void_p(d_dna), segs.ctypes.data_as(ctypes.c_void_p),
+                                    len(segs), ctypes.c_void_p(d_out), ctypes.c_void_p(d_ops),
+                                    int(ops_cap), ctypes.byref(h)), "mpg_plan_create")
+        return Plan(h)
+
     def cancel(self, job_id: int) -> int:
         return lib().mpg_cancel(self.ptr, ctypes.c_uint64(job_id))
 
@@ -305,6 +324,31 @@ class Context:
         s = mpg_stats()
         check(lib().mpg_get_stats(self.ptr, ctypes.byref(s)), "mpg_get_stats")
         return {k: int(getattr(s, k)) for k, _ in mpg_stats._fields_}
+
+
+class Plan:
+    """A planned batch (mpg_plan_*): launch, capture into a graph, replay."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    def launch(self, stream_handle: int = 0):
+        check(lib().mpg_plan_launch(self.h, ctypes.c_void_p(stream_handle or None)),
+              "mpg_plan_launch")
+
+    def graph(self, stream_handle: int):
+        check(lib().mpg_plan_graph(self.h, ctypes.c_void_p(stream_handle)), "mpg_plan_graph")
+
+    def close(self):
+        if self.h:
+            lib().mpg_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _result_dict(r: mpg_result) -> dict:

@@ -350,3 +350,60 @@ def test_autotune_keeps_results():
             gg, oo = scorings(0, 0)
             compare(c, pairs, gg, oo, tb, label="autotuned tb=%d" % tb)
         _i16_run(c, pairs, g, o, len(pairs))
+
+
+def test_plan_graph_replay(ctx):
+    """A planned batch (mpg_plan_*) gives the eager call's results when
+    launched directly and when captured into a hipGraph and replayed; every
+    replay (with eager work and synchronisation between them) is checked."""
+    import torch
+    pairs = _pairs(5150, n=50, max_prot=300, max_dna=1500)
+    g, _ = scorings(0, 0)
+    pb, db, segs = mpg.pack_pairs([(p, d, k % 2 == 0) for k, (p, d) in enumerate(pairs)])
+    dev = torch.device("cuda:0")
+    d_prot = torch.frombuffer(bytearray(pb), dtype=torch.uint8).to(dev)
+    d_dna = torch.frombuffer(bytearray(db), dtype=torch.uint8).to(dev)
+    cap = mpg.lib().mpg_ops_capacity(segs.ctypes.data, len(segs))
+    nrec = len(pairs) * mpg.DEV_RESULT_DTYPE.itemsize
+
+    def run_eager():
+        d_out = torch.zeros(nrec, dtype=torch.uint8, device=dev)
+        d_ops = torch.zeros(cap, dtype=torch.uint8, device=dev)
+        ctx.align_batch_dev(g, d_prot.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
+                            d_ops.data_ptr(), cap)
+        ctx.sync()
+        return d_out.cpu().numpy().tobytes(), d_ops.cpu().numpy().tobytes()
+
+    def results(rec, ops):
+        out = np.frombuffer(rec, dtype=mpg.DEV_RESULT_DTYPE)
+        res = []
+        for k in range(len(out)):
+            o0, ln = int(out["ops_off"][k]), int(out["ops_len"][k])
+            res.append((int(out["status"][k]), int(out["score"][k]), int(out["g_end"][k]),
+                        int(out["p_end"][k]), int(out["g_beg"][k]), int(out["p_beg"][k]),
+                        ops[o0:o0 + ln] if k % 2 == 0 else b""))
+        return res
+
+    ref = results(*run_eager())
+    d_out = torch.zeros(nrec, dtype=torch.uint8, device=dev)
+    d_ops = torch.zeros(cap, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    plan = ctx.plan(g, d_prot.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
+                    d_ops.data_ptr(), cap)
+    try:
+        plan.launch(stream.cuda_stream)
+        stream.synchronize()
+        assert results(d_out.cpu().numpy().tobytes(), d_ops.cpu().numpy().tobytes()) == ref
+        plan.graph(stream.cuda_stream)
+        for rep in range(3):
+            d_out.zero_()
+            d_ops.zero_()
+            x = torch.arange(1000, device=dev).sum()  # eager work between replays
+            torch.cuda.synchronize()
+            assert int(x) == 499500
+            plan.launch(stream.cuda_stream)
+            stream.synchronize()
+            got = results(d_out.cpu().numpy().tobytes(), d_ops.cpu().numpy().tobytes())
+            assert got == ref, "graph replay %d differs" % rep
+    finally:
+        plan.close()
