@@ -43,9 +43,12 @@ METRIC = "GCUPS batched spliced DP (bit-exact) + p50/p99 latency at fixed arriva
 # recorded by rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs in profiles/.  The
 # figure is reported only while the kernel sources still hash to the value
 # recorded beside it (otherwise the counters describe an older kernel).
-TRAFFIC_PROFILE = {"batch": "dp_kernel_k2_local_score__batch10k.md"}
-DP_SOURCES = ["paper_2210_08052_amd/csrc/mpg_dp.h", "paper_2210_08052_amd/csrc/mpg_internal.h",
-              "paper_2210_08052_amd/csrc/mpg_dp_k2.hip"]
+TRAFFIC_PROFILE = {"batch": "dp_kernel_k2_local_score__batch10k.md",
+                   "traceback": "dp_kernel_local_traceback__traceback10k.md",
+                   "batch16": "dp16_kernel_k2_local_score__batch10k.md"}
+DP_SOURCES = ["paper_2210_08052_amd/csrc/" + f for f in
+              ("mpg_dp.h", "mpg_internal.h", "mpg_walk.h", "mpg_dp_k1.hip", "mpg_dp_k2.hip",
+               "mpg_dp_k4.hip", "mpg_dp16.hip")]
 
 
 def log(*a):

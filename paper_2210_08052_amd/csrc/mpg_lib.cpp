@@ -1331,6 +1331,61 @@ void scheduler(mpg_ctx* c) {
 
 }  // namespace
 
+// Coding sequence of one traced alignment (Methods, "Avoiding pseudogenes"):
+// the genome bases the op string consumes, in path order, without the
+// interior of any intron.  A phase-0 intron (N) contributes nothing; a
+// phase-1 intron with its split codon (U) keeps the codon's first base and
+// its last two, a phase-2 one (V) its first two and its last one; a U/V token
+// shorter than a codon keeps its bases.  Returns false for an op string that
+// does not span exactly [g_beg, g_end) x [p_beg, p_end) of the pair.
+bool coding_sequence(const mpg_pair& pr, const mpg_result& r, std::string& cds, int32_t& introns) {
+    cds.clear();
+    introns = 0;
+    if (r.g_beg < 0 || r.p_beg < 0 || r.g_end > pr.dlen || r.p_end > pr.plen ||
+        r.g_beg > r.g_end || r.p_beg > r.p_end)
+        return false;
+    int64_t g = r.g_beg, res = r.p_beg;
+    const char* s = r.ops;
+    const char* end = r.ops + r.ops_len;
+    while (s < end) {
+        int64_t L = 0;
+        const char* d0 = s;
+        while (s < end && *s >= '0' && *s <= '9' && L <= MPG_MAX_DNA) L = L * 10 + (*s++ - '0');
+        if (s == d0 || s == end || L <= 0 || L > MPG_MAX_DNA) return false;
+        const char op = *s++;
+        int64_t nt = 0, aa = 0;
+        switch (op) {
+            case 'M': nt = 3 * L; aa = L; break;
+            case 'D': nt = 3 * L; break;
+            case 'I': aa = L; break;
+            case 'F': nt = L; aa = 1; break;
+            case 'G': nt = L; break;
+            case 'N': nt = L; break;
+            case 'U': case 'V': nt = L; aa = 1; break;
+            default: return false;
+        }
+        if (g + nt > r.g_end || res + aa > r.p_end) return false;
+        const char* b = pr.dna + g;
+        if (op == 'M' || op == 'D' || op == 'F' || op == 'G') {
+            cds.append(b, (size_t)nt);
+        } else if (op != 'I') {
+            ++introns;
+            if (op == 'U' && L >= 3) {
+                cds.push_back(b[0]);
+                cds.append(b + L - 2, 2);
+            } else if (op == 'V' && L >= 3) {
+                cds.append(b, 2);
+                cds.push_back(b[L - 1]);
+            } else if (op != 'N') {
+                cds.append(b, (size_t)L);
+            }
+        }
+        g += nt;
+        res += aa;
+    }
+    return g == r.g_end && res == r.p_end;
+}
+
 extern "C" {
 
 int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, int32_t n,
@@ -1349,6 +1404,65 @@ int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, in
     cfg.ncu = g_num_cu;
     cfg.tune = &ctx->tune;
     return align_host(ctx->stream, ctx->ws, p, pairs, n, out, cfg);
+}
+
+int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs,
+                        const mpg_result* res, int32_t n, int32_t* score, int32_t* exons,
+                        int32_t* status) {
+    if (!ctx || !p || n < 0 || (n > 0 && (!pairs || !res || !score || !exons || !status)))
+        return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    mpg_params p2 = *p;  // the second alignment: end to end, no intron states
+    p2.mode = MPG_GLOBAL;
+    p2.flags = (p->flags | MPG_NO_INTRON) & ~(uint32_t)(MPG_WANT_TB | MPG_ALLOW_I16);
+    std::vector<std::string> cds;
+    std::vector<int32_t> idx;
+    std::vector<mpg_pair> sub;
+    cds.reserve((size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        score[k] = 0;
+        exons[k] = 0;
+        status[k] = res[k].status;
+        if (res[k].status != MPG_OK) continue;
+        if (!res[k].ops || (pairs[k].dlen && !pairs[k].dna) || (pairs[k].plen && !pairs[k].prot))
+            return MPG_E_INVAL;
+        std::string c;
+        int32_t introns = 0;
+        if (!coding_sequence(pairs[k], res[k], c, introns)) return MPG_E_INVAL;
+        exons[k] = introns + 1;
+        cds.push_back(std::move(c));
+        idx.push_back(k);
+    }
+    for (size_t t = 0; t < idx.size(); ++t) {
+        const mpg_result& r = res[idx[t]];
+        mpg_pair q;
+        q.prot = pairs[idx[t]].prot + r.p_beg;
+        q.plen = r.p_end - r.p_beg;
+        q.dna = cds[t].data();
+        q.dlen = (int32_t)cds[t].size();
+        q.flags = 0;
+        sub.push_back(q);
+    }
+    if (sub.empty()) return MPG_OK;
+    std::vector<mpg_result> out(sub.size());
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16};
+    ctx->n_calls++;
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.tm = ctx->timing ? &tm : nullptr;
+    cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
+    rc = align_host(ctx->stream, ctx->ws, &p2, sub.data(), (int32_t)sub.size(), out.data(), cfg);
+    if (rc != MPG_OK) return rc;
+    for (size_t t = 0; t < idx.size(); ++t) {
+        const int32_t k = idx[t];
+        status[k] = out[t].status;
+        if (out[t].status == MPG_OK) score[k] = out[t].score - (exons[k] == 1 ? p->r : 0);
+    }
+    return MPG_OK;
 }
 
 int mpg_submit(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pair, uint64_t* job_id) {

@@ -88,7 +88,7 @@ EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_de
            "mpg_sync", "mpg_submit", "mpg_poll", "mpg_cancel", "mpg_get_stats",
            "mpg_result_release", "mpg_strerror", "mpg_enable_timing", "mpg_get_timing",
            "mpg_autotune", "mpg_plan_create", "mpg_plan_launch", "mpg_plan_graph",
-           "mpg_plan_destroy"]
+           "mpg_plan_destroy", "mpg_rescore_spliced"]
 
 _lib = None
 
@@ -144,6 +144,9 @@ def lib():
         L.mpg_plan_graph.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.mpg_plan_destroy.argtypes = [ctypes.c_void_p]
         L.mpg_plan_destroy.restype = None
+        L.mpg_rescore_spliced.argtypes = [ctypes.c_void_p, P(mpg_params), P(mpg_pair),
+                                          P(mpg_result), ctypes.c_int32, P(ctypes.c_int32),
+                                          P(ctypes.c_int32), P(ctypes.c_int32)]
         L.mpg_strerror.argtypes = [ctypes.c_int]
         L.mpg_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -238,6 +241,32 @@ class Context:
         res = [_result_dict(out[k]) for k in range(n)]
         lib().mpg_result_release(self.ptr, out, n)
         return res
+
+    def rescore_spliced(self, pairs, results, p: mpg_params):
+        """Pseudogene guard for traced results of align_batch on the same
+        pairs: a list of (status, score, exons) per pair."""
+        n = len(pairs)
+        arr = (mpg_pair * max(n, 1))()
+        res = (mpg_result * max(n, 1))()
+        keep = []
+        for k, (pr, r) in enumerate(zip(pairs, results)):
+            prot = pr[0].encode() if isinstance(pr[0], str) else bytes(pr[0])
+            dna = pr[1].encode() if isinstance(pr[1], str) else bytes(pr[1])
+            ops = r["ops"].encode() if r.get("ops") is not None else None
+            keep.append((prot, dna, ops))
+            arr[k].prot, arr[k].plen, arr[k].dna, arr[k].dlen = prot, len(prot), dna, len(dna)
+            res[k].status, res[k].score = r["status"], r["score"]
+            res[k].g_beg, res[k].g_end = r["g_beg"], r["g_end"]
+            res[k].p_beg, res[k].p_end = r["p_beg"], r["p_end"]
+            if ops is not None:
+                res[k].ops = ctypes.cast(ctypes.c_char_p(ops), ctypes.c_void_p).value
+                res[k].ops_len = len(ops)
+        sc = (ctypes.c_int32 * max(n, 1))()
+        ex = (ctypes.c_int32 * max(n, 1))()
+        st = (ctypes.c_int32 * max(n, 1))()
+        check(lib().mpg_rescore_spliced(self.ptr, ctypes.byref(p), arr, res, n, sc, ex, st),
+              "mpg_rescore_spliced")
+        return [(st[k], sc[k], ex[k]) for k in range(n)]
 
     # ---- device-resident batch (torch tensors for memory only)
     def align_batch_dev(self, p: mpg_params, d_prot, d_dna, segs: np.ndarray, d_out, d_ops,

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import pseudo
 from paper_2210_08052_amd import mpg
 from paper_2210_08052_amd import workloads as W
 
@@ -407,3 +408,41 @@ def test_plan_graph_replay(ctx):
             assert got == ref, "graph replay %d differs" % rep
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("mode,flags,rs", [(0, 0, None), (1, 0, None), (0, 2, None),
+                                           (0, 0, 501), (1, 2, 502)])
+def test_rescore_spliced(ctx, mode, flags, rs):
+    """Pseudogene guard: the HIP path (first alignment, coding-sequence cut
+    and end-to-end second alignment) against the oracle's, pair by pair."""
+    print("case rescore mode=%d flags=%d rs=%s" % (mode, flags, rs), flush=True)
+    g, o = scorings(mode, flags, rand_seed=rs)
+    pairs = [(p.prot, p.dna) for p in W.batch_pairs(16, seed=60 + (rs or 0) + mode)]
+    pairs += _pairs(70 + mode, n=16, max_prot=120, max_dna=600)
+    pairs.append((b"M", b"ATG"))
+    got = ctx.align_batch(pairs, g, want_tb=True)
+    want = [oracle.align(pr[0].decode(), pr[1].decode(), o, want_tb=True) for pr in pairs]
+    rescored = ctx.rescore_spliced(pairs, got, g)
+    seen = {"introns": 0, "single": 0}
+    for k, (pr, r) in enumerate(zip(pairs, want)):
+        st, sc, ex = pseudo.pseudo_rescore(pr[0].decode(), pr[1].decode(), r, o)
+        if r.status != oracle.OK:
+            assert rescored[k] == (r.status, 0, 0)
+            continue
+        assert rescored[k][0] == st, (k, rescored[k], st)
+        if st == oracle.OK:
+            assert rescored[k] == (0, sc, ex), (k, rescored[k], (st, sc, ex), r.ops)
+        seen["introns" if ex > 1 else "single"] += 1
+    assert seen["introns"] > 0 and seen["single"] > 0, seen
+
+
+def test_rescore_spliced_rejects_bad_ops(ctx):
+    g, _ = scorings(0, 0)
+    pairs = [(b"MKV", b"ATGAAAGTT")]
+    r = ctx.align_batch(pairs, g, want_tb=True)[0]
+    assert r["status"] == 0
+    bad = dict(r, ops=r["ops"] + "1M")  # consumes past the end cell
+    with pytest.raises(RuntimeError):
+        ctx.rescore_spliced(pairs, [bad], g)
+    assert ctx.rescore_spliced(pairs, [dict(r, status=mpg.MPG_E_NOALN)], g) == \
+        [(mpg.MPG_E_NOALN, 0, 0)]
