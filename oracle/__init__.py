@@ -28,7 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mpg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-LOCAL, EXTEND, GLOBAL = 0, 1, 2
+LOCAL, EXTEND, GLOBAL, EXTEND_LEFT = 0, 1, 2, 3
 NO_INTRON, NO_FS = 1, 2
 OK, E_NOALN = 0, -6
 

@@ -46,15 +46,16 @@ def _enc_aa(s: str):
 
 
 def best_score(prot: str, dna: str, sc) -> float:
-    """Maximum path score for ``sc.mode`` (LOCAL=0, EXTEND=1, GLOBAL=2);
-    -inf when GLOBAL has no path."""
+    """Maximum path score for ``sc.mode`` (LOCAL=0, EXTEND=1, GLOBAL=2,
+    EXTEND_LEFT=3: start anywhere, end at (n, m)); -inf when GLOBAL has no
+    path."""
     T = [4] + _enc_dna(dna)   # 1-based
     P = [22] + _enc_aa(prot)
     n, m = len(T) - 1, len(P) - 1
     q, e, f, r = sc.q, sc.e, sc.f, sc.r
     no_intron = bool(sc.flags & 1)
     no_fs = bool(sc.flags & 2)
-    local = sc.mode == 0
+    local = sc.mode in (0, 3)
 
     def base(x):
         return T[x] if 1 <= x <= n else 4
@@ -93,6 +94,6 @@ def best_score(prot: str, dna: str, sc) -> float:
                 v = max(v, best_to(i0 - 1, j - 1) - (r + d(i0 + 1) + a(i - 1)))
         return v
 
-    if sc.mode == 2:
+    if sc.mode in (2, 3):
         return best_to(n, m)
     return max(best_to(i, j) for i in range(n + 1) for j in range(m + 1))

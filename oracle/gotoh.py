@@ -32,13 +32,14 @@ def translate(dna: str, frame: int, codon_table: dict) -> str:
 
 def gotoh(prot: str, xlat: str, mat, q: int, e: int, kind: str) -> float:
     """kind: 'local' (Smith-Waterman-Gotoh), 'extend' (start at (0,0), free
-    end) or 'global' (Needleman-Wunsch-Gotoh)."""
+    end), 'global' (Needleman-Wunsch-Gotoh) or 'end' (start anywhere, end at
+    the last codon and the last residue)."""
     P = [(_AA.index(c.upper()) if c.upper() in _AA else 22) for c in prot]
     X = [(_AA.index(c) if c in _AA else 22) for c in xlat]
     L, m = len(X), len(P)
 
     def start(a, b):
-        if kind == "local":
+        if kind in ("local", "end"):
             return 0
         return 0 if (a == 0 and b == 0) else NEG
 
@@ -57,12 +58,14 @@ def gotoh(prot: str, xlat: str, mat, q: int, e: int, kind: str) -> float:
             if a >= 1:
                 Dy[a][b] = max(M[a - 1][b] - q - e, Dy[a - 1][b] - e,
                                Ix[a - 1][b] - q - e, start(a - 1, b) - q - e)
-            if kind != "global":
+            if kind in ("local", "extend"):
                 best = max(best, M[a][b], Ix[a][b], Dy[a][b])
     if kind == "global":
         if L == 0 and m == 0:
             return 0
         return max(M[L][m], Ix[L][m], Dy[L][m])
+    if kind == "end":
+        return max(M[L][m], Ix[L][m], Dy[L][m], 0)
     return best
 
 
@@ -71,12 +74,16 @@ def spliced_reduction(prot: str, dna: str, sc, codon_table: dict) -> float:
 
     LOCAL: best Smith-Waterman-Gotoh over the three forward frames.
     EXTEND: frame 0 from the origin.  GLOBAL: frame 0, defined only when the
-    region is a whole number of codons (else -inf = no alignment)."""
+    region is a whole number of codons (else -inf = no alignment).
+    EXTEND_LEFT: the frame whose last codon ends at the region's end, free
+    start, fixed end."""
     if sc.mode == 0:
         return max(gotoh(prot, translate(dna, ph, codon_table), sc.mat, sc.q, sc.e, "local")
                    for ph in range(3))
     if sc.mode == 1:
         return gotoh(prot, translate(dna, 0, codon_table), sc.mat, sc.q, sc.e, "extend")
+    if sc.mode == 3:
+        return gotoh(prot, translate(dna, len(dna) % 3, codon_table), sc.mat, sc.q, sc.e, "end")
     if len(dna) % 3 != 0:
         return NEG
     return gotoh(prot, translate(dna, 0, codon_table), sc.mat, sc.q, sc.e, "global")

@@ -29,8 +29,14 @@
  *  - d(x) is a table over the 3-mer T[x+1..x+3] and a(x) over T[x-2..x]
  *    (the splice models of the "Splice models" subsection), bases outside
  *    [1,n] count as N;
- *  - three boundary modes: LOCAL (0 floor at every cell, free end), EXTEND
- *    (start at H(0,0)=0, free end) and GLOBAL (start at H(0,0)=0, end (n,m));
+ *  - four boundary modes: LOCAL (0 floor at every cell, free end), EXTEND
+ *    (start at H(0,0)=0, free end), GLOBAL (start at H(0,0)=0, end (n,m)) and
+ *    EXTEND_LEFT (0 floor at every cell, end (n,m)).  The DP closes gaps
+ *    between anchors (GLOBAL) and extends from terminal anchors (Methods,
+ *    opening paragraph; "Residue alignment with dynamic programming"): to
+ *    the right an extension starts at the anchor and ends anywhere
+ *    (EXTEND); to the left it starts anywhere and ends at the anchor
+ *    (EXTEND_LEFT);
  *  - ties: H takes the first maximum in the order
  *    [start, M, I, D, F1, F2, G1, G2, A, B, C]; I/D/A/B/C prefer extension
  *    over opening on ties; the end cell is the first maximum in row-major
@@ -62,7 +68,7 @@ enum { C_START = 0, C_M, C_I, C_D, C_F1, C_F2, C_G1, C_G2, C_A, C_B, C_C };
 #define X_B (1u << 7)
 #define X_C (1u << 8)
 
-enum { ORC_LOCAL = 0, ORC_EXTEND = 1, ORC_GLOBAL = 2 };
+enum { ORC_LOCAL = 0, ORC_EXTEND = 1, ORC_GLOBAL = 2, ORC_EXTEND_LEFT = 3 };
 enum { ORC_NO_INTRON = 1, ORC_NO_FS = 2 };
 
 static const char ORC_AA[] = "ARNDCQEGHILKMFPSTWYVBZX*";
@@ -173,8 +179,8 @@ static int emit(tok_t **v, int64_t *nv, int64_t *cap, char op, int64_t len, int 
  * orc_align: align protein P (ASCII, length m) to genome T (ASCII, length n).
  * out[0..4] = score, g_beg, g_end, p_beg, p_end (begins are -1 without traceback).
  * ops: buffer for the run-length op string (NUL-terminated), ops_cap bytes.
- * Returns 0, -6 (GLOBAL end unreachable), -3 (out of memory) or -2 (ops buffer
- * too small).
+ * Returns 0, -6 (GLOBAL end unreachable), -3 (out of memory), -2 (ops buffer
+ * too small) or -1 (unknown mode).
  */
 int orc_align(const char *prot, int32_t m, const char *dna, int32_t n,
               int64_t q, int64_t e, int64_t f, int64_t r, int32_t flags, int32_t mode,
@@ -192,6 +198,9 @@ int orc_align(const char *prot, int32_t m, const char *dna, int32_t n,
     int status = 0;
     const int64_t w = (int64_t)m + 1;
 
+    if (mode < ORC_LOCAL || mode > ORC_EXTEND_LEFT) return -1;
+    const int floor0 = mode == ORC_LOCAL || mode == ORC_EXTEND_LEFT;
+    const int fixed_end = mode == ORC_GLOBAL || mode == ORC_EXTEND_LEFT;
     memset(&c, 0, sizeof c);
     c.q = q; c.e = e; c.f = f; c.r = r;
     c.no_intron = (flags & ORC_NO_INTRON) != 0;
@@ -265,7 +274,7 @@ int orc_align(const char *prot, int32_t m, const char *dna, int32_t n,
             }
 
             /* H candidates in tie-break order */
-            if (mode == ORC_LOCAL) cand[C_START] = 0;
+            if (floor0) cand[C_START] = 0;
             else cand[C_START] = (i == 0 && j == 0) ? 0 : NEG;
             cand[C_M] = (i >= 3 && j >= 1)
                 ? addsc(getH(&rw, i - 3, j - 1), mat[tri * 24 + P[j]]) : NEG;
@@ -296,10 +305,10 @@ int orc_align(const char *prot, int32_t m, const char *dna, int32_t n,
             AT(rw.C, i, j) = Cv;
             if (want_tb) code[(size_t)i * (size_t)w + (size_t)j] = cc;
 
-            if (mode != ORC_GLOBAL && h > best) { best = h; bi = i; bj = j; }
+            if (!fixed_end && h > best) { best = h; bi = i; bj = j; }
         }
     }
-    if (mode == ORC_GLOBAL) {
+    if (fixed_end) {
         best = getH(&rw, n, m);
         bi = n; bj = m;
         if (best == NEG) { status = -6; goto done; }

@@ -31,7 +31,7 @@ def _rand_case(rng, max_n=10, max_m=3, dna_alpha="ACGTGTAG", prot_alpha="ARNDCW*
 def _rand_scoring(rng, mode=None, flags=None, tables=False):
     kw = dict(q=rng.randint(0, 6), e=rng.randint(1, 3), f=rng.randint(0, 8),
               r=rng.randint(0, 10),
-              mode=rng.randint(0, 2) if mode is None else mode,
+              mode=rng.randint(0, 3) if mode is None else mode,
               flags=rng.randint(0, 3) if flags is None else flags)
     if tables:
         m = np.array([[rng.randint(-5, 8) for _ in range(24)] for _ in range(24)])
@@ -67,7 +67,7 @@ def test_brute_force_degenerate_penalties():
     rng = random.Random(7)
     for _ in range(60):
         prot, dna = _rand_case(rng, max_n=9, max_m=3)
-        for mode in (0, 1, 2):
+        for mode in (0, 1, 2, 3):
             sc = params.default_scoring(q=0, e=1, f=0, r=0, mode=mode,
                                         donor=np.zeros(125, np.uint8),
                                         acceptor=np.zeros(125, np.uint8))
@@ -91,7 +91,7 @@ def test_score_only_equals_traceback_run():
 
 
 # ------------------------------------------------------- Gotoh reduction
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_reduces_to_gotoh_without_introns_and_frameshifts(mode):
     """With introns and frameshifts removed, Eq. (full) is affine-gap
     alignment on a translated frame (LOCAL: best of 3 frames)."""
@@ -267,10 +267,11 @@ def test_mode_nesting_and_monotonicity():
         base = _rand_scoring(rng, mode=0, flags=0)
         sl = oracle.align(prot, dna, base, False).score
         se = oracle.align(prot, dna, base.replace(mode=1), False).score
+        sx = oracle.align(prot, dna, base.replace(mode=3), False).score
         g = oracle.align(prot, dna, base.replace(mode=2), False)
-        assert sl >= se
+        assert sl >= se and sl >= sx >= 0
         if g.status == 0:
-            assert se >= g.score
+            assert se >= g.score and sx >= g.score
         for field in ("q", "e", "f", "r"):
             bigger = base.replace(**{field: getattr(base, field) + rng.randint(1, 5)})
             assert oracle.align(prot, dna, bigger, False).score <= sl
@@ -291,6 +292,32 @@ def test_empty_inputs():
     assert r.status == 0 and r.score == -(sc.q + 2 * sc.e) and r.ops == "2I"
     r = oracle.align("", "ACGTA", sc.replace(mode=2, flags=3))
     assert r.status == oracle.E_NOALN
+    for prot, dna in (("", ""), ("MK", ""), ("", "ACGTA")):
+        r = oracle.align(prot, dna, sc.replace(mode=3))
+        assert (r.status, r.score, r.g_beg, r.g_end, r.p_beg, r.p_end, r.ops) == \
+            (0, 0, len(dna), len(dna), len(prot), len(prot), "")
+
+
+def test_left_extension_is_reversed_extension():
+    """Without introns, every path step (codon:residue, gap, frameshift) is
+    symmetric under reversal once codons are read backwards, so the best
+    alignment that starts anywhere and ends at (n, m) equals the best
+    extension from the origin of the reversed sequences with a reversed
+    genetic code."""
+    rng = random.Random(41)
+    for _ in range(60):
+        prot, dna = _rand_case(rng, max_n=90, max_m=25, dna_alpha="ACGTN",
+                               prot_alpha=params.AA)
+        sc = _rand_scoring(rng, mode=3, flags=rng.choice([1, 3]), tables=True)
+        gc = np.array([sc.gcode[16 * (k % 4) + 4 * ((k // 4) % 4) + k // 16]
+                       for k in range(64)], np.uint8)
+        rev = sc.replace(mode=1, gcode_tab=gc)
+        a = oracle.align(prot, dna, sc, True)
+        b = oracle.align(prot[::-1], dna[::-1], rev, False)
+        assert a.score == b.score, (prot, dna)
+        assert (a.g_end, a.p_end) == (len(dna), len(prot))
+        s, ge, pe = rescore.rescore(prot, dna, sc, a.g_beg, a.p_beg, a.ops)
+        assert (s, ge, pe) == (a.score, a.g_end, a.p_end)
 
 
 # ------------------------------------------------- planted mistakes are caught
@@ -310,6 +337,12 @@ MUTANTS = [
     ("Dv = pen(Dv, e);", "Dv = pen(Dv, 0);"),
     # wrong codon index order
     ("return c->gcode[16 * b1 + 4 * b2 + b3];", "return c->gcode[16 * b3 + 4 * b2 + b1];"),
+    # left extension read at its best cell instead of at (n, m)
+    ("const int fixed_end = mode == ORC_GLOBAL || mode == ORC_EXTEND_LEFT;",
+     "const int fixed_end = mode == ORC_GLOBAL;"),
+    # left extension started only at the origin
+    ("const int floor0 = mode == ORC_LOCAL || mode == ORC_EXTEND_LEFT;",
+     "const int floor0 = mode == ORC_LOCAL;"),
 ]
 
 
@@ -332,7 +365,7 @@ def test_planted_mistake_is_detected(k, tmp_path):
     ct = params.codon_table()
     rng = random.Random(500 + k)
     caught = False
-    for _ in range(300):
+    for _ in range(2000):
         prot, dna = _rand_case(rng, max_n=12, max_m=3, prot_alpha=params.AA)
         sc = _rand_scoring(rng, tables=True)
         out = (ctypes.c_int64 * 5)()
