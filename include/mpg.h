@@ -51,9 +51,11 @@ enum {
 
 /* ---- boundary modes (sources and sinks of the DP) ---------------------- */
 enum {
-    MPG_LOCAL = 0,  /* start and end anywhere; H never drops below 0 */
-    MPG_EXTEND = 1, /* start at H(0,0)=0 (an anchor), end anywhere */
-    MPG_GLOBAL = 2  /* start at H(0,0)=0, end at (n,m): closing a gap between anchors */
+    MPG_LOCAL = 0,      /* start and end anywhere; H never drops below 0 */
+    MPG_EXTEND = 1,     /* start at H(0,0)=0 (an anchor), end anywhere: rightward extension */
+    MPG_GLOBAL = 2,     /* start at H(0,0)=0, end at (n,m): closing a gap between anchors */
+    MPG_EXTEND_LEFT = 3 /* start anywhere (H never drops below 0), end at (n,m) (an anchor):
+                           leftward extension */
 };
 
 /* ---- flags -------------------------------------------------------------- */

@@ -73,8 +73,17 @@ __device__ __forceinline__ uint64_t end_key(int score, int row, int col) {
            ((uint64_t)(uint32_t)((1 << 21) - 1 - row) << 15) | (uint64_t)((1 << 15) - 1 - col);
 }
 
+// Modes whose H floors at 0 in every cell (a path may start anywhere), and
+// modes read at the single end cell (n, m).
+__host__ __device__ constexpr bool floor_mode(int mode) {
+    return mode == MPG_LOCAL || mode == MPG_EXTEND_LEFT;
+}
+__host__ __device__ constexpr bool fixed_end_mode(int mode) {
+    return mode == MPG_GLOBAL || mode == MPG_EXTEND_LEFT;
+}
+
 __device__ __forceinline__ int neg_for(int mode, bool tb) {
-    return mode == MPG_LOCAL ? (tb ? -(1 << 29) : -(1 << 25)) : -(1 << 30);
+    return floor_mode(mode) ? (tb ? -(1 << 29) : -(1 << 25)) : -(1 << 30);
 }
 
 // ---------------------------------------------------------------------- DP
@@ -99,12 +108,12 @@ struct LdsLayout {
     static constexpr int WAVE = RING + PROF + IN + OUT;
 };
 
-// Sentinels per layout.  LOCAL keeps -infinity small enough that a shifted
-// end-tracking key of any sentinel-derived value stays negative.
+// Sentinels per layout.  The floor modes keep -infinity small enough that a
+// shifted end-tracking key of any sentinel-derived value stays negative.
 template <int MODE, bool TB>
 struct Sentinel {
-    static constexpr int NEG = MODE == MPG_LOCAL ? (TB ? -(1 << 29) : -(1 << 25)) : -(1 << 30);
-    static constexpr int UNREACH = MODE == MPG_LOCAL ? NEG / 2 : -(1 << 29);
+    static constexpr int NEG = floor_mode(MODE) ? (TB ? -(1 << 29) : -(1 << 25)) : -(1 << 30);
+    static constexpr int UNREACH = floor_mode(MODE) ? NEG / 2 : -(1 << 29);
 };
 
 // acc = 2*acc + (ext >= open) in every lane: the compare is a wave ballot
@@ -398,7 +407,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         const int L1 = c ? h1[c - 1] : hl1;
                         const int L2 = c ? h2[c - 1] : hl2;
                         const int L3 = c ? h3[c - 1] : hl3;
-                        const int z = (MODE == MPG_LOCAL) ? zr : imin(zr, zl[c]);
+                        const int z = floor_mode(MODE) ? zr : imin(zr, zl[c]);
                         if (!TB) {
                             const int D = imax(h3[c] - cqD, d3[c]) - ce;
                             int H = D;
@@ -451,7 +460,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         }
                     }
                     // end-cell tracking (chunk-local, merged after the chunk)
-                    if (MODE == MPG_GLOBAL) {
+                    if (fixed_end_mode(MODE)) {
                         const bool at_n = (lane == t + srow_n);
 #pragma unroll
                         for (int c = 0; c < K; ++c) hn[c] = at_n ? Hn[c] : hn[c];
@@ -506,7 +515,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 }  // steps
 
                 // merge the chunk's best into the strip's best (first maximum)
-                if (MODE != MPG_GLOBAL) {
+                if (!fixed_end_mode(MODE)) {
 #pragma unroll
                     for (int c = 0; c < K; ++c) {
                         int v, tt;
@@ -544,7 +553,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
 
         // ---- strip epilogue: best cell of the strip, folded into the pair
         if (!failed) {
-            if (MODE == MPG_GLOBAL) {
+            if (fixed_end_mode(MODE)) {
 #pragma unroll
                 for (int c = 0; c < K; ++c)
                     if (col0 + c == m) st_dev(&ps->gsc, hn[c]);
@@ -590,7 +599,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 R.score = 0;
                 R.g_end = -1;
                 R.p_end = -1;
-            } else if (MODE == MPG_GLOBAL) {
+            } else if (fixed_end_mode(MODE)) {
                 if (gv < UNREACH) {
                     R.status = MPG_E_NOALN;
                     R.score = 0;
@@ -683,6 +692,7 @@ hipError_t launch_dp_k(hipStream_t s, int ncu, bool tb, const DevParams& P, cons
     switch (P.mode) {
         case MPG_LOCAL: MPG_MODE(MPG_LOCAL);
         case MPG_EXTEND: MPG_MODE(MPG_EXTEND);
+        case MPG_EXTEND_LEFT: MPG_MODE(MPG_EXTEND_LEFT);
         default: MPG_MODE(MPG_GLOBAL);
     }
 #undef MPG_MODE

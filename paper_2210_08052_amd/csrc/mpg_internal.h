@@ -37,7 +37,7 @@ struct DevParams {
     uint8_t acceptor[128];
 };
 
-// Per-pair launch plan (device copy; 80 bytes).
+// Per-pair launch plan (device copy; 96 bytes).
 struct PairJob {
     int32_t n, m;        // genome rows, protein columns
     int32_t res;         // index of the result record
@@ -54,7 +54,10 @@ struct PairJob {
     int32_t status;      // host pre-check status (MPG_OK or MPG_E_RANGE)
     int32_t prog_off;    // index of strip 0's progress counter
     int32_t i16;         // 1: runs in a packed int16 job (see PackJob)
+    int32_t mode;        // boundary mode of this pair (MPG_LOCAL ... MPG_EXTEND_LEFT)
+    int32_t _pad;
 };
+static_assert(sizeof(PairJob) == 96, "PairJob layout");
 
 // Two LOCAL score-only pairs run together by the lane-packed int16 kernel:
 // pair a in the low 16 bits of every lane value, pair b in the high 16 bits

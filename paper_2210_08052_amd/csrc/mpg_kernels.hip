@@ -74,8 +74,8 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
     };
     const bool valid = (i >= 0 && i <= n);
     int z;
-    const int neg = neg_for(P.mode, J.tb != 0);
-    if (P.mode == MPG_LOCAL) z = valid ? 0 : neg;
+    const int neg = neg_for(J.mode, J.tb != 0);
+    if (floor_mode(J.mode)) z = valid ? 0 : neg;
     else z = (i == 0) ? 0 : neg;
     int4* out = (int4*)(desc + J.desc_off + (int64_t)(i + kDescLo) * (J.tb ? 32 : 16));
     if (!J.tb) {

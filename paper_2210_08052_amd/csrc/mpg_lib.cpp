@@ -226,6 +226,7 @@ struct Group {
     int K;
     bool tb;
     bool i16;
+    int mode;  // every pair of a group has this boundary mode
     std::vector<int2> items;
 };
 
@@ -304,11 +305,11 @@ int64_t tb_bytes_max(int n, int m) {
 }
 
 // Bound on |value| of reachable cells (see the public header): the largest
-// match score times the protein length, and (EXTEND/GLOBAL) the largest
-// per-unit penalty times the number of units a path can consume.
+// match score times the protein length, and (EXTEND/GLOBAL, whose H has no 0
+// floor) the largest per-unit penalty times the number of units a path can
+// consume.
 struct BoundInfo {
     int64_t maxpos = 0, pmax = 0;
-    int mode = MPG_LOCAL;
     explicit BoundInfo(const mpg_params* p) {
         int mp = 0, mn = 0;
         for (int a = 0; a < 24; ++a)
@@ -324,24 +325,25 @@ struct BoundInfo {
         maxpos = mp;
         pmax = std::max<int64_t>({(int64_t)p->q + p->e, (int64_t)p->f,
                                   (int64_t)p->r + dmax + amax, (int64_t)-mn});
-        mode = p->mode;
     }
-    bool ok(int64_t n, int64_t m) const {
+    bool ok(int64_t n, int64_t m, int mode) const {
         const int64_t lim = (int64_t)1 << 24;
         if (maxpos * (m + 1) >= lim) return false;
-        if (mode == MPG_LOCAL) return pmax * 4 < lim;
+        if (mode == MPG_LOCAL || mode == MPG_EXTEND_LEFT) return pmax * 4 < lim;
         return (n + m + 4) * pmax < lim;
     }
     // int16 lanes (LOCAL only): H >= 0 everywhere, so reachable values lie in
     // [-(the largest penalty sum), the best score]; the best score of a
     // protein of m residues is at most m times the largest matrix entry.
     // Both must stay clear of the int16 range with room to spare.
-    bool ok16(int64_t m) const {
+    bool ok16(int64_t m, int mode) const {
         return mode == MPG_LOCAL && maxpos * m <= 32767 - 256 && pmax <= 8192;
     }
 };
 
-bool score_bound_ok(const mpg_params* p, int64_t n, int64_t m) { return BoundInfo(p).ok(n, m); }
+bool score_bound_ok(const mpg_params* p, int64_t n, int64_t m) {
+    return BoundInfo(p).ok(n, m, p->mode);
+}
 
 void make_dev_params(const mpg_params* p, DevParams* d) {
     std::memset(d, 0, sizeof(*d));
@@ -369,6 +371,8 @@ struct RunCfg {
                         // last) to memory the host polls; shortest pairs first
     const Tuning* tune = nullptr;  // measured costs for choosing K
     int force_K = 0, force_K16 = 0;  // calibration runs: one width for all
+    const int8_t* modes = nullptr;   // per pair of the call: its boundary mode
+                                     // (NULL: params.mode for every pair)
 };
 
 // Build the plan for the pairs idx[0..cnt) of a call with n pairs.  Each
@@ -386,7 +390,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     bysize.reserve(cnt);
     const Overrides ov;
     const BoundInfo bound(p);
-    const bool allow16 = (p->flags & MPG_ALLOW_I16) != 0 && p->mode == MPG_LOCAL;
+    const bool allow16 = (p->flags & MPG_ALLOW_I16) != 0;
     const int K16 = choose_K16(ov, cfg.tune, cfg.force_K16);
     const KChoice kc = choose_widths(ov, cfg.tune, cfg.force_K);
     std::vector<std::pair<int64_t, int32_t>> e16;
@@ -400,8 +404,10 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         J.dna_off = s.dna_off;
         J.prot_off = s.prot_off;
         J.status = MPG_OK;
+        J.mode = cfg.modes ? cfg.modes[idx[k]] : p->mode;
+        J._pad = 0;
         if (s.dlen < 0 || s.plen < 0 || s.dlen > MPG_MAX_DNA || s.plen > MPG_MAX_PROT ||
-            !bound.ok(s.dlen, s.plen))
+            !bound.ok(s.dlen, s.plen, J.mode))
             J.status = MPG_E_RANGE;
         const bool want_tb = ((s.flags | p->flags) & MPG_WANT_TB) != 0;
         const int K = kc.K[want_tb ? 1 : 0];
@@ -415,7 +421,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         J.ops_off = ops_off[idx[k]];
         J.i16 = 0;
         if (J.status != MPG_OK) continue;
-        if (allow16 && !J.tb && bound.ok16(mm)) {
+        if (allow16 && !J.tb && bound.ok16(mm, J.mode)) {
             J.i16 = 1;
             J.K = K16;
             J.nstrips = (mm + 1 + 64 * K16 - 1) / (64 * K16);
@@ -448,9 +454,9 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         const PairJob& J = P.jobs[e.second];
         Group* g = nullptr;
         for (auto& gg : P.groups)
-            if (gg.K == J.K && gg.tb == (J.tb != 0) && !gg.i16) g = &gg;
+            if (gg.K == J.K && gg.tb == (J.tb != 0) && !gg.i16 && gg.mode == J.mode) g = &gg;
         if (!g) {
-            P.groups.push_back(Group{J.K, J.tb != 0, false, {}});
+            P.groups.push_back(Group{J.K, J.tb != 0, false, J.mode, {}});
             g = &P.groups.back();
         }
         for (int st = 0; st < J.nstrips; ++st) g->items.push_back(make_int2(e.second, st));
@@ -462,7 +468,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
                   [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
                       return a.first > b.first || (a.first == b.first && a.second < b.second);
                   });
-        P.groups.push_back(Group{K16, false, true, {}});
+        P.groups.push_back(Group{K16, false, true, MPG_LOCAL, {}});
         Group& g = P.groups.back();
         for (size_t q = 0; q < e16.size(); q += 2) {
             const PairJob& A = P.jobs[e16[q].second];
@@ -746,11 +752,13 @@ int enqueue(hipStream_t st, Workspace& ws, const Prepared& X, const RunCfg& cfg,
     auto launch_group = [&](hipStream_t s2, size_t g) -> hipError_t {
         const Group& G = P.groups[g];
         const int nit = (int)G.items.size();
+        DevParams DG = DP;
+        DG.mode = G.mode;
         if (G.i16)
-            return launch_dp16(s2, G.K, cfg.ncu, DP, X.d_jobs, X.d_packs, X.d_items + X.goff[g],
+            return launch_dp16(s2, G.K, cfg.ncu, DG, X.d_jobs, X.d_packs, X.d_items + X.goff[g],
                                nit, X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot,
                                (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, sink);
-        return launch_dp(s2, G.K, G.tb, cfg.ncu, DP, X.d_jobs, X.d_items + X.goff[g], nit,
+        return launch_dp(s2, G.K, G.tb, cfg.ncu, DG, X.d_jobs, X.d_items + X.goff[g], nit,
                          X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot, (const uint8_t*)ws.desc.p,
                          (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, sink);
     };
@@ -841,7 +849,7 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
 int params_check_impl(const mpg_params* p) {
     if (!p) return MPG_E_INVAL;
     if (p->q < 0 || p->e < 0 || p->f < 0 || p->r < 0 || p->q + p->e <= 0) return MPG_E_INVAL;
-    if (p->mode < MPG_LOCAL || p->mode > MPG_GLOBAL) return MPG_E_INVAL;
+    if (p->mode < MPG_LOCAL || p->mode > MPG_EXTEND_LEFT) return MPG_E_INVAL;
     if (p->flags & ~(uint32_t)(MPG_NO_INTRON | MPG_NO_FRAMESHIFT | MPG_WANT_TB | MPG_ALLOW_I16))
         return MPG_E_INVAL;
     for (int k = 0; k < 64; ++k)

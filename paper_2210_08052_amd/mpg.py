@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("MPG_LIBRARY") or os.path.join(HERE, "libmpg.so")
 
 MPG_OK, MPG_E_INVAL, MPG_E_RANGE, MPG_E_NOMEM = 0, -1, -2, -3
 MPG_E_AGAIN, MPG_E_DEVICE, MPG_E_NOALN, MPG_E_CANCELLED = -4, -5, -6, -7
-MPG_LOCAL, MPG_EXTEND, MPG_GLOBAL = 0, 1, 2
+MPG_LOCAL, MPG_EXTEND, MPG_GLOBAL, MPG_EXTEND_LEFT = 0, 1, 2, 3
 MPG_NO_INTRON, MPG_NO_FRAMESHIFT, MPG_WANT_TB, MPG_ALLOW_I16 = 1, 2, 4, 8
 MPG_MAX_DNA, MPG_MAX_PROT = 1040000, 32000
 

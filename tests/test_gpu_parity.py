@@ -31,7 +31,7 @@ def _pairs(seed, n=40, max_prot=150, max_dna=700, dna="ACGTGTAGN", min_prot=0, m
 
 @pytest.mark.parametrize("tb", [False, True])
 @pytest.mark.parametrize("flags", [0, 1, 2, 3])
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_random_small_default_scoring(ctx, mode, flags, tb):
     print("case mode=%d flags=%d tb=%d" % (mode, flags, tb), flush=True)
     g, o = scorings(mode, flags)
@@ -39,7 +39,7 @@ def test_random_small_default_scoring(ctx, mode, flags, tb):
 
 
 @pytest.mark.parametrize("tb", [False, True])
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_random_small_random_scoring(ctx, mode, tb):
     for rs in range(3):
         print("case mode=%d tb=%d rs=%d" % (mode, tb, rs), flush=True)
@@ -54,7 +54,7 @@ def test_kernel_variants(ctx, K, monkeypatch):
     HBM while the strips run concurrently, with ragged last strips and tails."""
     monkeypatch.setenv("MPG_FORCE_K", str(K))
     pairs = _pairs(400 + K * 10, n=24, max_prot=700, max_dna=900, min_prot=100)
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         for tb in (False, True):
             print("case K=%d mode=%d tb=%d" % (K, mode, tb), flush=True)
             g, o = scorings(mode, 0)
@@ -66,7 +66,7 @@ def test_edge_cases(ctx):
              ("XB*Z", "NNNTAGNNN"), ("acdefghik", "gcttgtgatgaattttggtcatattaaa"),
              ("JOU?", "RYKMACGT"), ("M" * 200, "ATG"), ("M", "ATG" * 400),
              ("MKVLAT", "ATGAAAGTAAGTAAGTTTTTTTTCAGCTGGCGACC")]
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         for tb in (False, True):
             print("case edge mode=%d tb=%d" % (mode, tb), flush=True)
             g, o = scorings(mode, 0)

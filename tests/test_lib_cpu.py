@@ -88,8 +88,13 @@ def test_params_check():
     assert L.mpg_params_check(ctypes.byref(bad), 10, 10) == mpg.MPG_E_INVAL
     bad = mpg.params(q=0, e=0)
     assert L.mpg_params_check(ctypes.byref(bad), 10, 10) == mpg.MPG_E_INVAL
-    bad = mpg.params(mode=3)
+    bad = mpg.params(mode=4)
     assert L.mpg_params_check(ctypes.byref(bad), 10, 10) == mpg.MPG_E_INVAL
+    bad = mpg.params(mode=-1)
+    assert L.mpg_params_check(ctypes.byref(bad), 10, 10) == mpg.MPG_E_INVAL
+    left = mpg.params(mode=mpg.MPG_EXTEND_LEFT)
+    # a 0 floor, like LOCAL: only the best score bounds the values
+    assert L.mpg_params_check(ctypes.byref(left), 1000, 1000000) == mpg.MPG_OK
     bad = mpg.params(flags=64)
     assert L.mpg_params_check(ctypes.byref(bad), 10, 10) == mpg.MPG_E_INVAL
     g = mpg.params(mode=mpg.MPG_GLOBAL)
