@@ -169,6 +169,9 @@ def planted_gene(rng, L: int, rho: float, n_fs: int, intron_lens: list,
             mut[p] = min(b, 19)
     idx = np.floor(rng.random(L) * _SYNCNT[mut]).astype(np.int64)
     cds = _SYNTAB[mut, idx].reshape(-1).copy()
+    # where each residue's codon starts in the coding sequence, -1 once a
+    # frameshift has broken it (bookkeeping only: no draws)
+    cpos = np.arange(L, dtype=np.int64) * 3
     fs = []
     for _ in range(n_fs):
         if len(cds) < 8:
@@ -177,9 +180,15 @@ def planted_gene(rng, L: int, rho: float, n_fs: int, intron_lens: list,
         if rng.random() < 0.5:
             cds = np.insert(cds, p, BASES[rng.integers(0, 4)])
             fs.append(("ins", p))
+            ok = cpos >= 0
+            cpos[ok & (cpos < p) & (cpos + 3 > p)] = -1
+            cpos[(cpos >= 0) & (cpos >= p)] += 1
         else:
             cds = np.delete(cds, p)
             fs.append(("del", p))
+            ok = cpos >= 0
+            cpos[ok & (cpos <= p) & (cpos + 3 > p)] = -1
+            cpos[(cpos >= 0) & (cpos > p)] -= 1
     cuts = None
     n_introns = len(intron_lens)
     while n_introns > 0:
@@ -206,9 +215,21 @@ def planted_gene(rng, L: int, rho: float, n_fs: int, intron_lens: list,
             parts.append(introns[e])
             off += len(introns[e])
     gene = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+    # codon positions in the gene; a codon split by an intron gets -1
+    codon_at = np.full(L, -1, dtype=np.int64)
+    shift = 0
+    bounds = list(cuts) + [len(cds)]
+    lo = 0
+    for e, hi in enumerate(bounds):
+        sel = (cpos >= lo) & (cpos + 3 <= hi)
+        codon_at[sel] = cpos[sel] + shift
+        if e < len(introns):
+            shift += len(introns[e])
+        lo = hi
     truth = {"exons": exons, "cuts": cuts, "frameshifts": fs, "n_subst": k,
              "intron_lens": [len(x) for x in introns],
-             "canonical": [bool(x) for x in canonical[:len(introns)]]}
+             "canonical": [bool(x) for x in canonical[:len(introns)]],
+             "codon_at": codon_at, "kept": mut == prot}
     return _STD[prot].tobytes(), gene, truth
 
 
@@ -218,6 +239,10 @@ def _finish(rng, prot, gene, truth, region: int, left: int) -> Pair:
     truth = dict(truth)
     truth["gene_start"] = left
     truth["exons"] = [(a + left, b + left) for a, b in truth["exons"]]
+    if "codon_at" in truth:
+        ca = truth["codon_at"].copy()
+        ca[ca >= 0] += left
+        truth["codon_at"] = ca
     return Pair(prot, dna.tobytes(), False, truth)
 
 
@@ -367,6 +392,43 @@ def random_scoring(seed: int, with_tables: bool = True) -> dict:
         out["mat"] = m.astype(np.int8)
         out["donor"] = rng.integers(0, 31, size=125).astype(np.uint8)
         out["acceptor"] = rng.integers(0, 31, size=125).astype(np.uint8)
+    return out
+
+
+def true_anchors(pair: Pair, k: int = 6) -> list:
+    """Every exact seed hit of k residues on the planted path: (x, y) with
+    residues y..y+k-1 unchanged by the substitutions and their codons
+    consecutive and whole in the region at x, x+3, ... (0-based)."""
+    ca, kept = pair.truth["codon_at"], pair.truth["kept"]
+    L = len(ca)
+    good = (ca >= 0) & kept
+    out = []
+    for y in range(0, L - k + 1):
+        w = ca[y:y + k]
+        if good[y:y + k].all() and (np.diff(w) == 3).all():
+            out.append((int(w[0]), y))
+    return out
+
+
+def chain_jobs(n_chains: int = 10000, seed: int = 6, k: int = 6, keep: float = 0.25) -> list:
+    """Planted-gene pairs of the batch distribution with a chain of anchors
+    each: the true seed hits of k residues (see true_anchors), each kept with
+    probability `keep` (so kept hits often overlap on one diagonal), in
+    genome order.  Pairs without a kept hit are redrawn.  Returns a list of
+    (Pair, anchors)."""
+    pairs = batch_pairs(int(n_chains * 1.3) + 16, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    out = []
+    for p in pairs:
+        hits = true_anchors(p, k)
+        sel = [h for h, u in zip(hits, rng.random(len(hits))) if u < keep]
+        if not sel:
+            continue
+        out.append((p, sorted(sel)))
+        if len(out) == n_chains:
+            break
+    if len(out) < n_chains:
+        raise RuntimeError("not enough chains drawn")
     return out
 
 
