@@ -132,6 +132,132 @@ def cpu_baseline(pairs, tb: bool, budget_s: float):
                 k, len(pairs), cells, dt, model)}
 
 
+def cpu_baseline_chains(chains, budget_s: float):
+    """The oracle's anchor-driven alignment, as it stands, on all host cores
+    (one chain per task) over a bounded sample; the rate counts the DP cells
+    of the pieces, as the GPU figure does."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import chain as ochain
+    threads = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(len(chains))
+
+    def piece_cells(c):
+        prot, dna, anchors, k = c[0], c[1], c[2], c[3]
+        runs = ochain.anchor_runs(anchors, k, len(dna), len(prot))
+        x1, y1, _ = runs[0]
+        xr, yr, lr = runs[-1]
+        tot = x1 * y1 + (len(dna) - xr - 3 * lr) * (len(prot) - yr - lr)
+        for (xa, ya, la), (xb, yb, _) in zip(runs, runs[1:]):
+            tot += (xb - xa - 3 * la) * (yb - ya - la)
+        return tot
+
+    def one(c):
+        ochain.align_chain(c[0].decode(), c[1].decode(), c[2], c[3], sc, want_tb=True)
+        return piece_cells(c)
+
+    import oracle
+    sc = oracle.default_scoring()
+    k, cells = 0, 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        while k < len(order) and time.perf_counter() - t0 < budget_s:
+            part = [chains[i] for i in order[k:k + threads * 4]]
+            cells += sum(ex.map(one, part))
+            k += len(part)
+    dt = time.perf_counter() - t0
+    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d of %d chains (seeded random order), %.3g piece cells, %.1f s wall" % (
+                k, len(chains), cells, dt)}
+
+
+def bench_chains(args):
+    """Anchor-driven alignment of 10,000 planted genes with chains of true
+    seed hits (6 residues each), full traceback: one step is one
+    mpg_align_chains_dev over all chains (pieces in one batch, then the
+    stitch kernel).  GCUPS count the DP cells of the pieces."""
+    import torch
+    from paper_2210_08052_amd import mpg
+    from paper_2210_08052_amd import workloads as W
+    t0 = time.time()
+    jobs = W.chain_jobs(10000, seed=6)
+    chains = [(p.prot, p.dna, a, 6, True) for p, a in jobs]
+    region_cells = int(sum(len(c[0]) * len(c[1]) for c in chains))
+    log("workload chain: %d chains, %d anchors, generated in %.1f s" % (
+        len(chains), sum(len(c[2]) for c in chains), time.time() - t0))
+    pb, db, cs = mpg.pack_chains(chains)
+    dev = torch.device("cuda:0")
+    d_prot = torch.frombuffer(bytearray(pb), dtype=torch.uint8).to(dev)
+    d_dna = torch.frombuffer(bytearray(db), dtype=torch.uint8).to(dev)
+    p = mpg.params()
+    cap = cs.ops_capacity(p)
+    d_ops = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+    d_out = torch.empty(len(chains) * mpg.DEV_RESULT_DTYPE.itemsize, dtype=torch.uint8,
+                        device=dev)
+    ctx = mpg.Context(0)
+    stream = torch.cuda.Stream(device=dev)
+    ctx.set_stream(stream.cuda_stream)
+
+    def step():
+        ctx.align_chains_dev(p, d_prot.data_ptr(), d_dna.data_ptr(), cs, d_out.data_ptr(),
+                             d_ops.data_ptr(), cap)
+
+    for w in range(args.warmup):
+        step()
+        ctx.sync()
+        log("warmup %d done" % w)
+    out = np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=mpg.DEV_RESULT_DTYPE)
+    log("warmup results: %d/%d ok, score sum %d" % (int((out["status"] == 0).sum()), len(out),
+                                                   int(out["score"].sum())))
+    ctx.enable_timing(True)
+    ctx.timing(reset=True)
+    torch.cuda.synchronize()
+    ctx.sync()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        ctx.sync()
+        log("step %d done" % k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = ctx.timing(reset=True)
+    cells = tim["cells"] // max(1, args.steps)
+    ms_step = dt * 1e3 / args.steps
+    gcups = cells / (dt / args.steps) / 1e9
+    dp_ms = tim["dp_ms"] / max(1, args.steps)
+    ops = OPS_PER_CELL["traceback"]
+    peak = PEAK_INT_OPS / 1e12
+    achieved = cells * ops / (dp_ms * 1e-3) / 1e12
+    log("step %.3f ms, GCUPS %.1f (%d piece cells, %.1f%% of the regions' %d); DP kernels "
+        "%.3f ms/step, prepass %.3f ms, walk %.3f ms, host %.3f ms" % (
+            ms_step, gcups, cells, 100.0 * cells / region_cells, region_cells, dp_ms,
+            tim["prepass_ms"] / args.steps, tim["walk_ms"] / args.steps,
+            tim["host_ms"] / args.steps))
+    cpu = None
+    if args.cpu_budget > 0:
+        cpu = cpu_baseline_chains([c[:4] for c in chains], args.cpu_budget)
+        log("cpu baseline: %s" % json.dumps(cpu))
+    line = {
+        "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded planted genes, chains of true seed hits)",
+        "config": {"workload": "anchor-driven alignment: 10,000 planted genes, chains of "
+                               "6-residue seed hits, traceback; EXTEND_LEFT/GLOBAL/EXTEND pieces",
+                   "chains": len(chains), "cells": cells, "region_cells": region_cells,
+                   "traceback": True, "chains_per_s": round(len(chains) / (dt / args.steps), 1)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                     "unit": "Tops/s (int32 lane-ops)", "frac": round(achieved / peak, 4),
+                     "traffic": recorded_traffic("chain"),
+                     "kernel_gcups": round(cells / (dp_ms * 1e-3) / 1e9, 2), "ops_per_cell": ops,
+                     "dp_ms_per_step": round(dp_ms, 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 # Arrival rate of the serving workload (jobs/s): 0.7 x the batched capacity
 # (one mpg_align_batch call over the first 20,000 jobs of the same stream,
 # measured by ``--config serving --calibrate``), rounded to two significant
@@ -356,6 +482,10 @@ def main():
               "across GPUs with no exchange, and the figure here is one GPU's share.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "chain":
+        bench_chains(args)
+        return
 
     if args.config == "serving":
         # the serving scheduler runs seven streams (three short, four long

@@ -227,6 +227,82 @@ int mpg_align_batch_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot
 /* Wait for all work enqueued on the context's stream. */
 int mpg_sync(mpg_ctx *ctx);
 
+/* ---- anchor-driven alignment ------------------------------------------- */
+
+/* One chain: a protein, its genomic region and the anchors that chaining put
+ * on them.  Anchor a is the seed hit anchors[2a] = x, anchors[2a+1] = y: the k
+ * codons of the region starting at base x (0-based) against residues
+ * y .. y+k-1, one to one. */
+typedef struct {
+    const char *prot;
+    int32_t plen;
+    const char *dna;
+    int32_t dlen;           /* up to 2^30 nucleotides: each DP piece has its own limit */
+    const int32_t *anchors; /* nanchors (x, y) pairs in genome order */
+    int32_t nanchors;       /* >= 1 */
+    int32_t k;              /* residues per anchor, >= 1 */
+    uint32_t flags;         /* MPG_WANT_TB for this chain (OR-ed with params.flags) */
+    int32_t _pad;
+} mpg_chain;
+
+/*
+ * Align n chains (Methods, opening paragraph; "Residue alignment with dynamic
+ * programming"): the DP closes the gaps between consecutive anchors and
+ * extends from the first and the last anchor.  Per chain:
+ *  - anchors become runs: an anchor on the current run's diagonal
+ *    (x - x0 == 3 (y - y0)) that overlaps or abuts it extends the run; one
+ *    that starts at or after the run's end in both sequences starts a new
+ *    run; any other anchor is dropped;
+ *  - every run is aligned as M steps (codon against residue, scored by the
+ *    matrix); the pieces between are DP calls of their own, all chains'
+ *    pieces in one batch: P[0, y_1) x T[0, x_1) in MPG_EXTEND_LEFT, each gap
+ *    P[y_t + l_t, y_{t+1}) x T[x_t + 3 l_t, x_{t+1}) in MPG_GLOBAL, and
+ *    P[y_R + l_R, m) x T[x_R + 3 l_R, n) in MPG_EXTEND, with p's scoring
+ *    (p->mode is not used; bases outside a piece count as N);
+ *  - out[c]: the sum of the runs' and the pieces' scores, the alignment from
+ *    the left piece's start (traceback only, else -1) to the right piece's
+ *    end in the chain's coordinates, and (traceback) the joined op string,
+ *    adjacent M tokens merged.  A piece that fails fails the chain with its
+ *    status (MPG_E_NOALN: a gap with no end-to-end path; MPG_E_RANGE: a piece
+ *    beyond the limits or the traceback budget, or a protein longer than
+ *    MPG_MAX_PROT).
+ * The call fails with MPG_E_INVAL for a chain without anchors, k < 1 or an
+ * anchor outside its sequences.  Synchronous; strings and anchors are
+ * borrowed for the call; ops strings are released with mpg_result_release.
+ */
+int mpg_align_chains(mpg_ctx *ctx, const mpg_params *p, const mpg_chain *chains, int32_t n,
+                     mpg_result *out);
+
+/* One chain whose letters already sit in device memory (offsets into the
+ * caller's concatenated device buffers, as mpg_seg); the anchors stay in host
+ * memory. */
+typedef struct {
+    int64_t prot_off;
+    int64_t dna_off;
+    int32_t plen;
+    int32_t dlen;
+    const int32_t *anchors; /* host memory: nanchors (x, y) pairs in genome order */
+    int32_t nanchors;
+    int32_t k;
+    uint32_t flags;         /* MPG_WANT_TB */
+    int32_t _pad;
+} mpg_chain_seg;
+
+/* Bytes of op-string buffer mpg_align_chains_dev needs: chains take
+ * consecutive slots in input order, 2*(plen+dlen)+1 bytes for a traceback
+ * chain (params.flags or the chain's flags) and 1 byte otherwise. */
+int64_t mpg_chain_ops_capacity(const mpg_params *p, const mpg_chain_seg *chains, int32_t n);
+
+/* As mpg_align_chains for chains whose letters are in device memory: plans on
+ * the host, enqueues everything on the context's stream and returns without
+ * waiting.  d_out (device, n records) and d_ops (device, ops_cap bytes)
+ * receive the results; each record's ops_off locates its op string.  The
+ * device buffers must stay valid until the stream has finished; the anchors
+ * are read before the call returns.  MPG_E_RANGE if ops_cap is too small. */
+int mpg_align_chains_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot,
+                         const uint8_t *d_dna, const mpg_chain_seg *chains, int32_t n,
+                         mpg_dev_result *d_out, char *d_ops, int64_t ops_cap);
+
 /* ---- serving ------------------------------------------------------------ */
 
 /*
@@ -282,6 +358,7 @@ typedef struct {
     uint64_t calls;    /* batch calls since the last reset */
     double host_ms;    /* host wall time planning and enqueuing the device work */
     uint64_t i16_pairs; /* pairs that ran in the lane-packed int16 kernel */
+    uint64_t cells;     /* DP cells (genome length x protein length) of the pairs run */
 } mpg_timing;
 
 /* Turn event timing of batch calls on (1) or off (0). */

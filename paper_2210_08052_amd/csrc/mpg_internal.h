@@ -119,6 +119,32 @@ hipError_t launch_walk(hipStream_t s, const PairJob* jobs, const int32_t* order,
 
 hipError_t launch_status(hipStream_t s, const PairJob* jobs, int npairs, const DpSink& sink);
 
+// One chain of anchor runs (device copy; 56 bytes).  Its pieces are
+// consecutive in the piece results: the left extension, the gaps between
+// consecutive runs, then the right extension (nruns + 1 pieces).
+struct ChainJob {
+    int32_t piece0;    // index of the left piece's result record
+    int32_t nruns;     // anchor runs, at runs[run0 .. run0 + nruns) as (x, y, len, 0)
+    int32_t run0;
+    int32_t tb;        // 1: assemble the op string
+    int64_t prot_off;  // the chain's letters in the device buffers
+    int64_t dna_off;
+    int64_t ops_off;   // the chain's op-string slot
+    int64_t ops_cap;   // bytes of that slot
+    int32_t res;       // index of the chain's result record
+    int32_t status;    // MPG_OK, or the chain's host-side error (it has no pieces then)
+};
+static_assert(sizeof(ChainJob) == 56, "ChainJob layout");
+
+// One wavefront per chain: add the runs' codon scores to the pieces' optima,
+// take the end coordinates from the last run and the right piece, and (tb)
+// concatenate the pieces' op strings with the runs as M tokens, merging
+// adjacent M tokens.  A chain whose piece failed gets that piece's status.
+hipError_t launch_stitch(hipStream_t s, const ChainJob* chains, int nchains, const int4* runs,
+                         const mpg_dev_result* pres, const char* pops, const uint8_t* prot,
+                         const uint8_t* dna, const DevParams& P, mpg_dev_result* out,
+                         char* ops);
+
 // Dynamic LDS bytes of one DP wavefront.
 int dp_lds_bytes(int K, bool tb);
 

@@ -159,6 +159,144 @@ __global__ void status_kernel(const PairJob* __restrict__ jobs, int npairs, DpSi
     publish(sink.out + J.res, R, sink.system);
 }
 
+// ------------------------------------------------------------------ stitch
+// First token "<len><op>" of s[beg, end): returns the op, sets *len and *next.
+__device__ __forceinline__ char head_token(const char* s, int beg, int end, int* len, int* next) {
+    int v = 0, i = beg;
+    while (i < end && s[i] >= '0' && s[i] <= '9') v = v * 10 + (s[i++] - '0');
+    *len = v;
+    *next = i + 1;
+    return i < end ? s[i] : 0;
+}
+
+__global__ void __launch_bounds__(64) stitch_kernel(const ChainJob* __restrict__ chains,
+                                                    int nchains, const int4* __restrict__ runs,
+                                                    const mpg_dev_result* __restrict__ pres,
+                                                    const char* __restrict__ pops,
+                                                    const uint8_t* __restrict__ prot,
+                                                    const uint8_t* __restrict__ dna, DevParams P,
+                                                    mpg_dev_result* __restrict__ out,
+                                                    char* __restrict__ ops) {
+    const int c = blockIdx.x;
+    if (c >= nchains) return;
+    const int lane = threadIdx.x;
+    const ChainJob C = chains[c];
+    mpg_dev_result R;
+    R.status = MPG_OK;
+    R.score = 0;
+    R.g_beg = R.g_end = R.p_beg = R.p_end = -1;
+    R.ops_off = C.ops_off;
+    R.ops_len = 0;
+    R._pad = 0;
+    if (C.status != MPG_OK) R.status = C.status;
+    for (int t = 0; t <= C.nruns && R.status == MPG_OK; ++t) {
+        const int st = pres[C.piece0 + t].status;
+        if (st != MPG_OK) {
+            R.status = st;
+            break;
+        }
+    }
+    char* txt = ops + C.ops_off;
+    if (R.status != MPG_OK) {
+        if (lane == 0) {
+            out[C.res] = R;
+            if (C.tb && C.ops_cap > 0) txt[0] = 0;
+        }
+        return;
+    }
+    // the runs' M steps: codon x+3u .. x+3u+2 against residue y+u, lanes over u
+    int acc = 0;
+    const uint8_t* T = dna + C.dna_off;
+    const uint8_t* Pa = prot + C.prot_off;
+    for (int r = 0; r < C.nruns; ++r) {
+        const int4 X = runs[C.run0 + r];
+        for (int u = lane; u < X.z; u += 64) {
+            const int g = X.x + 3 * u;
+            const int b1 = dna_code(T[g]), b2 = dna_code(T[g + 1]), b3 = dna_code(T[g + 2]);
+            const int tr = (b1 == 4 || b2 == 4 || b3 == 4) ? 22 : P.gcode[16 * b1 + 4 * b2 + b3];
+            acc += P.mat[tr * 24 + aa_code(Pa[X.y + u])];
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    for (int t = 0; t <= C.nruns; ++t) acc += pres[C.piece0 + t].score;
+    const mpg_dev_result L = pres[C.piece0];
+    const mpg_dev_result Rt = pres[C.piece0 + C.nruns];
+    const int4 last = runs[C.run0 + C.nruns - 1];
+    R.score = acc;
+    R.g_end = last.x + 3 * last.z + Rt.g_end;
+    R.p_end = last.y + last.z + Rt.p_end;
+    if (C.tb) {
+        R.g_beg = L.g_beg;
+        R.p_beg = L.p_beg;
+        // concatenate: left piece, then (run, following piece) per run; an M
+        // token at either end of a piece joins the pending M run
+        int64_t pos = 0;
+        int pend = 0;
+        bool overflow = false;
+        const int64_t room = (int64_t)C.ops_cap - 1;  // the NUL
+        auto emit_m = [&]() {
+            if (pend == 0) return;
+            const int nd = ndigits(pend);
+            if (pos + nd + 1 > room) {
+                overflow = true;
+                return;
+            }
+            if (lane == 0) {
+                int v = pend;
+                for (int d = nd - 1; d >= 0; --d) {
+                    txt[pos + d] = (char)('0' + v % 10);
+                    v /= 10;
+                }
+                txt[pos + nd] = 'M';
+            }
+            pos += nd + 1;
+            pend = 0;
+        };
+        for (int t = 0; t <= C.nruns && !overflow; ++t) {
+            if (t > 0) pend += runs[C.run0 + t - 1].z;
+            const mpg_dev_result& Q = pres[C.piece0 + t];
+            const char* s = pops + Q.ops_off;
+            const int len = Q.ops_len;
+            if (len <= 0) continue;
+            int v, nx;
+            int beg = 0;
+            if (head_token(s, 0, len, &v, &nx) == 'M') {
+                pend += v;
+                beg = nx;
+            }
+            if (beg >= len) continue;
+            // last token: digits back from the op letter
+            int end = len, tail = 0;
+            if (s[len - 1] == 'M') {
+                int j = len - 2;
+                while (j >= beg && s[j] >= '0' && s[j] <= '9') --j;
+                int w = 0;
+                for (int q = j + 1; q < len - 1; ++q) w = w * 10 + (s[q] - '0');
+                end = j + 1;
+                tail = w;
+            }
+            emit_m();
+            if (overflow || pos + (end - beg) > room) {
+                overflow = true;
+                break;
+            }
+            for (int q = beg + lane; q < end; q += 64) txt[pos + q - beg] = s[q];
+            pos += end - beg;
+            pend = tail;
+        }
+        emit_m();  // what is still pending after the right piece
+        if (overflow) {
+            R.status = MPG_E_DEVICE;
+            pos = 0;
+        }
+        if (lane == 0 && C.ops_cap > 0) txt[pos] = 0;
+        R.ops_len = (int32_t)pos;
+    }
+    __syncthreads();
+    if (lane == 0) out[C.res] = R;
+}
+
 }  // namespace dev
 
 hipError_t launch_dp_k1(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
@@ -213,6 +351,16 @@ hipError_t launch_walk(hipStream_t s, const PairJob* jobs, const int32_t* order,
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(walk_kernel, dim3(count), dim3(64), 0, s, jobs, order, count,
                        tbbuf, out, ops);
+    return hipGetLastError();
+}
+
+hipError_t launch_stitch(hipStream_t s, const ChainJob* chains, int nchains, const int4* runs,
+                         const mpg_dev_result* pres, const char* pops, const uint8_t* prot,
+                         const uint8_t* dna, const DevParams& P, mpg_dev_result* out,
+                         char* ops) {
+    if (nchains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stitch_kernel, dim3(nchains), dim3(64), 0, s, chains, nchains, runs, pres,
+                       pops, prot, dna, P, out, ops);
     return hipGetLastError();
 }
 

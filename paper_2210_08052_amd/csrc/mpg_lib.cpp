@@ -176,13 +176,15 @@ struct HostBuf {  // pinned host memory
 // from the batch stream and joined back with events.
 constexpr int kSideStreams = 8;
 struct Workspace {
-    DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops, state;
-    HostBuf hplan, hseq, hout, hops;
+    DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops, state, chain, piece_out,
+        piece_ops;
+    HostBuf hplan, hseq, hout, hops, hchain;
     HostBuf prec, pops;  // serving: host-mapped records and op strings the host polls
     void defer_frees(Retired* r) {
-        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state};
+        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state,
+                       &chain, &piece_out, &piece_ops};
         for (auto* b : d) b->later = r;
-        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops};
+        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops, &hchain};
         for (auto* b : h) b->later = r;
     }
     hipStream_t side[kSideStreams] = {};
@@ -202,9 +204,10 @@ struct Workspace {
         return MPG_OK;
     }
     void release() {
-        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state};
+        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state,
+                       &chain, &piece_out, &piece_ops};
         for (auto* b : d) b->release();
-        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops};
+        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops, &hchain};
         for (auto* b : h) b->release();
         if (streams_ready) {
             for (int k = 0; k < kSideStreams; ++k) {
@@ -265,9 +268,10 @@ struct Tuning {
 
 int strip_cols(int m, int K) { return ((m + 1 + 64 * K - 1) / (64 * K)) * 64 * K; }
 
-// Columns per lane: one width for all pairs of a call (pairs of one width
-// share a launch; mixed widths would split the device between concurrent
-// persistent launches): a forced width, else the tuned one, else 2.
+// Columns per lane: one width for the pairs of a call wider than 64 columns
+// (pairs of one width share a launch; mixed widths would split the device
+// between concurrent persistent launches): a forced width, else the tuned
+// one, else 2.  Pairs of at most 64 columns take width 1.
 struct KChoice {
     int K[2] = {2, 2};  // [traceback]
 };
@@ -410,9 +414,11 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
             !bound.ok(s.dlen, s.plen, J.mode))
             J.status = MPG_E_RANGE;
         const bool want_tb = ((s.flags | p->flags) & MPG_WANT_TB) != 0;
-        const int K = kc.K[want_tb ? 1 : 0];
-        J.K = K;
         const int nn = std::max(0, J.n), mm = std::max(0, J.m);
+        // a pair whose columns fit one strip of 64 takes one column per lane:
+        // wider lanes would only add idle columns to every step
+        const int K = (mm + 1 <= 64 && !ov.K && !cfg.force_K) ? 1 : kc.K[want_tb ? 1 : 0];
+        J.K = K;
         const int nsteps = ((nn + 64 + 63) / 64) * 64;
         J.nchunks = nsteps / 64;
         J.nstrips = (mm + 1 + 64 * K - 1) / (64 * K);
@@ -519,7 +525,7 @@ struct mpg_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pre, ev_dp, ev_walk;
     std::vector<hipEvent_t> ev_pool;
     double t_pre = 0, t_dp = 0, t_walk = 0, t_host = 0;
-    uint64_t n_dp = 0, n_calls = 0, n_i16 = 0;
+    uint64_t n_dp = 0, n_calls = 0, n_i16 = 0, n_cells = 0;
 
     // ---- serving
     std::mutex mu;
@@ -570,6 +576,7 @@ struct Timer {
     std::vector<hipEvent_t>* pool;
     double* host_ms;  // wall time spent planning and enqueuing on the host
     uint64_t* i16 = nullptr;  // pairs run in the int16 kernel
+    uint64_t* cells = nullptr;  // DP cells (n*m) of the pairs run
     hipEvent_t open[3] = {nullptr, nullptr, nullptr};
     hipEvent_t get() {
         hipEvent_t e = nullptr;
@@ -657,6 +664,9 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     X.npacks = npacks;
     if (tm && tm->i16)
         for (const PackJob& Q : P.packs) *tm->i16 += Q.b >= 0 ? 2 : 1;
+    if (tm && tm->cells)
+        for (const PairJob& J : P.jobs)
+            if (J.status == MPG_OK) *tm->cells += (uint64_t)J.n * (uint64_t)J.m;
     // work items of every launch, then the walk order (local job indices)
     std::vector<int2> items;
     X.goff.clear();
@@ -990,7 +1000,8 @@ int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot
     if (need > 0 && (!d_ops || ops_cap < need)) return MPG_E_RANGE;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
-    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16};
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
+             &ctx->n_cells};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -1339,6 +1350,125 @@ void scheduler(mpg_ctx* c) {
 
 }  // namespace
 
+// Anchor runs of one chain (Methods, opening paragraph: the DP closes the
+// gaps between the anchors of a chain and extends from its terminal ones).
+// Anchors arrive in genome order; one on the current run's diagonal that
+// overlaps or abuts it extends the run, one at or after the run's end in
+// both sequences starts a new run, any other is dropped.  Returns false for
+// an anchor outside the sequences.
+constexpr int64_t kMaxChainDna = (int64_t)1 << 30;  // longest region of one chain
+
+bool chain_runs(const mpg_chain_seg& ch, std::vector<int4>& runs) {
+    runs.clear();
+    const int64_t k = ch.k;
+    for (int32_t a = 0; a < ch.nanchors; ++a) {
+        const int64_t x = ch.anchors[2 * a], y = ch.anchors[2 * a + 1];
+        if (x < 0 || y < 0 || x + 3 * k > ch.dlen || y + k > ch.plen) return false;
+        if (!runs.empty()) {
+            int4& R = runs.back();
+            if (x - R.x == 3 * (y - R.y) && y >= R.y && y <= (int64_t)R.y + R.z) {
+                R.z = (int)std::max<int64_t>(R.z, y + k - R.y);
+                continue;
+            }
+            if (!(x >= (int64_t)R.x + 3 * R.z && y >= (int64_t)R.y + R.z)) continue;
+        }
+        runs.push_back(make_int4((int)x, (int)y, (int)k, 0));
+    }
+    return true;
+}
+
+bool chain_tb(const mpg_chain_seg& c, const mpg_params* p) {
+    return ((c.flags | p->flags) & MPG_WANT_TB) != 0;
+}
+
+// Enqueue the alignment of n chains whose letters are on the device: plan
+// the runs and pieces, run every piece in one batch (per-pair modes), then
+// the stitch kernel writes chain c's record d_out[c] and op string (slot at
+// the prefix sum of mpg_chain_ops_capacity).  Waits for earlier work on st
+// before reusing the staging buffers.
+int chains_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
+               const uint8_t* d_dna, const mpg_chain_seg* chains, int32_t n,
+               mpg_dev_result* d_out, char* d_ops, int64_t ops_cap, RunCfg cfg) {
+    std::vector<int4> runs, cr;
+    std::vector<ChainJob> cj(n);
+    std::vector<mpg_seg> psegs;
+    std::vector<int8_t> modes;
+    int64_t cops = 0;
+    for (int32_t c = 0; c < n; ++c) {
+        const mpg_chain_seg& ch = chains[c];
+        if (ch.plen < 0 || ch.dlen < 0 || ch.prot_off < 0 || ch.dna_off < 0 || ch.k <= 0 ||
+            ch.nanchors <= 0 || !ch.anchors)
+            return MPG_E_INVAL;
+        if (!chain_runs(ch, cr)) return MPG_E_INVAL;
+        const bool tb = chain_tb(ch, p);
+        ChainJob& J = cj[c];
+        J.piece0 = (int32_t)psegs.size();
+        J.nruns = 0;
+        J.run0 = (int32_t)runs.size();
+        J.tb = tb ? 1 : 0;
+        J.prot_off = ch.prot_off;
+        J.dna_off = ch.dna_off;
+        J.ops_off = cops;
+        J.ops_cap = tb ? 2 * ((int64_t)ch.plen + ch.dlen) + 1 : 1;
+        J.res = c;
+        J.status = MPG_OK;
+        cops += J.ops_cap;
+        if (ch.plen > MPG_MAX_PROT || ch.dlen > kMaxChainDna) {
+            J.status = MPG_E_RANGE;
+            continue;
+        }
+        J.nruns = (int32_t)cr.size();
+        auto piece = [&](int64_t p0, int64_t p1, int64_t d0, int64_t d1, int mode) {
+            mpg_seg s;
+            s.prot_off = ch.prot_off + p0;
+            s.plen = (int32_t)(p1 - p0);
+            s.dna_off = ch.dna_off + d0;
+            s.dlen = (int32_t)(d1 - d0);
+            s.flags = tb ? MPG_WANT_TB : 0;
+            s._pad = 0;
+            psegs.push_back(s);
+            modes.push_back((int8_t)mode);
+        };
+        piece(0, cr[0].y, 0, cr[0].x, MPG_EXTEND_LEFT);
+        for (size_t t = 0; t + 1 < cr.size(); ++t)
+            piece(cr[t].y + cr[t].z, cr[t + 1].y, cr[t].x + 3 * (int64_t)cr[t].z, cr[t + 1].x,
+                  MPG_GLOBAL);
+        const int4& L = cr.back();
+        piece(L.y + L.z, ch.plen, L.x + 3 * (int64_t)L.z, ch.dlen, MPG_EXTEND);
+        runs.insert(runs.end(), cr.begin(), cr.end());
+    }
+    if (cops > ops_cap) return MPG_E_RANGE;
+    const int32_t np = (int32_t)psegs.size();
+    const int64_t pops_cap = mpg_ops_capacity(psegs.data(), np);
+    const size_t cj_b = sizeof(ChainJob) * (size_t)n, run_b = sizeof(int4) * runs.size();
+    int rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    if ((rc = ws.piece_out.ensure(sizeof(mpg_dev_result) * (size_t)np + 64)) != MPG_OK) return rc;
+    if ((rc = ws.piece_ops.ensure((size_t)pops_cap + 64)) != MPG_OK) return rc;
+    if ((rc = ws.chain.ensure(cj_b + run_b + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hchain.ensure(cj_b + run_b + 64)) != MPG_OK) return rc;
+    std::memcpy(ws.hchain.p, cj.data(), cj_b);
+    if (run_b) std::memcpy((uint8_t*)ws.hchain.p + cj_b, runs.data(), run_b);
+    if (hipMemcpyAsync(ws.chain.p, ws.hchain.p, cj_b + run_b, hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return MPG_E_DEVICE;
+    mpg_dev_result* d_pres = (mpg_dev_result*)ws.piece_out.p;
+    char* d_pops = (char*)ws.piece_ops.p;
+    cfg.modes = modes.data();
+    if (np > 0) {
+        rc = run_dev_waves(st, ws, p, d_prot, d_dna, psegs.data(), np, d_pres, d_pops, cfg);
+        if (rc != MPG_OK) return rc;
+    }
+    DevParams DP;
+    make_dev_params(p, &DP);
+    const ChainJob* d_cj = (const ChainJob*)ws.chain.p;
+    const int4* d_runs = (const int4*)((const uint8_t*)ws.chain.p + cj_b);
+    if (launch_stitch(st, d_cj, n, d_runs, d_pres, d_pops, d_prot, d_dna, DP, d_out, d_ops) !=
+        hipSuccess)
+        return MPG_E_DEVICE;
+    return MPG_OK;
+}
+
 // Coding sequence of one traced alignment (Methods, "Avoiding pseudogenes"):
 // the genome bases the op string consumes, in path order, without the
 // interior of any intron.  A phase-0 intron (N) contributes nothing; a
@@ -1404,7 +1534,8 @@ int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, in
     if (n == 0) return MPG_OK;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
-    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16};
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
+             &ctx->n_cells};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -1412,6 +1543,129 @@ int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, in
     cfg.ncu = g_num_cu;
     cfg.tune = &ctx->tune;
     return align_host(ctx->stream, ctx->ws, p, pairs, n, out, cfg);
+}
+
+int64_t mpg_chain_ops_capacity(const mpg_params* p, const mpg_chain_seg* chains, int32_t n) {
+    if (!p || n < 0 || (n > 0 && !chains)) return 0;
+    int64_t o = 0;
+    for (int32_t c = 0; c < n; ++c)
+        o += chain_tb(chains[c], p)
+                 ? 2 * ((int64_t)std::max(0, chains[c].plen) + std::max(0, chains[c].dlen)) + 1
+                 : 1;
+    return o;
+}
+
+int mpg_align_chains_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot,
+                         const uint8_t* d_dna, const mpg_chain_seg* chains, int32_t n,
+                         mpg_dev_result* d_out, char* d_ops, int64_t ops_cap) {
+    if (!ctx || !p || n < 0 || (n > 0 && (!chains || !d_out || !d_ops))) return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    if (n == 0) return MPG_OK;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
+             &ctx->n_cells};
+    ctx->n_calls++;
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.tm = ctx->timing ? &tm : nullptr;
+    cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
+    return chains_dev(ctx->stream, ctx->ws, p, d_prot, d_dna, chains, n, d_out, d_ops, ops_cap,
+                      cfg);
+}
+
+int mpg_align_chains(mpg_ctx* ctx, const mpg_params* p, const mpg_chain* chains, int32_t n,
+                     mpg_result* out) {
+    if (!ctx || !p || n < 0 || (n > 0 && (!chains || !out))) return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    if (n == 0) return MPG_OK;
+    std::vector<mpg_chain_seg> cs(n);
+    int64_t pbytes = 0, dbytes = 0;
+    for (int32_t c = 0; c < n; ++c) {
+        const mpg_chain& ch = chains[c];
+        if (ch.plen < 0 || ch.dlen < 0 || (ch.plen && !ch.prot) || (ch.dlen && !ch.dna))
+            return MPG_E_INVAL;
+        cs[c].prot_off = pbytes;
+        cs[c].dna_off = dbytes;
+        cs[c].plen = ch.plen;
+        cs[c].dlen = ch.dlen;
+        cs[c].anchors = ch.anchors;
+        cs[c].nanchors = ch.nanchors;
+        cs[c].k = ch.k;
+        cs[c].flags = ch.flags;
+        cs[c]._pad = 0;
+        pbytes += ch.plen;
+        dbytes += ch.dlen;
+    }
+    const int64_t cops = mpg_chain_ops_capacity(p, cs.data(), n);
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
+             &ctx->n_cells};
+    ctx->n_calls++;
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.tm = ctx->timing ? &tm : nullptr;
+    cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
+    Workspace& ws = ctx->ws;
+    hipStream_t st = ctx->stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    if ((rc = ws.seq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return rc;
+    if ((rc = ws.out.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return rc;
+    if ((rc = ws.ops.ensure((size_t)cops + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hseq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hout.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return rc;
+    uint8_t* hs = (uint8_t*)ws.hseq.p;
+    for (int32_t c = 0; c < n; ++c) {
+        if (chains[c].plen) std::memcpy(hs + cs[c].prot_off, chains[c].prot, chains[c].plen);
+        if (chains[c].dlen) std::memcpy(hs + pbytes + cs[c].dna_off, chains[c].dna, chains[c].dlen);
+    }
+    uint8_t* d_seq = (uint8_t*)ws.seq.p;
+    if (pbytes + dbytes > 0 &&
+        hipMemcpyAsync(d_seq, hs, (size_t)(pbytes + dbytes), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        return MPG_E_DEVICE;
+    mpg_dev_result* d_cres = (mpg_dev_result*)ws.out.p;
+    char* d_cops = (char*)ws.ops.p;
+    rc = chains_dev(st, ws, p, d_seq, d_seq + pbytes, cs.data(), n, d_cres, d_cops, cops, cfg);
+    if (rc != MPG_OK) return rc;
+    if (hipMemcpyAsync(ws.hout.p, d_cres, sizeof(mpg_dev_result) * (size_t)n,
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+        return MPG_E_DEVICE;
+    bool any_tb = false;
+    for (int32_t c = 0; c < n; ++c) any_tb |= chain_tb(cs[c], p);
+    if (any_tb) {
+        if ((rc = ws.hops.ensure((size_t)cops + 64)) != MPG_OK) return rc;
+        if (hipMemcpyAsync(ws.hops.p, d_cops, (size_t)cops, hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+            return MPG_E_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    const mpg_dev_result* R = (const mpg_dev_result*)ws.hout.p;
+    for (int32_t c = 0; c < n; ++c) {
+        mpg_result& o = out[c];
+        std::memset(&o, 0, sizeof(o));
+        o.job_id = (uint64_t)c;
+        o.status = R[c].status;
+        o.score = R[c].score;
+        o.g_beg = R[c].g_beg;
+        o.g_end = R[c].g_end;
+        o.p_beg = R[c].p_beg;
+        o.p_end = R[c].p_end;
+        if (chain_tb(cs[c], p) && o.status == MPG_OK) {
+            char* sdup = (char*)std::malloc((size_t)R[c].ops_len + 1);
+            if (!sdup) return MPG_E_NOMEM;
+            std::memcpy(sdup, (const char*)ws.hops.p + R[c].ops_off, (size_t)R[c].ops_len);
+            sdup[R[c].ops_len] = 0;
+            o.ops = sdup;
+            o.ops_len = R[c].ops_len;
+        }
+    }
+    return MPG_OK;
 }
 
 int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs,
@@ -1456,7 +1710,8 @@ int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs
     std::vector<mpg_result> out(sub.size());
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
-    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16};
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
+             &ctx->n_cells};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -1831,9 +2086,10 @@ int mpg_get_timing(mpg_ctx* ctx, mpg_timing* t, int reset) {
     t->calls = ctx->n_calls;
     t->host_ms = ctx->t_host;
     t->i16_pairs = ctx->n_i16;
+    t->cells = ctx->n_cells;
     if (reset) {
         ctx->t_pre = ctx->t_dp = ctx->t_walk = ctx->t_host = 0;
-        ctx->n_dp = ctx->n_calls = ctx->n_i16 = 0;
+        ctx->n_dp = ctx->n_calls = ctx->n_i16 = ctx->n_cells = 0;
     }
     return MPG_OK;
 }

@@ -45,6 +45,20 @@ class mpg_result(ctypes.Structure):
                 ("t_done_ns", ctypes.c_int64)]
 
 
+class mpg_chain(ctypes.Structure):
+    _fields_ = [("prot", ctypes.c_char_p), ("plen", ctypes.c_int32),
+                ("dna", ctypes.c_char_p), ("dlen", ctypes.c_int32),
+                ("anchors", ctypes.c_void_p), ("nanchors", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("flags", ctypes.c_uint32), ("_pad", ctypes.c_int32)]
+
+
+class mpg_chain_seg(ctypes.Structure):
+    _fields_ = [("prot_off", ctypes.c_int64), ("dna_off", ctypes.c_int64),
+                ("plen", ctypes.c_int32), ("dlen", ctypes.c_int32),
+                ("anchors", ctypes.c_void_p), ("nanchors", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("flags", ctypes.c_uint32), ("_pad", ctypes.c_int32)]
+
+
 class mpg_seg(ctypes.Structure):
     _fields_ = [("prot_off", ctypes.c_int64), ("dna_off", ctypes.c_int64),
                 ("plen", ctypes.c_int32), ("dlen", ctypes.c_int32), ("flags", ctypes.c_uint32),
@@ -69,7 +83,7 @@ class mpg_timing(ctypes.Structure):
     _fields_ = [("prepass_ms", ctypes.c_double), ("dp_ms", ctypes.c_double),
                 ("walk_ms", ctypes.c_double), ("dp_spans", ctypes.c_uint64),
                 ("calls", ctypes.c_uint64), ("host_ms", ctypes.c_double),
-                ("i16_pairs", ctypes.c_uint64)]
+                ("i16_pairs", ctypes.c_uint64), ("cells", ctypes.c_uint64)]
 
 
 class mpg_tuning(ctypes.Structure):
@@ -88,7 +102,8 @@ EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_de
            "mpg_sync", "mpg_submit", "mpg_poll", "mpg_cancel", "mpg_get_stats",
            "mpg_result_release", "mpg_strerror", "mpg_enable_timing", "mpg_get_timing",
            "mpg_autotune", "mpg_plan_create", "mpg_plan_launch", "mpg_plan_graph",
-           "mpg_plan_destroy", "mpg_rescore_spliced"]
+           "mpg_plan_destroy", "mpg_rescore_spliced", "mpg_align_chains",
+           "mpg_chain_ops_capacity", "mpg_align_chains_dev"]
 
 _lib = None
 
@@ -147,6 +162,13 @@ def lib():
         L.mpg_rescore_spliced.argtypes = [ctypes.c_void_p, P(mpg_params), P(mpg_pair),
                                           P(mpg_result), ctypes.c_int32, P(ctypes.c_int32),
                                           P(ctypes.c_int32), P(ctypes.c_int32)]
+        L.mpg_align_chains.argtypes = [ctypes.c_void_p, P(mpg_params), P(mpg_chain),
+                                       ctypes.c_int32, P(mpg_result)]
+        L.mpg_chain_ops_capacity.argtypes = [P(mpg_params), P(mpg_chain_seg), ctypes.c_int32]
+        L.mpg_chain_ops_capacity.restype = ctypes.c_int64
+        L.mpg_align_chains_dev.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
+                                           ctypes.c_void_p, P(mpg_chain_seg), ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
         L.mpg_strerror.argtypes = [ctypes.c_int]
         L.mpg_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -241,6 +263,37 @@ class Context:
         res = [_result_dict(out[k]) for k in range(n)]
         lib().mpg_result_release(self.ptr, out, n)
         return res
+
+    def align_chains(self, chains, p: mpg_params, want_tb=None):
+        """chains: list of (prot, dna, anchors [(x, y), ...], k[, want_tb]);
+        returns a list of result dicts."""
+        n = len(chains)
+        arr = (mpg_chain * max(n, 1))()
+        keep = []
+        for c, ch in enumerate(chains):
+            prot = ch[0].encode() if isinstance(ch[0], str) else bytes(ch[0])
+            dna = ch[1].encode() if isinstance(ch[1], str) else bytes(ch[1])
+            anc = np.ascontiguousarray(np.asarray(ch[2], dtype=np.int32).reshape(-1))
+            tb = ch[4] if len(ch) > 4 else want_tb
+            keep.append((prot, dna, anc))
+            arr[c].prot, arr[c].plen, arr[c].dna, arr[c].dlen = prot, len(prot), dna, len(dna)
+            arr[c].anchors = anc.ctypes.data if anc.size else None
+            arr[c].nanchors = anc.size // 2
+            arr[c].k = int(ch[3])
+            arr[c].flags = MPG_WANT_TB if tb else 0
+        out = (mpg_result * max(n, 1))()
+        check(lib().mpg_align_chains(self.ptr, ctypes.byref(p), arr, n, out), "mpg_align_chains")
+        res = [_result_dict(out[k]) for k in range(n)]
+        lib().mpg_result_release(self.ptr, out, n)
+        return res
+
+    def align_chains_dev(self, p: mpg_params, d_prot, d_dna, chains, d_out, d_ops,
+                         ops_cap: int):
+        """Enqueue on the context's stream; chains is a ChainSegs (pack_chains)."""
+        check(lib().mpg_align_chains_dev(self.ptr, ctypes.byref(p), ctypes.c_void_p(d_prot),
+                                         ctypes.c_void_p(d_dna), chains.arr, chains.n,
+                                         ctypes.c_void_p(d_out), ctypes.c_void_p(d_ops),
+                                         ops_cap), "mpg_align_chains_dev")
 
     def rescore_spliced(self, pairs, results, p: mpg_params):
         """Pseudogene guard for traced results of align_batch on the same
@@ -385,6 +438,41 @@ def _result_dict(r: mpg_result) -> dict:
     return {"status": r.status, "score": r.score, "g_beg": r.g_beg, "g_end": r.g_end,
             "p_beg": r.p_beg, "p_end": r.p_end, "ops": ops, "job_id": int(r.job_id),
             "t_arrive_ns": int(r.t_arrive_ns), "t_done_ns": int(r.t_done_ns)}
+
+
+class ChainSegs:
+    """Device-resident chains: the mpg_chain_seg array and the anchors it
+    points to (kept alive here)."""
+
+    def __init__(self, arr, n, keep):
+        self.arr, self.n, self._keep = arr, n, keep
+
+    def ops_capacity(self, p: mpg_params) -> int:
+        return int(lib().mpg_chain_ops_capacity(ctypes.byref(p), self.arr, self.n))
+
+
+def pack_chains(chains):
+    """chains: list of (prot, dna, anchors, k[, want_tb]); returns
+    (prot_bytes, dna_bytes, ChainSegs) for align_chains_dev."""
+    n = len(chains)
+    arr = (mpg_chain_seg * max(n, 1))()
+    keep, pb, db = [], [], []
+    po = do = 0
+    for c, ch in enumerate(chains):
+        prot, dna = bytes(ch[0]), bytes(ch[1])
+        anc = np.ascontiguousarray(np.asarray(ch[2], dtype=np.int32).reshape(-1))
+        keep.append(anc)
+        arr[c].prot_off, arr[c].dna_off = po, do
+        arr[c].plen, arr[c].dlen = len(prot), len(dna)
+        arr[c].anchors = anc.ctypes.data if anc.size else None
+        arr[c].nanchors = anc.size // 2
+        arr[c].k = int(ch[3])
+        arr[c].flags = MPG_WANT_TB if (len(ch) > 4 and ch[4]) else 0
+        pb.append(prot)
+        db.append(dna)
+        po += len(prot)
+        do += len(dna)
+    return b"".join(pb), b"".join(db), ChainSegs(arr, n, keep)
 
 
 def pack_pairs(pairs):

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import chain as ochain
 from oracle import pseudo
 from paper_2210_08052_amd import mpg
 from paper_2210_08052_amd import workloads as W
@@ -446,3 +447,117 @@ def test_rescore_spliced_rejects_bad_ops(ctx):
         ctx.rescore_spliced(pairs, [bad], g)
     assert ctx.rescore_spliced(pairs, [dict(r, status=mpg.MPG_E_NOALN)], g) == \
         [(mpg.MPG_E_NOALN, 0, 0)]
+
+
+def _chain_key(r, tb, gpu):
+    st = r["status"] if gpu else r.status
+    if st != 0:
+        return ("status", st)
+    if gpu:
+        t = (r["score"], r["g_beg"], r["g_end"], r["p_beg"], r["p_end"], r["ops"])
+    else:
+        t = (r.score, r.g_beg, r.g_end, r.p_beg, r.p_end, r.ops)
+    return t if tb else (t[0], t[2], t[4])
+
+
+def _chain_edge_cases():
+    rp = W.random_pairs(2, 808, max_prot=100, max_dna=300, min_prot=100, min_dna=300)
+    P, D = rp[0].prot, rp[0].dna
+    return [
+        (b"MKVLAT", b"ATGAAAGTTCTGGCGACC", [(0, 0)], 6),          # one run, empty pieces
+        (b"MKVLAT", b"ATGAAAGTTCTGGCGACC", [(0, 0), (9, 3)], 3),  # abutting: one run
+        (b"MKVL", b"ATGAAACCGTTCTG", [(0, 0), (8, 2)], 2),        # 2-nt gap, no residue
+        (P, D, [(30, 10), (33, 11), (51, 17)], 6),                 # collinear overlap
+        (P, D, [(30, 10), (36, 11), (120, 50)], 6),                # off-diagonal dropped
+        (P, D, [(0, 0), (282, 94)], 6),                            # anchors at both ends
+        (P, D, [(150, 0)], 6),                                     # left piece: no protein
+        (P, D, [(0, 50)], 6),                                      # left piece: no genome
+        (P, D, [(282, 50)], 6),                                    # right piece: no genome
+    ]
+
+
+@pytest.mark.parametrize("tb", [False, True])
+@pytest.mark.parametrize("flags,rs", [(0, None), (2, None), (3, None), (0, 601), (2, 602)])
+def test_chains(ctx, tb, flags, rs):
+    """Anchor-driven alignment: the HIP path (one batch of EXTEND_LEFT,
+    GLOBAL and EXTEND pieces, then the stitch kernel) against the oracle's
+    orchestration, chain by chain."""
+    print("case chains tb=%d flags=%d rs=%s" % (tb, flags, rs), flush=True)
+    g, o = scorings(0, flags, rand_seed=rs)
+    cases = [(p.prot, p.dna, a, 6) for p, a in W.chain_jobs(40, seed=70 + flags + (rs or 0))]
+    cases += _chain_edge_cases()
+    got = ctx.align_chains([c + (tb,) for c in cases], g)
+    bad = []
+    for k, (c, r) in enumerate(zip(cases, got)):
+        want = ochain.align_chain(c[0].decode(), c[1].decode(), c[2], c[3], o, want_tb=tb)
+        if _chain_key(r, tb, True) != _chain_key(want, tb, False):
+            bad.append((k, _chain_key(r, tb, True), _chain_key(want, tb, False)))
+    assert not bad, "%d/%d mismatches, first: %s" % (len(bad), len(cases), bad[:2])
+    if flags == 3:  # no intron states: gaps over introns have no path
+        assert any(r["status"] == mpg.MPG_E_NOALN for r in got)
+
+
+def test_chains_long_genes(ctx):
+    """Long planted genes (3-8k residues in 100-300 kb regions, long introns)
+    with sparse true anchors: many uneven pieces per chain."""
+    rng = np.random.default_rng(5)
+    cases = []
+    for p in W.long_tail(3, 0, seed=9):
+        hits = W.true_anchors(p, 6)
+        sel = [h for h, u in zip(hits, rng.random(len(hits))) if u < 0.05]
+        cases.append((p.prot, p.dna, sorted(sel), 6, True))
+    g, o = scorings(0, 0)
+    got = ctx.align_chains(cases, g)
+    for c, r in zip(cases, got):
+        want = ochain.align_chain(c[0].decode(), c[1].decode(), c[2], 6, o, want_tb=True)
+        assert _chain_key(r, True, True) == _chain_key(want, True, False)
+        assert "N" in r["ops"] or "U" in r["ops"] or "V" in r["ops"]
+
+
+def test_chains_errors(ctx):
+    g, _ = scorings(0, 0)
+    with pytest.raises(RuntimeError):
+        ctx.align_chains([(b"MKV", b"ATGAAAGTT", [], 3)], g)
+    with pytest.raises(RuntimeError):
+        ctx.align_chains([(b"MKV", b"ATGAAAGTT", [(3, 0)], 3)], g)
+    with pytest.raises(RuntimeError):
+        ctx.align_chains([(b"MKV", b"ATGAAAGTT", [(0, 0)], 0)], g)
+    r = ctx.align_chains([(b"M" * 32001, b"ATG" * 10, [(0, 0)], 2),
+                          (b"MKV", b"ATGAAAGTT", [(0, 0)], 3)], g, want_tb=True)
+    assert r[0]["status"] == mpg.MPG_E_RANGE
+    assert r[1]["status"] == 0 and r[1]["ops"] == "3M"
+
+
+def test_chains_dev_matches_host(ctx):
+    """Device-resident chains (the bench's entry point) give the host entry
+    point's results; the op-string slots follow mpg_chain_ops_capacity."""
+    import torch
+    cases = [(p.prot, p.dna, a, 6, k % 2 == 0)
+             for k, (p, a) in enumerate(W.chain_jobs(30, seed=91))]
+    g, _ = scorings(0, 0)
+    ref = ctx.align_chains(cases, g)
+    pb, db, cs = mpg.pack_chains(cases)
+    dev = torch.device("cuda:0")
+    d_prot = torch.frombuffer(bytearray(pb), dtype=torch.uint8).to(dev)
+    d_dna = torch.frombuffer(bytearray(db), dtype=torch.uint8).to(dev)
+    cap = cs.ops_capacity(g)
+    assert cap == sum(2 * (len(c[0]) + len(c[1])) + 1 if c[4] else 1 for c in cases)
+    d_ops = torch.zeros(cap, dtype=torch.uint8, device=dev)
+    d_out = torch.zeros(len(cases) * mpg.DEV_RESULT_DTYPE.itemsize, dtype=torch.uint8,
+                        device=dev)
+    for rep in range(2):
+        ctx.align_chains_dev(g, d_prot.data_ptr(), d_dna.data_ptr(), cs, d_out.data_ptr(),
+                             d_ops.data_ptr(), cap)
+        ctx.sync()
+        out = np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=mpg.DEV_RESULT_DTYPE)
+        ops = d_ops.cpu().numpy().tobytes()
+        for k, r in enumerate(ref):
+            assert (out["status"][k], out["score"][k], out["g_end"][k], out["p_end"][k]) == (
+                r["status"], r["score"], r["g_end"], r["p_end"])
+            if k % 2 == 0:
+                o0 = int(out["ops_off"][k])
+                assert ops[o0:o0 + int(out["ops_len"][k])].decode() == r["ops"]
+                assert (out["g_beg"][k], out["p_beg"][k]) == (r["g_beg"], r["p_beg"])
+    with pytest.raises(RuntimeError):
+        ctx.align_chains_dev(g, d_prot.data_ptr(), d_dna.data_ptr(), cs, d_out.data_ptr(),
+                             d_ops.data_ptr(), cap - 1)
