@@ -59,6 +59,13 @@ def _load():
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
             ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_char_p,
             ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_align_profile.restype = ctypes.c_int
+        lib.orc_align_profile.argtypes = [
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
+            ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_char_p,
+            ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         lib.orc_dna_code.restype = ctypes.c_int
         lib.orc_aa_code.restype = ctypes.c_int
         _lib = lib
@@ -97,6 +104,38 @@ def align(prot, dna, sc: Scoring | None = None, want_tb: bool = True) -> Result:
                        sc.mat.ctypes.data, sc.gcode.ctypes.data, sc.donor.ctypes.data,
                        sc.acceptor.ctypes.data, 1 if want_tb else 0, out, buf, cap,
                        ctypes.byref(olen))
+    if st == E_NOALN:
+        return Result(st, 0, -1, -1, -1, -1, None)
+    if st != OK:
+        raise RuntimeError("oracle failed with status %d" % st)
+    ops = buf.raw[: olen.value].decode() if want_tb else None
+    return Result(OK, int(out[0]), int(out[1]), int(out[2]), int(out[3]), int(out[4]), ops)
+
+
+def align_profile(S, gap, dna, sc: Scoring | None = None, want_tb: bool = True) -> Result:
+    """Align a position-specific query to one genomic region.
+
+    S: (m, 24) int8, the score of each translated amino acid at each column;
+    gap: (m + 1, 4) int16, per column the I open/extend costs (columns 1..m)
+    and the D open/extend costs (columns 0..m).  sc supplies f, r, the flags,
+    the mode, the genetic code and the splice tables (its q, e and matrix are
+    not used)."""
+    lib = _load()
+    sc = sc or default_scoring()
+    S = np.ascontiguousarray(S, dtype=np.int8)
+    gap = np.ascontiguousarray(gap, dtype=np.int16)
+    m = S.shape[0]
+    if S.shape != (m, 24) or gap.shape != (m + 1, 4):
+        raise ValueError("profile shapes")
+    d = _b(dna)
+    out = (ctypes.c_int64 * 5)()
+    cap = 2 * (m + len(d)) + 64 if want_tb else 1
+    buf = ctypes.create_string_buffer(cap)
+    olen = ctypes.c_int64(0)
+    st = lib.orc_align_profile(S.ctypes.data, gap.ctypes.data, m, d, len(d), sc.f, sc.r,
+                               sc.flags, sc.mode, sc.gcode.ctypes.data, sc.donor.ctypes.data,
+                               sc.acceptor.ctypes.data, 1 if want_tb else 0, out, buf, cap,
+                               ctypes.byref(olen))
     if st == E_NOALN:
         return Result(st, 0, -1, -1, -1, -1, None)
     if st != OK:

@@ -45,14 +45,35 @@ def _enc_aa(s: str):
     return out
 
 
-def best_score(prot: str, dna: str, sc) -> float:
+def best_score(prot: str, dna: str, sc, S=None, gap=None) -> float:
     """Maximum path score for ``sc.mode`` (LOCAL=0, EXTEND=1, GLOBAL=2,
     EXTEND_LEFT=3: start anywhere, end at (n, m)); -inf when GLOBAL has no
-    path."""
+    path.
+
+    With a position-specific query (S: m rows of 24 scores, gap: m+1 rows of
+    I open, I extend, D open, D extend) prot is ignored: a codon at column j
+    scores S[j-1][codon's amino acid], a run of residues j0..j1 against no
+    genome costs I-open(j0) + the I-extend costs of j0..j1, and a run of L
+    codons against no residue after column j costs D-open(j) + L D-extend(j)."""
     T = [4] + _enc_dna(dna)   # 1-based
-    P = [22] + _enc_aa(prot)
+    P = [22] + (_enc_aa(prot) if S is None else [0] * len(S))
     n, m = len(T) - 1, len(P) - 1
     q, e, f, r = sc.q, sc.e, sc.f, sc.r
+
+    def subst(i, j):
+        if S is None:
+            return int(sc.mat[tr(i)][P[j]])
+        return int(S[j - 1][tr(i)])
+
+    def ins_cost(j0, j1):
+        if gap is None:
+            return q + e * (j1 - j0 + 1)
+        return int(gap[j0][0]) + sum(int(gap[u][1]) for u in range(j0, j1 + 1))
+
+    def del_cost(j, L):
+        if gap is None:
+            return q + e * L
+        return int(gap[j][2]) + L * int(gap[j][3])
     no_intron = bool(sc.flags & 1)
     no_fs = bool(sc.flags & 2)
     local = sc.mode in (0, 3)
@@ -78,11 +99,11 @@ def best_score(prot: str, dna: str, sc) -> float:
             return NEG
         v = 0 if (local or (i == 0 and j == 0)) else NEG
         if i >= 3 and j >= 1:
-            v = max(v, best_to(i - 3, j - 1) + int(sc.mat[tr(i)][P[j]]))
+            v = max(v, best_to(i - 3, j - 1) + subst(i, j))
         for L in range(1, j + 1):
-            v = max(v, best_to(i, j - L) - (q + e * L))
+            v = max(v, best_to(i, j - L) - ins_cost(j - L + 1, j))
         for L in range(1, i // 3 + 1):
-            v = max(v, best_to(i - 3 * L, j) - (q + e * L))
+            v = max(v, best_to(i - 3 * L, j) - del_cost(j, L))
         if not no_fs:
             for k in (1, 2):
                 v = max(v, best_to(i - k, j - 1) - f)

@@ -30,13 +30,34 @@ def translate(dna: str, frame: int, codon_table: dict) -> str:
     return "".join(out)
 
 
-def gotoh(prot: str, xlat: str, mat, q: int, e: int, kind: str) -> float:
+def gotoh(prot: str, xlat: str, mat, q: int, e: int, kind: str, S=None, gap=None) -> float:
     """kind: 'local' (Smith-Waterman-Gotoh), 'extend' (start at (0,0), free
     end), 'global' (Needleman-Wunsch-Gotoh) or 'end' (start anywhere, end at
-    the last codon and the last residue)."""
-    P = [(_AA.index(c.upper()) if c.upper() in _AA else 22) for c in prot]
+    the last codon and the last residue).  With a position-specific query (S,
+    gap as in brute.best_score) prot and mat are not used: residue b scores
+    S[b-1][codon], and the gap costs of the affine recurrences are the ones of
+    the column the gap is at."""
+    if S is None:
+        P = [(_AA.index(c.upper()) if c.upper() in _AA else 22) for c in prot]
+    else:
+        P = [0] * len(S)
     X = [(_AA.index(c) if c in _AA else 22) for c in xlat]
     L, m = len(X), len(P)
+
+    def sub(a, b):  # codon a (1-based) against residue b (1-based)
+        return int(mat[X[a - 1]][P[b - 1]]) if S is None else int(S[b - 1][X[a - 1]])
+
+    def oi(b):  # open + first extension of a residue gap at column b
+        return q + e if gap is None else int(gap[b][0]) + int(gap[b][1])
+
+    def ei(b):
+        return e if gap is None else int(gap[b][1])
+
+    def od(b):
+        return q + e if gap is None else int(gap[b][2]) + int(gap[b][3])
+
+    def ed(b):
+        return e if gap is None else int(gap[b][3])
 
     def start(a, b):
         if kind in ("local", "end"):
@@ -50,14 +71,14 @@ def gotoh(prot: str, xlat: str, mat, q: int, e: int, kind: str) -> float:
     for a in range(L + 1):
         for b in range(m + 1):
             if a >= 1 and b >= 1:
-                M[a][b] = int(mat[X[a - 1]][P[b - 1]]) + max(
+                M[a][b] = sub(a, b) + max(
                     M[a - 1][b - 1], Ix[a - 1][b - 1], Dy[a - 1][b - 1], start(a - 1, b - 1))
             if b >= 1:
-                Ix[a][b] = max(M[a][b - 1] - q - e, Ix[a][b - 1] - e,
-                               Dy[a][b - 1] - q - e, start(a, b - 1) - q - e)
+                Ix[a][b] = max(M[a][b - 1] - oi(b), Ix[a][b - 1] - ei(b),
+                               Dy[a][b - 1] - oi(b), start(a, b - 1) - oi(b))
             if a >= 1:
-                Dy[a][b] = max(M[a - 1][b] - q - e, Dy[a - 1][b] - e,
-                               Ix[a - 1][b] - q - e, start(a - 1, b) - q - e)
+                Dy[a][b] = max(M[a - 1][b] - od(b), Dy[a - 1][b] - ed(b),
+                               Ix[a - 1][b] - od(b), start(a - 1, b) - od(b))
             if kind in ("local", "extend"):
                 best = max(best, M[a][b], Ix[a][b], Dy[a][b])
     if kind == "global":
@@ -69,7 +90,7 @@ def gotoh(prot: str, xlat: str, mat, q: int, e: int, kind: str) -> float:
     return best
 
 
-def spliced_reduction(prot: str, dna: str, sc, codon_table: dict) -> float:
+def spliced_reduction(prot: str, dna: str, sc, codon_table: dict, S=None, gap=None) -> float:
     """Expected Eq. (full) score with introns and frameshifts disabled.
 
     LOCAL: best Smith-Waterman-Gotoh over the three forward frames.
@@ -78,12 +99,12 @@ def spliced_reduction(prot: str, dna: str, sc, codon_table: dict) -> float:
     EXTEND_LEFT: the frame whose last codon ends at the region's end, free
     start, fixed end."""
     if sc.mode == 0:
-        return max(gotoh(prot, translate(dna, ph, codon_table), sc.mat, sc.q, sc.e, "local")
+        return max(gotoh(prot, translate(dna, ph, codon_table), sc.mat, sc.q, sc.e, "local", S, gap)
                    for ph in range(3))
     if sc.mode == 1:
-        return gotoh(prot, translate(dna, 0, codon_table), sc.mat, sc.q, sc.e, "extend")
+        return gotoh(prot, translate(dna, 0, codon_table), sc.mat, sc.q, sc.e, "extend", S, gap)
     if sc.mode == 3:
-        return gotoh(prot, translate(dna, len(dna) % 3, codon_table), sc.mat, sc.q, sc.e, "end")
+        return gotoh(prot, translate(dna, len(dna) % 3, codon_table), sc.mat, sc.q, sc.e, "end", S, gap)
     if len(dna) % 3 != 0:
         return NEG
-    return gotoh(prot, translate(dna, 0, codon_table), sc.mat, sc.q, sc.e, "global")
+    return gotoh(prot, translate(dna, 0, codon_table), sc.mat, sc.q, sc.e, "global", S, gap)

@@ -182,11 +182,49 @@ static int emit(tok_t **v, int64_t *nv, int64_t *cap, char op, int64_t len, int 
  * Returns 0, -6 (GLOBAL end unreachable), -3 (out of memory), -2 (ops buffer
  * too small) or -1 (unknown mode).
  */
+static int align_core(const char *prot, int32_t m, const char *dna, int32_t n,
+                      int64_t q, int64_t e, int64_t f, int64_t r, int32_t flags, int32_t mode,
+                      const int8_t *mat, const int8_t *S, const int16_t *gap,
+                      const uint8_t *gcode, const uint8_t *donor, const uint8_t *acceptor,
+                      int32_t want_tb, int64_t *out, char *ops, int64_t ops_cap,
+                      int64_t *ops_len);
+
 int orc_align(const char *prot, int32_t m, const char *dna, int32_t n,
               int64_t q, int64_t e, int64_t f, int64_t r, int32_t flags, int32_t mode,
               const int8_t *mat, const uint8_t *gcode, const uint8_t *donor,
               const uint8_t *acceptor, int32_t want_tb,
               int64_t *out, char *ops, int64_t ops_cap, int64_t *ops_len)
+{
+    return align_core(prot, m, dna, n, q, e, f, r, flags, mode, mat, NULL, NULL, gcode, donor,
+                      acceptor, want_tb, out, ops, ops_cap, ops_len);
+}
+
+/*
+ * orc_align_profile: the same DP with a position-specific query of m columns
+ * in place of a protein and one matrix (the paper's outlook on profile
+ * queries: position-specific substitution and gap costs, Discussion).
+ *   S[24*(j-1) + a]  score of a codon translating to a at column j (1..m);
+ *   gap[4*j + 0, 1]  I open and extend at column j (1..m): residue j against
+ *                    no genome, I(i,j) = max(H(i,j-1) - o, I(i,j-1)) - x;
+ *   gap[4*j + 2, 3]  D open and extend at column j (0..m): codons against no
+ *                    residue after column j, D(i,j) = max(H(i-3,j) - o, D(i-3,j)) - x.
+ * f, r and the splice tables are those of the uniform DP.
+ */
+int orc_align_profile(const int8_t *S, const int16_t *gap, int32_t m, const char *dna, int32_t n,
+                      int64_t f, int64_t r, int32_t flags, int32_t mode, const uint8_t *gcode,
+                      const uint8_t *donor, const uint8_t *acceptor, int32_t want_tb,
+                      int64_t *out, char *ops, int64_t ops_cap, int64_t *ops_len)
+{
+    return align_core(NULL, m, dna, n, 0, 0, f, r, flags, mode, NULL, S, gap, gcode, donor,
+                      acceptor, want_tb, out, ops, ops_cap, ops_len);
+}
+
+static int align_core(const char *prot, int32_t m, const char *dna, int32_t n,
+                      int64_t q, int64_t e, int64_t f, int64_t r, int32_t flags, int32_t mode,
+                      const int8_t *mat, const int8_t *S, const int16_t *gap,
+                      const uint8_t *gcode, const uint8_t *donor, const uint8_t *acceptor,
+                      int32_t want_tb, int64_t *out, char *ops, int64_t ops_cap,
+                      int64_t *ops_len)
 {
     orc_ctx c;
     rows_t rw;
@@ -224,7 +262,7 @@ int orc_align(const char *prot, int32_t m, const char *dna, int32_t n,
         goto done;
     }
     for (i = 1; i <= n; ++i) T[i] = (uint8_t)orc_dna_code((unsigned char)dna[i - 1]);
-    for (j = 1; j <= m; ++j) P[j] = (uint8_t)orc_aa_code((unsigned char)prot[j - 1]);
+    for (j = 1; j <= m; ++j) P[j] = S ? 0 : (uint8_t)orc_aa_code((unsigned char)prot[j - 1]);
     c.T = T; c.P = P;
 
     for (i = 0; i <= n; ++i) {
@@ -240,17 +278,17 @@ int orc_align(const char *prot, int32_t m, const char *dna, int32_t n,
 
             /* I: one residue against no genome */
             if (j >= 1) {
-                int64_t op = pen(getH(&rw, i, j - 1), q);
+                int64_t op = pen(getH(&rw, i, j - 1), gap ? gap[4 * j] : q);
                 int64_t ex = getS(rw.I, &rw, i, j - 1);
                 if (ex >= op) { Iv = ex; cc |= X_I; } else Iv = op;
-                Iv = pen(Iv, e);
+                Iv = pen(Iv, gap ? gap[4 * j + 1] : e);
             }
             /* D: one codon (3 nt) against no residue */
             if (i >= 3) {
-                int64_t op = pen(getH(&rw, i - 3, j), q);
+                int64_t op = pen(getH(&rw, i - 3, j), gap ? gap[4 * j + 2] : q);
                 int64_t ex = getS(rw.D, &rw, i - 3, j);
                 if (ex >= op) { Dv = ex; cc |= X_D; } else Dv = op;
-                Dv = pen(Dv, e);
+                Dv = pen(Dv, gap ? gap[4 * j + 3] : e);
             }
             if (!c.no_intron && i >= 1) {
                 /* A: phase-0 intron, opened from H(i-1,j) */
@@ -277,7 +315,8 @@ int orc_align(const char *prot, int32_t m, const char *dna, int32_t n,
             if (floor0) cand[C_START] = 0;
             else cand[C_START] = (i == 0 && j == 0) ? 0 : NEG;
             cand[C_M] = (i >= 3 && j >= 1)
-                ? addsc(getH(&rw, i - 3, j - 1), mat[tri * 24 + P[j]]) : NEG;
+                ? addsc(getH(&rw, i - 3, j - 1), S ? S[24 * (j - 1) + tri] : mat[tri * 24 + P[j]])
+                : NEG;
             cand[C_I] = Iv;
             cand[C_D] = Dv;
             if (!c.no_fs) {

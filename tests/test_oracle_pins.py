@@ -323,8 +323,8 @@ def test_left_extension_is_reversed_extension():
 # ------------------------------------------------- planted mistakes are caught
 MUTANTS = [
     # the printed match term H(i-3,j)+s consumes no residue
-    ("addsc(getH(&rw, i - 3, j - 1), mat[tri * 24 + P[j]])",
-     "addsc(getH(&rw, i - 3, j), mat[tri * 24 + P[j]])"),
+    ("addsc(getH(&rw, i - 3, j - 1), S ? S[24 * (j - 1) + tri] : mat[tri * 24 + P[j]])",
+     "addsc(getH(&rw, i - 3, j), S ? S[24 * (j - 1) + tri] : mat[tri * 24 + P[j]])"),
     # phase-1 donor read one base late
     ("int64_t op = pen(getH(&rw, i - 1, j - 1), r + d0);",
      "int64_t op = pen(getH(&rw, i - 1, j - 1), r + dp1);"),
@@ -334,7 +334,7 @@ MUTANTS = [
     ("cand[C_G2] = pen(getH(&rw, i - 2, j), f);",
      "cand[C_G2] = pen(getH(&rw, i - 2, j - 1), f);"),
     # gap extension cost dropped
-    ("Dv = pen(Dv, e);", "Dv = pen(Dv, 0);"),
+    ("Dv = pen(Dv, gap ? gap[4 * j + 3] : e);", "Dv = pen(Dv, gap ? gap[4 * j + 3] : 0);"),
     # wrong codon index order
     ("return c->gcode[16 * b1 + 4 * b2 + b3];", "return c->gcode[16 * b3 + 4 * b2 + b1];"),
     # left extension read at its best cell instead of at (n, m)
