@@ -303,6 +303,66 @@ int mpg_align_chains_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_pro
                          const uint8_t *d_dna, const mpg_chain_seg *chains, int32_t n,
                          mpg_dev_result *d_out, char *d_ops, int64_t ops_cap);
 
+/* ---- position-specific (profile) queries ---------------------------------- */
+
+/*
+ * A query given as a profile instead of a protein and one matrix: the
+ * position-specific substitution and gap costs that the paper's Discussion
+ * names for profile queries (HMMER families).  For columns j = 1..m:
+ *   score[24*(j-1) + a]  the score of a codon translating to amino acid a
+ *                        (order of mpg_params.mat) at column j;
+ *   gap[4*j + 0], [4*j + 1]  open and extend cost of column j's residue
+ *                        against no genome: I(i,j) = max(H(i,j-1) - open,
+ *                        I(i,j-1)) - extend;
+ * and for columns j = 0..m:
+ *   gap[4*j + 2], [4*j + 3]  open and extend cost of codons against no
+ *                        residue after column j: D(i,j) = max(H(i-3,j) - open,
+ *                        D(i-3,j)) - extend.
+ * (gap[0], gap[1] are unused.)  Costs lie in [0, 8191], and each used
+ * open + extend pair is at least 1.  f, r, the splice tables, the genetic
+ * code, the mode and the flags come from mpg_params; its q, e and mat are not
+ * used.  A profile made of the matrix rows of a protein's residues with
+ * uniform costs q, e gives exactly the protein's results.
+ */
+typedef struct {
+    const int8_t *score;  /* m x 24 */
+    const int16_t *gap;   /* (m + 1) x 4 */
+    int32_t m;
+    const char *dna;
+    int32_t dlen;
+    uint32_t flags;       /* MPG_WANT_TB for this pair (OR-ed with params.flags) */
+} mpg_profile_pair;
+
+/* Align n profile queries to their regions (as mpg_align_batch; the int16
+ * kernel is not used).  MPG_E_INVAL for a cost outside the rules above. */
+int mpg_align_profiles(mpg_ctx *ctx, const mpg_params *p, const mpg_profile_pair *pairs,
+                       int32_t n, mpg_result *out);
+
+/* Bytes of the device layout of one profile: the m x 24 scores, zero-padded
+ * to a multiple of 8 bytes, then the (m + 1) x 4 gap costs. */
+int64_t mpg_profile_bytes(int32_t m);
+
+/* A profile query already in device memory. */
+typedef struct {
+    int64_t prof_off;  /* byte offset of the profile (mpg_profile_bytes layout) in d_prof;
+                          a multiple of 8 */
+    int64_t dna_off;   /* offset of the region in d_dna */
+    int32_t m;
+    int32_t dlen;
+    uint32_t flags;    /* MPG_WANT_TB */
+    int32_t smax;      /* >= every score entry, >= 0 */
+    int32_t pmax;      /* >= every used open + extend pair and >= -(every score entry) */
+    int32_t _pad;
+} mpg_profile_seg;
+
+/* As mpg_align_batch_dev for profile queries in device memory.  The library
+ * cannot read them before the launch: smax and pmax are taken as given (they
+ * size the score-bound check), and the cost rules above are the caller's to
+ * keep; values outside them give wrong results, never a fault. */
+int mpg_align_profiles_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prof,
+                           const uint8_t *d_dna, const mpg_profile_seg *segs, int32_t n,
+                           mpg_dev_result *d_out, char *d_ops, int64_t ops_cap);
+
 /* ---- serving ------------------------------------------------------------ */
 
 /*

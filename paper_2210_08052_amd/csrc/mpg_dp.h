@@ -202,7 +202,9 @@ __device__ __forceinline__ bool wait_prog(const int* flag, int target) {
 // strips of a long pair run as a pipeline spread over many CUs, and every
 // wavefront slot stays busy until the queue is empty.  Dependencies only point
 // to items taken earlier by running wavefronts, so the waits always end.
-template <int K, int MODE, bool TB, bool NOI, bool NOF>
+// PRO: the query is a position-specific profile block (prof_scores /
+// prof_gaps) instead of protein letters and one matrix.
+template <int K, int MODE, bool TB, bool NOI, bool NOF, bool PRO>
 __global__ void __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(WavesPerEu<K, TB>::value)))
 dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int nitems,
@@ -256,10 +258,12 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
 #pragma unroll
             for (int c = 0; c < K; ++c) {
                 const int j = col0 + c;
-                const int pc = (j >= 1 && j <= m) ? aa_code(Pa[j - 1]) : -1;
+                const int pc = (j >= 1 && j <= m) ? (PRO ? 0 : aa_code(Pa[j - 1])) : -1;
                 for (int tr = 0; tr < 25; ++tr) {
                     const bool poison = pc < 0 || tr == 24;
-                    const int sv = poison ? 0 : P.mat[tr * 24 + pc];
+                    const int sv = poison ? 0
+                                          : (PRO ? (int)prof_scores(Pa)[24 * (j - 1) + tr]
+                                                 : (int)P.mat[tr * 24 + pc]);
                     if (TB)
                         ((int16_t*)prof)[tr * LY::SW + lane * K + c] =
                             (int16_t)(poison ? -32768 : 16 * sv + 14);
@@ -270,6 +274,25 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
             inb[lane] = make_int2(NEG, NEG);
         }
 
+        // gap costs of this lane's columns in the layout of the variant (a
+        // profile's own per column; columns beyond m take column m's)
+        int cqv[K], cqDv[K], cev[K], ceDv[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            if (PRO) {
+                const int16_t* g = prof_gaps(Pa, m) + 4 * imin(col0 + c, m);
+                const int oi = g[0], ei = g[1], od = g[2], ed = g[3];
+                cqv[c] = TB ? 16 * (oi + ei) - 13 : oi;
+                cev[c] = TB ? 16 * ei : ei;
+                cqDv[c] = TB ? 16 * (od + ed) - 12 : od;
+                ceDv[c] = TB ? 16 * ed : ed;
+            } else {
+                cqv[c] = cq;
+                cev[c] = ce;
+                cqDv[c] = cqD;
+                ceDv[c] = ce;
+            }
+        }
         int h1[K], h2[K], h3[K], d1[K], d2[K], d3[K], a1[K], b1[K], c1[K];
         int zl[K], best[K], bstep[K], bk[K], bkt[K], hn[K];
         uint32_t nacc[K];
@@ -409,7 +432,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         const int L3 = c ? h3[c - 1] : hl3;
                         const int z = floor_mode(MODE) ? zr : imin(zr, zl[c]);
                         if (!TB) {
-                            const int D = imax(h3[c] - cqD, d3[c]) - ce;
+                            const int D = imax(h3[c] - cqDv[c], d3[c]) - ceDv[c];
                             int H = D;
                             if (!NOI) {
                                 const int A = imax(h1[c] - ddm1, a1[c]);
@@ -422,12 +445,12 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                                 const int fg = imax(imax3(L1, L2, h1[c]), h2[c]) - cf;
                                 H = imax(H, fg);
                             }
-                            const int I = imax(L0 - cq, IL) - ce;
+                            const int I = imax(L0 - cqv[c], IL) - cev[c];
                             H = imax3(H, L3 + csc[c], I);
                             H = imax(H, z);
                             Hn[c] = H; In[c] = I; Dn[c] = D;
                         } else {
-                            const int oD = h3[c] - cqD, xD = d3[c] - ce;
+                            const int oD = h3[c] - cqDv[c], xD = d3[c] - ceDv[c];
                             xacc[1][c] = push_ge(xacc[1][c], xD, oD);
                             const int D = imax(oD, xD);
                             int Hk = D;
@@ -449,7 +472,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                                 Hk = imax3(Hk, L1 - (cf - 11), L2 - (cf - 10));
                                 Hk = imax3(Hk, h1[c] - (cf - 9), h2[c] - (cf - 8));
                             }
-                            const int oI = L0 - cq, xI = IL - ce;
+                            const int oI = L0 - cqv[c], xI = IL - cev[c];
                             xacc[0][c] = push_ge(xacc[0][c], xI, oI);
                             const int I = imax(oI, xI);
                             Hk = imax3(Hk, z, L3 + csc[c]);
@@ -648,7 +671,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
     }  // queue
 }
 
-template <int K, int MODE, bool TB>
+template <int K, int MODE, bool TB, bool PRO>
 hipError_t launch_dp_t(hipStream_t s, int ncu, const DevParams& P, const PairJob* jobs,
                        const int2* items, int nitems, int* qhead, PairState* pst, int* prog,
                        const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
@@ -664,11 +687,11 @@ hipError_t launch_dp_t(hipStream_t s, int ncu, const DevParams& P, const PairJob
         static int per_cu = 0;                                                                  \
         if (per_cu <= 0 &&                                                                      \
             hipOccupancyMaxActiveBlocksPerMultiprocessor(                                       \
-                &per_cu, dp_kernel<K, MODE, TB, NI, NF>, 64, lds) != hipSuccess)                \
+                &per_cu, dp_kernel<K, MODE, TB, NI, NF, PRO>, 64, lds) != hipSuccess)           \
             per_cu = 0;                                                                         \
         const int waves = per_cu > 0 ? per_cu * ncu : 8 * ncu;                                \
         dim3 g(nitems < waves ? nitems : waves);                                                \
-        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, NI, NF>), g, b, lds, s, jobs, items,        \
+        hipLaunchKernelGGL((dp_kernel<K, MODE, TB, NI, NF, PRO>), g, b, lds, s, jobs, items,   \
                            nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink, P);          \
     } while (0)
     if (!noi && !nof) MPG_LAUNCH(false, false);
@@ -679,16 +702,16 @@ hipError_t launch_dp_t(hipStream_t s, int ncu, const DevParams& P, const PairJob
     return hipGetLastError();
 }
 
-template <int K>
+template <int K, bool PRO>
 hipError_t launch_dp_k(hipStream_t s, int ncu, bool tb, const DevParams& P, const PairJob* jobs,
                        const int2* items, int nitems, int* qhead, PairState* pst, int* prog,
                        const uint8_t* prot, const uint8_t* desc, int2* bnd, uint8_t* tbbuf,
                        const DpSink& sink) {
 #define MPG_MODE(M)                                                                             \
-    return tb ? launch_dp_t<K, M, true>(s, ncu, P, jobs, items, nitems, qhead, pst, prog, prot, \
-                                        desc, bnd, tbbuf, sink)                                 \
-              : launch_dp_t<K, M, false>(s, ncu, P, jobs, items, nitems, qhead, pst, prog,     \
-                                         prot, desc, bnd, tbbuf, sink)
+    return tb ? launch_dp_t<K, M, true, PRO>(s, ncu, P, jobs, items, nitems, qhead, pst, prog, \
+                                             prot, desc, bnd, tbbuf, sink)                      \
+              : launch_dp_t<K, M, false, PRO>(s, ncu, P, jobs, items, nitems, qhead, pst, prog, \
+                                              prot, desc, bnd, tbbuf, sink)
     switch (P.mode) {
         case MPG_LOCAL: MPG_MODE(MPG_LOCAL);
         case MPG_EXTEND: MPG_MODE(MPG_EXTEND);

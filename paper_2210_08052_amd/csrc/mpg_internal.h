@@ -75,6 +75,19 @@ struct PackJob {
     int64_t bnd_off;     // int2 index of boundary row -kBndLo
 };
 
+// A position-specific query block (see the public header): the m x 24 int8
+// scores, padded to 8 bytes, then the (m+1) x 4 int16 gap costs.
+__host__ __device__ constexpr int64_t prof_gap_offset(int64_t m) { return (24 * m + 7) & ~(int64_t)7; }
+__host__ __device__ constexpr int64_t prof_block_bytes(int64_t m) {
+    return prof_gap_offset(m) + 8 * (m + 1);
+}
+__host__ __device__ inline const int8_t* prof_scores(const uint8_t* blk) {
+    return (const int8_t*)blk;
+}
+__host__ __device__ inline const int16_t* prof_gaps(const uint8_t* blk, int64_t m) {
+    return (const int16_t*)(blk + prof_gap_offset(m));
+}
+
 // Bytes of per-pair shared state of the DP launch (end-cell key, counters).
 constexpr int kPairStateBytes = 24;
 
@@ -105,7 +118,9 @@ hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row
 // and flags.  The grid holds as many wavefronts as `ncu` compute units run at
 // once for this kernel, capped at the item count.  qhead must be zero, pst
 // and prog zeroed by launch_init.
-hipError_t launch_dp(hipStream_t s, int K, bool tb, int ncu, const DevParams& P,
+// pro: the pairs are position-specific queries (prot points at their
+// profile blocks; K must be 1 or 2).
+hipError_t launch_dp(hipStream_t s, int K, bool tb, bool pro, int ncu, const DevParams& P,
                      const PairJob* jobs, const int2* items, int nitems, int* qhead, void* pst,
                      int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
                      uint8_t* tbbuf, const DpSink& sink);

@@ -308,6 +308,12 @@ hipError_t launch_dp_k2(hipStream_t, int, bool, const DevParams&, const PairJob*
 hipError_t launch_dp_k4(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
                         int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
                         const DpSink&);
+hipError_t launch_dp_p1(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
+                        int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
+                        const DpSink&);
+hipError_t launch_dp_p2(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
+                        int*, void*, int*, const uint8_t*, const uint8_t*, int2*, uint8_t*,
+                        const DpSink&);
 
 int dp_lds_bytes(int K, bool tb) {
     if (K == 1) return tb ? LdsLayout<1, true>::WAVE : LdsLayout<1, false>::WAVE;
@@ -324,11 +330,18 @@ hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row
     return hipGetLastError();
 }
 
-hipError_t launch_dp(hipStream_t s, int K, bool tb, int ncu, const DevParams& P,
+hipError_t launch_dp(hipStream_t s, int K, bool tb, bool pro, int ncu, const DevParams& P,
                      const PairJob* jobs, const int2* items, int nitems, int* qhead, void* pst,
                      int* prog, const uint8_t* prot, const uint8_t* desc, int2* bnd,
                      uint8_t* tbbuf, const DpSink& sink) {
     if (nitems <= 0) return hipSuccess;
+    if (pro) {
+        switch (K) {
+            case 1: return launch_dp_p1(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink);
+            case 2: return launch_dp_p2(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (K) {
         case 1: return launch_dp_k1(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink);
         case 2: return launch_dp_k2(s, ncu, tb, P, jobs, items, nitems, qhead, pst, prog, prot, desc, bnd, tbbuf, sink);

@@ -314,6 +314,7 @@ int64_t tb_bytes_max(int n, int m) {
 // consume.
 struct BoundInfo {
     int64_t maxpos = 0, pmax = 0;
+    int64_t pfix = 0;  // the penalties a profile does not replace: f, r + d + a
     explicit BoundInfo(const mpg_params* p) {
         int mp = 0, mn = 0;
         for (int a = 0; a < 24; ++a)
@@ -327,8 +328,16 @@ struct BoundInfo {
             amax = std::max<int>(amax, p->acceptor[k]);
         }
         maxpos = mp;
-        pmax = std::max<int64_t>({(int64_t)p->q + p->e, (int64_t)p->f,
-                                  (int64_t)p->r + dmax + amax, (int64_t)-mn});
+        pfix = std::max<int64_t>((int64_t)p->f, (int64_t)p->r + dmax + amax);
+        pmax = std::max<int64_t>({(int64_t)p->q + p->e, pfix, (int64_t)-mn});
+    }
+    // the same bound for a position-specific query whose largest score is
+    // smax and whose largest gap cost or negated score is gmax
+    BoundInfo profile(int64_t smax, int64_t gmax) const {
+        BoundInfo b = *this;
+        b.maxpos = std::max<int64_t>(0, smax);
+        b.pmax = std::max(pfix, gmax);
+        return b;
     }
     bool ok(int64_t n, int64_t m, int mode) const {
         const int64_t lim = (int64_t)1 << 24;
@@ -377,6 +386,8 @@ struct RunCfg {
     int force_K = 0, force_K16 = 0;  // calibration runs: one width for all
     const int8_t* modes = nullptr;   // per pair of the call: its boundary mode
                                      // (NULL: params.mode for every pair)
+    bool pro = false;                // position-specific queries (prot_off: profile block)
+    const int32_t* pro_bounds = nullptr;  // per pair: largest score, largest cost
 };
 
 // Build the plan for the pairs idx[0..cnt) of a call with n pairs.  Each
@@ -394,7 +405,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     bysize.reserve(cnt);
     const Overrides ov;
     const BoundInfo bound(p);
-    const bool allow16 = (p->flags & MPG_ALLOW_I16) != 0;
+    const bool allow16 = (p->flags & MPG_ALLOW_I16) != 0 && !cfg.pro;
     const int K16 = choose_K16(ov, cfg.tune, cfg.force_K16);
     const KChoice kc = choose_widths(ov, cfg.tune, cfg.force_K);
     std::vector<std::pair<int64_t, int32_t>> e16;
@@ -410,14 +421,18 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         J.status = MPG_OK;
         J.mode = cfg.modes ? cfg.modes[idx[k]] : p->mode;
         J._pad = 0;
+        const BoundInfo bk = cfg.pro ? bound.profile(cfg.pro_bounds[2 * idx[k]],
+                                                     cfg.pro_bounds[2 * idx[k] + 1])
+                                     : bound;
         if (s.dlen < 0 || s.plen < 0 || s.dlen > MPG_MAX_DNA || s.plen > MPG_MAX_PROT ||
-            !bound.ok(s.dlen, s.plen, J.mode))
+            !bk.ok(s.dlen, s.plen, J.mode))
             J.status = MPG_E_RANGE;
         const bool want_tb = ((s.flags | p->flags) & MPG_WANT_TB) != 0;
         const int nn = std::max(0, J.n), mm = std::max(0, J.m);
         // a pair whose columns fit one strip of 64 takes one column per lane:
         // wider lanes would only add idle columns to every step
-        const int K = (mm + 1 <= 64 && !ov.K && !cfg.force_K) ? 1 : kc.K[want_tb ? 1 : 0];
+        int K = (mm + 1 <= 64 && !ov.K && !cfg.force_K) ? 1 : kc.K[want_tb ? 1 : 0];
+        if (cfg.pro && K > 2) K = 2;  // profile kernels come in widths 1 and 2
         J.K = K;
         const int nsteps = ((nn + 64 + 63) / 64) * 64;
         J.nchunks = nsteps / 64;
@@ -768,7 +783,8 @@ int enqueue(hipStream_t st, Workspace& ws, const Prepared& X, const RunCfg& cfg,
             return launch_dp16(s2, G.K, cfg.ncu, DG, X.d_jobs, X.d_packs, X.d_items + X.goff[g],
                                nit, X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot,
                                (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, sink);
-        return launch_dp(s2, G.K, G.tb, cfg.ncu, DG, X.d_jobs, X.d_items + X.goff[g], nit,
+        return launch_dp(s2, G.K, G.tb, cfg.pro, cfg.ncu, DG, X.d_jobs, X.d_items + X.goff[g],
+                         nit,
                          X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot, (const uint8_t*)ws.desc.p,
                          (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, sink);
     };
@@ -1015,6 +1031,48 @@ int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot
 
 namespace {
 
+// Copy the records (and op strings) of a finished call from ws.out / ws.ops
+// into out[], duplicating each op string for the caller.
+int download_results(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_seg* segs,
+                     int32_t n, int64_t ops_cap, mpg_result* out) {
+    int rc;
+    if (hipMemcpyAsync(ws.hout.p, ws.out.p, sizeof(mpg_dev_result) * (size_t)n,
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+        return MPG_E_DEVICE;
+    bool any_tb = false;
+    for (int32_t k = 0; k < n; ++k) any_tb |= ((segs[k].flags | p->flags) & MPG_WANT_TB) != 0;
+    if (any_tb) {
+        if ((rc = ws.hops.ensure((size_t)ops_cap + 64)) != MPG_OK) return rc;
+        if (hipMemcpyAsync(ws.hops.p, ws.ops.p, (size_t)ops_cap, hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+            return MPG_E_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    const mpg_dev_result* R = (const mpg_dev_result*)ws.hout.p;
+    for (int32_t k = 0; k < n; ++k) {
+        mpg_result& o = out[k];
+        std::memset(&o, 0, sizeof(o));
+        o.status = R[k].status;
+        o.score = R[k].score;
+        o.g_beg = R[k].g_beg;
+        o.g_end = R[k].g_end;
+        o.p_beg = R[k].p_beg;
+        o.p_end = R[k].p_end;
+        o.job_id = (uint64_t)k;
+        o.ops = nullptr;
+        o.ops_len = 0;
+        if (((segs[k].flags | p->flags) & MPG_WANT_TB) && o.status == MPG_OK) {
+            char* sdup = (char*)std::malloc((size_t)R[k].ops_len + 1);
+            if (!sdup) return MPG_E_NOMEM;
+            std::memcpy(sdup, (const char*)ws.hops.p + R[k].ops_off, (size_t)R[k].ops_len);
+            sdup[R[k].ops_len] = 0;
+            o.ops = sdup;
+            o.ops_len = R[k].ops_len;
+        }
+    }
+    return MPG_OK;
+}
+
 // Synchronous host-memory batch on a given stream/workspace; fills out[].
 int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pair* pairs,
                int32_t n, mpg_result* out, const RunCfg& cfg) {
@@ -1054,41 +1112,7 @@ int align_host(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pai
     rc = run_dev_waves(st, ws, p, d_seq, d_seq + pbytes, segs.data(), n,
                        (mpg_dev_result*)ws.out.p, (char*)ws.ops.p, cfg);
     if (rc != MPG_OK) return rc;
-    if (hipMemcpyAsync(ws.hout.p, ws.out.p, sizeof(mpg_dev_result) * (size_t)n,
-                       hipMemcpyDeviceToHost, st) != hipSuccess)
-        return MPG_E_DEVICE;
-    bool any_tb = false;
-    for (int32_t k = 0; k < n; ++k) any_tb |= (segs[k].flags & MPG_WANT_TB) != 0;
-    if (any_tb) {
-        if ((rc = ws.hops.ensure((size_t)ops_cap + 64)) != MPG_OK) return rc;
-        if (hipMemcpyAsync(ws.hops.p, ws.ops.p, (size_t)ops_cap, hipMemcpyDeviceToHost, st) !=
-            hipSuccess)
-            return MPG_E_DEVICE;
-    }
-    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
-    const mpg_dev_result* R = (const mpg_dev_result*)ws.hout.p;
-    for (int32_t k = 0; k < n; ++k) {
-        mpg_result& o = out[k];
-        std::memset(&o, 0, sizeof(o));
-        o.status = R[k].status;
-        o.score = R[k].score;
-        o.g_beg = R[k].g_beg;
-        o.g_end = R[k].g_end;
-        o.p_beg = R[k].p_beg;
-        o.p_end = R[k].p_end;
-        o.job_id = (uint64_t)k;
-        o.ops = nullptr;
-        o.ops_len = 0;
-        if ((segs[k].flags & MPG_WANT_TB) && o.status == MPG_OK) {
-            char* sdup = (char*)std::malloc((size_t)R[k].ops_len + 1);
-            if (!sdup) return MPG_E_NOMEM;
-            std::memcpy(sdup, (const char*)ws.hops.p + R[k].ops_off, (size_t)R[k].ops_len);
-            sdup[R[k].ops_len] = 0;
-            o.ops = sdup;
-            o.ops_len = R[k].ops_len;
-        }
-    }
-    return MPG_OK;
+    return download_results(st, ws, p, segs.data(), n, ops_cap, out);
 }
 
 // ------------------------------------------------------------------ serving
@@ -1469,6 +1493,28 @@ int chains_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t
     return MPG_OK;
 }
 
+// Largest score (at least 0) and largest gap cost or negated score of a
+// position-specific query; false if a cost is outside [0, 8191] or an open +
+// extend pair is 0 (costs enter the traceback layout as 16 * cost - nibble).
+bool profile_bounds(const int8_t* S, const int16_t* gap, int32_t m, int32_t* smax,
+                    int32_t* gmax) {
+    int32_t hi = 0, g = 0;
+    for (int64_t k = 0; k < 24 * (int64_t)m; ++k) {
+        hi = std::max<int32_t>(hi, S[k]);
+        g = std::max<int32_t>(g, -S[k]);
+    }
+    for (int64_t j = 0; j <= m; ++j) {
+        const int16_t* c = gap + 4 * j;
+        for (int t = 0; t < 4; ++t)
+            if (c[t] < 0 || c[t] > 8191) return false;
+        if (c[2] + c[3] < 1 || (j >= 1 && c[0] + c[1] < 1)) return false;
+        g = std::max<int32_t>(g, std::max(c[0] + c[1], c[2] + c[3]));
+    }
+    *smax = hi;
+    *gmax = g;
+    return true;
+}
+
 // Coding sequence of one traced alignment (Methods, "Avoiding pseudogenes"):
 // the genome bases the op string consumes, in path order, without the
 // interior of any intron.  A phase-0 intron (N) contributes nothing; a
@@ -1666,6 +1712,117 @@ int mpg_align_chains(mpg_ctx* ctx, const mpg_params* p, const mpg_chain* chains,
         }
     }
     return MPG_OK;
+}
+
+int64_t mpg_profile_bytes(int32_t m) { return m < 0 ? 0 : prof_block_bytes(m); }
+
+int mpg_align_profiles_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prof,
+                           const uint8_t* d_dna, const mpg_profile_seg* segs, int32_t n,
+                           mpg_dev_result* d_out, char* d_ops, int64_t ops_cap) {
+    if (!ctx || !p || n < 0 || (n > 0 && (!segs || !d_out))) return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    if (n == 0) return MPG_OK;
+    std::vector<mpg_seg> ps(n);
+    std::vector<int32_t> bounds(2 * (size_t)n);
+    int64_t need = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const mpg_profile_seg& g = segs[k];
+        if (g.prof_off < 0 || (g.prof_off & 7) || g.dna_off < 0 || g.smax < 0 || g.pmax < 0)
+            return MPG_E_INVAL;
+        ps[k].prot_off = g.prof_off;
+        ps[k].dna_off = g.dna_off;
+        ps[k].plen = g.m;
+        ps[k].dlen = g.dlen;
+        ps[k].flags = g.flags;
+        ps[k]._pad = 0;
+        bounds[2 * k] = g.smax;
+        bounds[2 * k + 1] = g.pmax;
+        const bool tb = ((g.flags | p->flags) & MPG_WANT_TB) != 0;
+        need += tb ? 2 * ((int64_t)std::max(0, g.dlen) + std::max(0, g.m)) + 1 : 1;
+    }
+    if (need > 0 && (!d_ops || ops_cap < need)) return MPG_E_RANGE;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
+             &ctx->n_cells};
+    ctx->n_calls++;
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.tm = ctx->timing ? &tm : nullptr;
+    cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
+    cfg.pro = true;
+    cfg.pro_bounds = bounds.data();
+    return run_dev_waves(ctx->stream, ctx->ws, p, d_prof, d_dna, ps.data(), n, d_out, d_ops, cfg);
+}
+
+int mpg_align_profiles(mpg_ctx* ctx, const mpg_params* p, const mpg_profile_pair* pairs,
+                       int32_t n, mpg_result* out) {
+    if (!ctx || !p || n < 0 || (n > 0 && (!pairs || !out))) return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    if (n == 0) return MPG_OK;
+    std::vector<mpg_seg> ps(n);
+    std::vector<int32_t> bounds(2 * (size_t)n);
+    int64_t fbytes = 0, dbytes = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const mpg_profile_pair& q = pairs[k];
+        if (q.m < 0 || q.dlen < 0 || !q.gap || (q.m && !q.score) || (q.dlen && !q.dna))
+            return MPG_E_INVAL;
+        if (q.m <= MPG_MAX_PROT &&
+            !profile_bounds(q.score, q.gap, q.m, &bounds[2 * k], &bounds[2 * k + 1]))
+            return MPG_E_INVAL;
+        ps[k].prot_off = fbytes;
+        ps[k].dna_off = dbytes;
+        ps[k].plen = q.m;
+        ps[k].dlen = q.dlen;
+        ps[k].flags = q.flags | (p->flags & MPG_WANT_TB);
+        ps[k]._pad = 0;
+        fbytes += q.m <= MPG_MAX_PROT ? prof_block_bytes(q.m) : 0;
+        dbytes += q.dlen;
+    }
+    const int64_t ops_cap = mpg_ops_capacity(ps.data(), n);
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
+             &ctx->n_cells};
+    ctx->n_calls++;
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.tm = ctx->timing ? &tm : nullptr;
+    cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
+    cfg.pro = true;
+    cfg.pro_bounds = bounds.data();
+    Workspace& ws = ctx->ws;
+    hipStream_t st = ctx->stream;
+    const size_t tot = (size_t)(fbytes + dbytes);
+    if ((rc = ws.seq.ensure(tot + 64)) != MPG_OK) return rc;
+    if ((rc = ws.out.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return rc;
+    if ((rc = ws.ops.ensure((size_t)ops_cap + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hseq.ensure(tot + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hout.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    uint8_t* hs = (uint8_t*)ws.hseq.p;
+    for (int32_t k = 0; k < n; ++k) {
+        const mpg_profile_pair& q = pairs[k];
+        if (q.m <= MPG_MAX_PROT) {
+            uint8_t* blk = hs + ps[k].prot_off;
+            std::memset(blk, 0, (size_t)prof_block_bytes(q.m));
+            if (q.m) std::memcpy(blk, q.score, (size_t)24 * q.m);
+            std::memcpy(blk + prof_gap_offset(q.m), q.gap, (size_t)8 * (q.m + 1));
+        }
+        if (q.dlen) std::memcpy(hs + fbytes + ps[k].dna_off, q.dna, (size_t)q.dlen);
+    }
+    uint8_t* d_seq = (uint8_t*)ws.seq.p;
+    if (tot && hipMemcpyAsync(d_seq, hs, tot, hipMemcpyHostToDevice, st) != hipSuccess)
+        return MPG_E_DEVICE;
+    mpg_dev_result* d_out = (mpg_dev_result*)ws.out.p;
+    rc = run_dev_waves(st, ws, p, d_seq, d_seq + fbytes, ps.data(), n, d_out, (char*)ws.ops.p,
+                       cfg);
+    if (rc != MPG_OK) return rc;
+    return download_results(st, ws, p, ps.data(), n, ops_cap, out);
 }
 
 int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs,

@@ -59,6 +59,17 @@ class mpg_chain_seg(ctypes.Structure):
                 ("k", ctypes.c_int32), ("flags", ctypes.c_uint32), ("_pad", ctypes.c_int32)]
 
 
+class mpg_profile_pair(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_void_p), ("gap", ctypes.c_void_p), ("m", ctypes.c_int32),
+                ("dna", ctypes.c_char_p), ("dlen", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class mpg_profile_seg(ctypes.Structure):
+    _fields_ = [("prof_off", ctypes.c_int64), ("dna_off", ctypes.c_int64),
+                ("m", ctypes.c_int32), ("dlen", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("smax", ctypes.c_int32), ("pmax", ctypes.c_int32), ("_pad", ctypes.c_int32)]
+
+
 class mpg_seg(ctypes.Structure):
     _fields_ = [("prot_off", ctypes.c_int64), ("dna_off", ctypes.c_int64),
                 ("plen", ctypes.c_int32), ("dlen", ctypes.c_int32), ("flags", ctypes.c_uint32),
@@ -103,7 +114,8 @@ EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_de
            "mpg_result_release", "mpg_strerror", "mpg_enable_timing", "mpg_get_timing",
            "mpg_autotune", "mpg_plan_create", "mpg_plan_launch", "mpg_plan_graph",
            "mpg_plan_destroy", "mpg_rescore_spliced", "mpg_align_chains",
-           "mpg_chain_ops_capacity", "mpg_align_chains_dev"]
+           "mpg_chain_ops_capacity", "mpg_align_chains_dev", "mpg_align_profiles",
+           "mpg_profile_bytes", "mpg_align_profiles_dev"]
 
 _lib = None
 
@@ -169,6 +181,14 @@ def lib():
         L.mpg_align_chains_dev.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
                                            ctypes.c_void_p, P(mpg_chain_seg), ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.mpg_align_profiles.argtypes = [ctypes.c_void_p, P(mpg_params), P(mpg_profile_pair),
+                                         ctypes.c_int32, P(mpg_result)]
+        L.mpg_profile_bytes.argtypes = [ctypes.c_int32]
+        L.mpg_profile_bytes.restype = ctypes.c_int64
+        L.mpg_align_profiles_dev.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
+                                             ctypes.c_void_p, P(mpg_profile_seg),
+                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int64]
         L.mpg_strerror.argtypes = [ctypes.c_int]
         L.mpg_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -294,6 +314,38 @@ class Context:
                                          ctypes.c_void_p(d_dna), chains.arr, chains.n,
                                          ctypes.c_void_p(d_out), ctypes.c_void_p(d_ops),
                                          ops_cap), "mpg_align_chains_dev")
+
+    def align_profiles(self, pairs, p: mpg_params, want_tb=None):
+        """pairs: list of (score (m, 24) int8, gap (m + 1, 4) int16, dna[, want_tb]);
+        returns a list of result dicts."""
+        n = len(pairs)
+        arr = (mpg_profile_pair * max(n, 1))()
+        keep = []
+        for k, pr in enumerate(pairs):
+            S = np.ascontiguousarray(pr[0], dtype=np.int8)
+            G = np.ascontiguousarray(pr[1], dtype=np.int16)
+            dna = pr[2].encode() if isinstance(pr[2], str) else bytes(pr[2])
+            tb = pr[3] if len(pr) > 3 else want_tb
+            keep.append((S, G, dna))
+            arr[k].score = S.ctypes.data if S.size else None
+            arr[k].gap = G.ctypes.data
+            arr[k].m = S.shape[0]
+            arr[k].dna, arr[k].dlen = dna, len(dna)
+            arr[k].flags = MPG_WANT_TB if tb else 0
+        out = (mpg_result * max(n, 1))()
+        check(lib().mpg_align_profiles(self.ptr, ctypes.byref(p), arr, n, out),
+              "mpg_align_profiles")
+        res = [_result_dict(out[k]) for k in range(n)]
+        lib().mpg_result_release(self.ptr, out, n)
+        return res
+
+    def align_profiles_dev(self, p: mpg_params, d_prof, d_dna, segs, d_out, d_ops,
+                           ops_cap: int):
+        """Enqueue on the context's stream; segs from pack_profiles."""
+        check(lib().mpg_align_profiles_dev(self.ptr, ctypes.byref(p), ctypes.c_void_p(d_prof),
+                                           ctypes.c_void_p(d_dna), segs.arr, segs.n,
+                                           ctypes.c_void_p(d_out), ctypes.c_void_p(d_ops),
+                                           ops_cap), "mpg_align_profiles_dev")
 
     def rescore_spliced(self, pairs, results, p: mpg_params):
         """Pseudogene guard for traced results of align_batch on the same
@@ -473,6 +525,48 @@ def pack_chains(chains):
         po += len(prot)
         do += len(dna)
     return b"".join(pb), b"".join(db), ChainSegs(arr, n, keep)
+
+
+class ProfileSegs:
+    """The mpg_profile_seg array for align_profiles_dev."""
+
+    def __init__(self, arr, n):
+        self.arr, self.n = arr, n
+
+
+def pack_profiles(pairs):
+    """pairs: list of (score, gap, dna[, want_tb]); returns (profile bytes in the
+    device layout, dna bytes, ProfileSegs, ops capacity with want_tb flags)."""
+    n = len(pairs)
+    arr = (mpg_profile_seg * max(n, 1))()
+    blocks, dbs = [], []
+    fo = do = 0
+    cap = 0
+    for k, pr in enumerate(pairs):
+        S = np.ascontiguousarray(pr[0], dtype=np.int8)
+        G = np.ascontiguousarray(pr[1], dtype=np.int16)
+        m = S.shape[0]
+        dna = bytes(pr[2])
+        tb = len(pr) > 3 and pr[3]
+        nb = int(lib().mpg_profile_bytes(m))
+        blk = bytearray(nb)
+        blk[:24 * m] = S.tobytes()
+        go = nb - 8 * (m + 1)
+        blk[go:] = G.tobytes()
+        used = G[1:, :2].sum(axis=1) if m else np.zeros(0, np.int64)
+        pmax = max([int(-S.min()) if S.size else 0, int(G[:, 2:].sum(axis=1).max())] +
+                   ([int(used.max())] if m else []))
+        arr[k].prof_off, arr[k].dna_off = fo, do
+        arr[k].m, arr[k].dlen = m, len(dna)
+        arr[k].flags = MPG_WANT_TB if tb else 0
+        arr[k].smax = max(0, int(S.max()) if S.size else 0)
+        arr[k].pmax = pmax
+        blocks.append(bytes(blk))
+        dbs.append(dna)
+        fo += nb
+        do += len(dna)
+        cap += 2 * (m + len(dna)) + 1 if tb else 1
+    return b"".join(blocks), b"".join(dbs), ProfileSegs(arr, n), cap
 
 
 def pack_pairs(pairs):

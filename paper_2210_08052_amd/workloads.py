@@ -432,6 +432,54 @@ def chain_jobs(n_chains: int = 10000, seed: int = 6, k: int = 6, keep: float = 0
     return out
 
 
+_B62_20_ARR = None
+
+
+def family_profile(prot: bytes, rng, members: int = 3, loop_rate: float = 0.02,
+                   loop_len: int = 6) -> tuple:
+    """A position-specific query standing in for a gene-family profile: column
+    j averages (rounded half to even) the BLOSUM62 rows of the query residue
+    and of `members` family members' residues, each the query residue with
+    probability 0.7, else drawn from it with the substitution law of step 2;
+    amino acids B, Z and X score -1 and the stop -4.  Gap costs are 11 to
+    open and 1 to extend, except in loops: runs of loop_len columns starting
+    with probability loop_rate per column, where opening costs 5.  Returns
+    (score (m, 24) int8, gap (m + 1, 4) int16)."""
+    global _B62_20_ARR
+    if _B62_20_ARR is None:
+        _B62_20_ARR = _b62_20().astype(np.float64)
+    idx = np.array([STD20.index(chr(c)) for c in prot], dtype=np.int64)
+    m = len(idx)
+    S = np.zeros((m, 24), dtype=np.int8)
+    if m:
+        keep = rng.random((m, members)) < 0.7
+        draws = rng.random((m, members))
+        rows = np.empty((m, members + 1), dtype=np.int64)
+        rows[:, 0] = idx
+        for t in range(members):
+            for j in range(m):
+                rows[j, t + 1] = idx[j] if keep[j, t] else min(
+                    int(np.searchsorted(_CDF[idx[j]], draws[j, t], side="right")), 19)
+        S[:, :20] = np.rint(_B62_20_ARR[rows].mean(axis=1)).astype(np.int8)
+        S[:, 20:23] = -1
+        S[:, 23] = -4
+    gap = np.tile(np.array([11, 1, 11, 1], dtype=np.int16), (m + 1, 1))
+    starts = np.nonzero(rng.random(m + 1) < loop_rate)[0]
+    for st in starts:
+        gap[st:st + loop_len, 0] = 5
+        gap[st:st + loop_len, 2] = 5
+    return S, gap
+
+
+def profile_jobs(n: int = 10000, seed: int = 2, profile_seed: int = 7) -> list:
+    """The planted-gene batch (batch_pairs(n, seed)) with each query protein
+    replaced by its family profile (family_profile, its own generator seeded
+    with profile_seed).  Returns a list of (Pair, score, gap)."""
+    pairs = batch_pairs(n, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(profile_seed))
+    return [(p,) + family_profile(p.prot, rng) for p in pairs]
+
+
 def digest(pairs) -> str:
     """SHA-256 over the concatenated pairs (determinism checks)."""
     h = hashlib.sha256()

@@ -561,3 +561,110 @@ def test_chains_dev_matches_host(ctx):
     with pytest.raises(RuntimeError):
         ctx.align_chains_dev(g, d_prot.data_ptr(), d_dna.data_ptr(), cs, d_out.data_ptr(),
                              d_ops.data_ptr(), cap - 1)
+
+
+def _rand_profile(rng, m, lo=-6, hi=10, gmax=14):
+    S = rng.integers(lo, hi, size=(m, 24)).astype(np.int8)
+    gap = np.stack([rng.integers(0, gmax, m + 1), rng.integers(1, 4, m + 1),
+                    rng.integers(0, gmax, m + 1), rng.integers(1, 4, m + 1)], axis=1)
+    return S, gap.astype(np.int16)
+
+
+def _profile_compare(ctx, cases, g, o, tb, label):
+    got = ctx.align_profiles([c[:3] + (tb,) for c in cases], g)
+    bad = []
+    for k, (c, r) in enumerate(zip(cases, got)):
+        e = oracle.align_profile(c[0], c[1], c[2].decode(), o, want_tb=tb)
+        if key_gpu(r, tb) != key_orc(e, tb):
+            bad.append((k, key_gpu(r, tb), key_orc(e, tb), c[0].shape[0], len(c[2])))
+    assert not bad, "%s: %d/%d mismatches, first: %s" % (label, len(bad), len(cases), bad[:2])
+    return got
+
+
+@pytest.mark.parametrize("tb", [False, True])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_profiles_random(ctx, mode, tb):
+    """Random position-specific queries (per-column scores and gap costs)
+    against the oracle, including strips with ragged tails."""
+    rng = np.random.default_rng(500 + 10 * mode + tb)
+    for flags in (0, 3):
+        print("case profile mode=%d tb=%d flags=%d" % (mode, tb, flags), flush=True)
+        g, o = scorings(mode, flags)
+        cases = []
+        for k in range(30):
+            m = int(rng.integers(0, 300 if k % 3 else 40))
+            S, gap = _rand_profile(rng, m)
+            dna = bytes(rng.choice(np.frombuffer(b"ACGTGTAGN", np.uint8),
+                                   int(rng.integers(0, 900))))
+            cases.append((S, gap, dna))
+        _profile_compare(ctx, cases, g, o, tb, "random m%d f%d" % (mode, flags))
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_profiles_family_batch(ctx, K, monkeypatch):
+    """Family profiles of planted genes at every forced width (4 runs the
+    profile kernels at width 2)."""
+    monkeypatch.setenv("MPG_FORCE_K", str(K))
+    jobs = W.profile_jobs(24, seed=31, profile_seed=32)
+    g, o = scorings(0, 0)
+    for tb in (False, True):
+        print("case profile family K=%d tb=%d" % (K, tb), flush=True)
+        _profile_compare(ctx, [(S, G, p.dna) for p, S, G in jobs], g, o, tb, "family")
+
+
+def test_profile_of_protein_equals_protein_path(ctx):
+    """A profile made of the matrix rows of a protein, uniform gaps: the
+    profile kernels return the protein kernels' results field by field."""
+    pairs = _pairs(77, n=30, max_prot=300, max_dna=1500)
+    for mode in (0, 2):
+        g, o = scorings(mode, 0)
+        mat = np.ctypeslib.as_array(g.mat).astype(np.int64)
+        prof = []
+        for pr, d in pairs:
+            codes = [oracle.aa_code(chr(c)) for c in pr]
+            S = np.array([[mat[a][c] for a in range(24)] for c in codes], np.int8).reshape(-1, 24)
+            G = np.tile(np.array([g.q, g.e, g.q, g.e], np.int16), (len(pr) + 1, 1))
+            prof.append((S, G, d, True))
+        a = ctx.align_batch([(pr, d, True) for pr, d in pairs], g)
+        b = ctx.align_profiles(prof, g)
+        assert [key_gpu(x, True) for x in a] == [key_gpu(x, True) for x in b]
+
+
+def test_profile_errors_and_dev_entry(ctx):
+    import torch
+    g, o = scorings(0, 0)
+    S = np.zeros((3, 24), np.int8)
+    G = np.tile(np.array([11, 1, 11, 1], np.int16), (4, 1))
+    bad = G.copy()
+    bad[2, 0] = -1
+    with pytest.raises(RuntimeError):
+        ctx.align_profiles([(S, bad, b"ACGTACGT")], g)
+    bad = G.copy()
+    bad[1, 0:2] = 0
+    with pytest.raises(RuntimeError):
+        ctx.align_profiles([(S, bad, b"ACGTACGT")], g)
+    big = np.zeros((32001, 24), np.int8)
+    r = ctx.align_profiles([(big, np.tile(G[:1], (32002, 1)), b"ACGT")], g)
+    assert r[0]["status"] == mpg.MPG_E_RANGE
+    # device-resident entry == host entry
+    jobs = W.profile_jobs(20, seed=41, profile_seed=42)
+    cases = [(S, G2, p.dna, k % 2 == 0) for k, (p, S, G2) in enumerate(jobs)]
+    ref = ctx.align_profiles(cases, g)
+    fb, db, segs, cap = mpg.pack_profiles(cases)
+    dev = torch.device("cuda:0")
+    d_prof = torch.frombuffer(bytearray(fb), dtype=torch.uint8).to(dev)
+    d_dna = torch.frombuffer(bytearray(db), dtype=torch.uint8).to(dev)
+    d_ops = torch.zeros(cap, dtype=torch.uint8, device=dev)
+    d_out = torch.zeros(len(cases) * mpg.DEV_RESULT_DTYPE.itemsize, dtype=torch.uint8,
+                        device=dev)
+    ctx.align_profiles_dev(g, d_prof.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
+                           d_ops.data_ptr(), cap)
+    ctx.sync()
+    out = np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=mpg.DEV_RESULT_DTYPE)
+    ops = d_ops.cpu().numpy().tobytes()
+    for k, r in enumerate(ref):
+        assert (out["status"][k], out["score"][k], out["g_end"][k], out["p_end"][k]) == (
+            r["status"], r["score"], r["g_end"], r["p_end"])
+        if k % 2 == 0:
+            o0 = int(out["ops_off"][k])
+            assert ops[o0:o0 + int(out["ops_len"][k])].decode() == r["ops"]

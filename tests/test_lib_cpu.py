@@ -37,7 +37,9 @@ def test_struct_layouts(tmp_path):
                "mpg_result": mpg.mpg_result, "mpg_seg": mpg.mpg_seg,
                "mpg_dev_result": mpg.mpg_dev_result, "mpg_stats": mpg.mpg_stats,
                "mpg_timing": mpg.mpg_timing, "mpg_tuning": mpg.mpg_tuning,
-               "mpg_chain": mpg.mpg_chain, "mpg_chain_seg": mpg.mpg_chain_seg}
+               "mpg_chain": mpg.mpg_chain, "mpg_chain_seg": mpg.mpg_chain_seg,
+               "mpg_profile_pair": mpg.mpg_profile_pair,
+               "mpg_profile_seg": mpg.mpg_profile_seg}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpg.h"', 'int main(void){']
     for nm, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (nm, nm))
