@@ -365,6 +365,99 @@ def bench_profiles(args):
     ctx.close()
 
 
+def bench_chaining(args):
+    """Chaining (first round, binned genome) of 10,000 anchor sets: the true
+    seed hits of planted genes plus spurious hits; one step is one
+    mpg_chain_anchors_dev.  The rate counts candidate pairs (i < j) of the
+    O(n^2) recurrence."""
+    import torch
+    from paper_2210_08052_amd import mpg
+    from paper_2210_08052_amd import workloads as W
+    t0 = time.time()
+    sets = W.chaining_sets(10000, seed=8, binned=True)
+    ns = np.array([len(a) for a in sets], dtype=np.int64)
+    pairs = int((ns * (ns - 1) // 2).sum())
+    off = np.zeros(len(sets) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(ns)
+    log("workload chaining: %d sets, %d anchors, %d candidate pairs, generated in %.1f s" % (
+        len(sets), int(off[-1]), pairs, time.time() - t0))
+    dev = torch.device("cuda:0")
+    allv = np.ascontiguousarray(np.concatenate(sets))
+    d_a = torch.from_numpy(allv).to(dev)
+    tot = int(off[-1])
+    cp = mpg.chaining_params()
+    d_f = torch.empty(tot, dtype=torch.float64, device=dev)
+    d_p = torch.empty(tot, dtype=torch.int32, device=dev)
+    d_i = torch.empty(tot, dtype=torch.int32, device=dev)
+    d_t = torch.empty(len(sets) * cp.max_chains * 16, dtype=torch.uint8, device=dev)
+    d_n = torch.empty(len(sets), dtype=torch.int32, device=dev)
+    ctx = mpg.Context(0)
+    stream = torch.cuda.Stream(device=dev)
+    ctx.set_stream(stream.cuda_stream)
+
+    def step():
+        ctx.chain_anchors_dev(cp, d_a.data_ptr(), off, d_f.data_ptr(), d_p.data_ptr(),
+                              d_i.data_ptr(), d_t.data_ptr(), d_n.data_ptr())
+
+    for w in range(args.warmup):
+        step()
+        ctx.sync()
+        log("warmup %d done" % w)
+    log("warmup: %d sets chained, best chain mean %.1f" % (
+        int((d_n.cpu().numpy() > 0).sum()),
+        float(np.frombuffer(d_t.cpu().numpy().tobytes(), dtype=mpg.CHAIN_OUT_DTYPE)["score"]
+              .reshape(len(sets), cp.max_chains)[:, 0].mean())))
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        ev0.record(stream)
+    for k in range(args.steps):
+        step()
+        log("step %d enqueued" % k)
+    with torch.cuda.stream(stream):
+        ev1.record(stream)
+    ctx.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1) / args.steps
+    ms_step = dt * 1e3 / args.steps
+    rate = pairs / (dt / args.steps) / 1e9
+    log("step %.3f ms (stream %.3f ms), %.2f G candidate pairs/s" % (ms_step, gpu_ms, rate))
+    cpu = None
+    if args.cpu_budget > 0:
+        from oracle import chaining as C
+        order = np.random.default_rng(12345).permutation(len(sets))
+        k, done = 0, 0
+        t1 = time.perf_counter()
+        while k < len(order) and time.perf_counter() - t1 < args.cpu_budget:
+            a = sets[order[k]]
+            C.chain(a)
+            done += len(a) * (len(a) - 1) // 2
+            k += 1
+        dt1 = time.perf_counter() - t1
+        cpu = {"value": round(done / dt1 / 1e9, 5), "unit": "G candidate pairs/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "%d of %d sets (seeded random order), %d pairs, %.1f s wall" % (
+                   k, len(sets), done, dt1)}
+        log("cpu baseline: %s" % json.dumps(cpu))
+    line = {
+        "metric": "chaining candidate pairs per second (fp64, Eq. gap / gap-pen)",
+        "value": round(rate, 3), "unit": "G candidate pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (planted-gene seed hits plus spurious hits)",
+        "config": {"workload": "chaining: 10,000 anchor sets, binned genome, k 6, G 200 kb, "
+                               "beta 0.75, 30 chains", "sets": len(sets), "anchors": tot,
+                   "candidate_pairs": pairs, "stream_ms_per_step": round(gpu_ms, 3)},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 # Arrival rate of the serving workload (jobs/s): 0.7 x the batched capacity
 # (one mpg_align_batch call over the first 20,000 jobs of the same stream,
 # measured by ``--config serving --calibrate``), rounded to two significant
@@ -595,6 +688,9 @@ def main():
         return
     if args.config == "profile":
         bench_profiles(args)
+        return
+    if args.config == "chaining":
+        bench_chaining(args)
         return
 
     if args.config == "serving":

@@ -363,6 +363,67 @@ int mpg_align_profiles_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_p
                            const uint8_t *d_dna, const mpg_profile_seg *segs, int32_t n,
                            mpg_dev_result *d_out, char *d_ops, int64_t ops_cap);
 
+/* ---- chaining ------------------------------------------------------------- */
+
+/*
+ * Chaining of seed anchors (Methods, "Chaining").  Anchor (x, y): genome
+ * position x (a 256-bp bin when binned, else a base) and residue y.  For
+ * anchors sorted by x, then y, with dx = x_j - x_i, dy = y_j - y_i (i may
+ * precede j only if dx >= 0 and dy > 0):
+ *   g(i,j) = 3dy - 256(dx-1) if 3dy < 256(dx-1); 3dy - 256(dx+1) if
+ *            3dy > 256(dx+1); else 0 (Eq. (gap), binned); 3dy - dx otherwise
+ *            (the base-resolution second round);
+ *   gamma(g) = 0 (g = 0), infinite (|g| >= G), g/3 + beta log2(g+1) (g > 0),
+ *            min(|g|/3, beta log2(|g|+1)) (g < 0) (Eq. (gap-pen));
+ *   f(j) = max(k, max_i f(i) + min(dy, k) - gamma(g(i,j))), pred(j) the first
+ *          i reaching it or -1.
+ * All in fp64.  Chains: the unused anchor of largest f (ties: smaller index)
+ * starts a chain that follows pred until -1 or a used anchor; its score is
+ * f(end) minus f(that anchor) (or 0).  Chains are ranked by score (ties: the
+ * earlier extracted) and the first max_chains are reported.
+ */
+typedef struct {
+    int32_t k;          /* anchor length in residues (6) */
+    int32_t G;          /* largest gap (200,000) */
+    double beta;        /* weight of the log term (0.75) */
+    int32_t binned;     /* 1: x in 256-bp bins; 0: x in bases */
+    int32_t max_chains; /* chains reported per set (30) */
+} mpg_chaining_params;
+
+void mpg_chaining_params_default(mpg_chaining_params *cp);
+
+/* One reported chain: its score and its anchors idx[first .. first+len) of
+ * the set's range of idx (anchor indices within the set, ascending). */
+typedef struct {
+    double score;
+    int32_t first;
+    int32_t len;
+} mpg_chain_out;
+
+#define MPG_MAX_ANCHORS 6144 /* anchors of one set */
+
+/*
+ * Chain nsets anchor sets on the GPU.  anchors: 2 int32 per anchor (x, y), all
+ * sets concatenated; set s is anchors[set_off[s] .. set_off[s+1]) (set_off has
+ * nsets + 1 ascending entries, set_off[0] = 0), sorted by x then y.  Outputs
+ * are indexed like the anchors: f and pred (pred relative to the set), idx
+ * (the extracted chains' anchors); top holds max_chains records per set and
+ * ntop[s] the number reported, or MPG_E_RANGE for a set of more than
+ * MPG_MAX_ANCHORS anchors.  The call fails with MPG_E_INVAL for a set that is
+ * not sorted or bad parameters (k < 1, G < 1, beta < 0, max_chains < 1).
+ * Host memory, synchronous.
+ */
+int mpg_chain_anchors(mpg_ctx *ctx, const mpg_chaining_params *cp, const int32_t *anchors,
+                      const int64_t *set_off, int32_t nsets, double *f, int32_t *pred,
+                      int32_t *idx, mpg_chain_out *top, int32_t *ntop);
+
+/* As mpg_chain_anchors with anchors and every output in device memory
+ * (set_off stays in host memory); enqueued on the context's stream.  Sets
+ * are not checked for order: an unsorted set gives unspecified chains. */
+int mpg_chain_anchors_dev(mpg_ctx *ctx, const mpg_chaining_params *cp, const int32_t *d_anchors,
+                          const int64_t *set_off, int32_t nsets, double *d_f, int32_t *d_pred,
+                          int32_t *d_idx, mpg_chain_out *d_top, int32_t *d_ntop);
+
 /* ---- serving ------------------------------------------------------------ */
 
 /*

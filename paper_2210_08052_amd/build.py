@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpg.so")
 SOURCES = ["mpg_dp_k1.hip", "mpg_dp_k2.hip", "mpg_dp_k4.hip", "mpg_dp_p1.hip", "mpg_dp_p2.hip",
-           "mpg_dp16.hip", "mpg_kernels.hip", "mpg_lib.cpp"]
+           "mpg_dp16.hip", "mpg_chain.hip", "mpg_kernels.hip", "mpg_lib.cpp"]
 ARCH = os.environ.get("MPG_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.

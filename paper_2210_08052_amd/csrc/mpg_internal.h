@@ -163,6 +163,26 @@ hipError_t launch_stitch(hipStream_t s, const ChainJob* chains, int nchains, con
 // Dynamic LDS bytes of one DP wavefront.
 int dp_lds_bytes(int K, bool tb);
 
+// Chaining (mpg_chain.hip): one wavefront per anchor set.
+struct ChainSetJob {
+    int64_t off;     // first anchor of the set (in anchors, f, pred, idx and the records)
+    int32_t n;       // anchors
+    int32_t status;  // MPG_OK, or the set's error (the kernel writes it to ntop)
+};
+struct ChainCfg {
+    int32_t k, G, binned, max_chains;
+    int32_t max_n;   // largest set of the launch (sizes the LDS)
+    int32_t _pad;
+    double beta;
+};
+struct ChainRec {    // one extracted chain (scratch)
+    double score;
+    int32_t first, len;
+};
+hipError_t launch_chain(hipStream_t st, const ChainSetJob* sets, int nsets, const int2* anchors,
+                        const ChainCfg& cfg, double* f, int* pred, ChainRec* recs, int* idx,
+                        mpg_chain_out* top, int* ntop);
+
 // Lane-packed int16 path (mpg_dp16.hip): packed row descriptors of every
 // PackJob (rows [-kDescLo, 64*nchunks + kDescHi), pack k's first row at
 // global row row_start[k]; also zeroes the packs' progress counters), and the

@@ -177,14 +177,14 @@ struct HostBuf {  // pinned host memory
 constexpr int kSideStreams = 8;
 struct Workspace {
     DevBuf jobs, row_start, order, desc, bnd, tb, seq, out, ops, state, chain, piece_out,
-        piece_ops;
-    HostBuf hplan, hseq, hout, hops, hchain;
+        piece_ops, cset, cio;
+    HostBuf hplan, hseq, hout, hops, hchain, hcset;
     HostBuf prec, pops;  // serving: host-mapped records and op strings the host polls
     void defer_frees(Retired* r) {
         DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state,
-                       &chain, &piece_out, &piece_ops};
+                       &chain, &piece_out, &piece_ops, &cset, &cio};
         for (auto* b : d) b->later = r;
-        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops, &hchain};
+        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops, &hchain, &hcset};
         for (auto* b : h) b->later = r;
     }
     hipStream_t side[kSideStreams] = {};
@@ -205,9 +205,9 @@ struct Workspace {
     }
     void release() {
         DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state,
-                       &chain, &piece_out, &piece_ops};
+                       &chain, &piece_out, &piece_ops, &cset, &cio};
         for (auto* b : d) b->release();
-        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops, &hchain};
+        HostBuf* h[] = {&hplan, &hseq, &hout, &hops, &prec, &pops, &hchain, &hcset};
         for (auto* b : h) b->release();
         if (streams_ready) {
             for (int k = 0; k < kSideStreams; ++k) {
@@ -1515,6 +1515,52 @@ bool profile_bounds(const int8_t* S, const int16_t* gap, int32_t m, int32_t* sma
     return true;
 }
 
+int chaining_params_check(const mpg_chaining_params* cp) {
+    if (!cp || cp->k < 1 || cp->G < 1 || !(cp->beta >= 0.0) || cp->max_chains < 1 ||
+        (cp->binned != 0 && cp->binned != 1))
+        return MPG_E_INVAL;
+    return MPG_OK;
+}
+
+// Enqueue the chaining of nsets sets whose anchors are on the device.
+int chain_sets_dev(hipStream_t st, Workspace& ws, const mpg_chaining_params* cp,
+                   const int32_t* d_anchors, const int64_t* set_off, int32_t nsets, double* d_f,
+                   int32_t* d_pred, int32_t* d_idx, mpg_chain_out* d_top, int32_t* d_ntop) {
+    std::vector<ChainSetJob> jobs(nsets);
+    int32_t max_n = 1;
+    for (int32_t t = 0; t < nsets; ++t) {
+        const int64_t n = set_off[t + 1] - set_off[t];
+        if (set_off[t] < 0 || n < 0) return MPG_E_INVAL;
+        jobs[t].off = set_off[t];
+        jobs[t].n = (int32_t)std::min<int64_t>(n, MPG_MAX_ANCHORS);
+        jobs[t].status = n > MPG_MAX_ANCHORS ? MPG_E_RANGE : MPG_OK;
+        if (jobs[t].status == MPG_OK) max_n = std::max<int32_t>(max_n, (int32_t)n);
+    }
+    const int64_t total = set_off[nsets];
+    const size_t jb = sizeof(ChainSetJob) * (size_t)nsets;
+    const size_t rb = sizeof(ChainRec) * (size_t)std::max<int64_t>(total, 1);
+    int rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    if ((rc = ws.cset.ensure(((jb + 15) & ~(size_t)15) + rb + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hcset.ensure(jb + 64)) != MPG_OK) return rc;
+    std::memcpy(ws.hcset.p, jobs.data(), jb);
+    if (hipMemcpyAsync(ws.cset.p, ws.hcset.p, jb, hipMemcpyHostToDevice, st) != hipSuccess)
+        return MPG_E_DEVICE;
+    ChainCfg cfg;
+    cfg.k = cp->k;
+    cfg.G = cp->G;
+    cfg.binned = cp->binned;
+    cfg.max_chains = cp->max_chains;
+    cfg.max_n = max_n;
+    cfg._pad = 0;
+    cfg.beta = cp->beta;
+    ChainRec* recs = (ChainRec*)((uint8_t*)ws.cset.p + ((jb + 15) & ~(size_t)15));
+    if (launch_chain(st, (const ChainSetJob*)ws.cset.p, nsets, (const int2*)d_anchors, cfg, d_f,
+                     d_pred, recs, d_idx, d_top, d_ntop) != hipSuccess)
+        return MPG_E_DEVICE;
+    return MPG_OK;
+}
+
 // Coding sequence of one traced alignment (Methods, "Avoiding pseudogenes"):
 // the genome bases the op string consumes, in path order, without the
 // interior of any intron.  A phase-0 intron (N) contributes nothing; a
@@ -1823,6 +1869,76 @@ int mpg_align_profiles(mpg_ctx* ctx, const mpg_params* p, const mpg_profile_pair
                        cfg);
     if (rc != MPG_OK) return rc;
     return download_results(st, ws, p, ps.data(), n, ops_cap, out);
+}
+
+void mpg_chaining_params_default(mpg_chaining_params* cp) {
+    if (!cp) return;
+    cp->k = 6;
+    cp->G = 200000;
+    cp->beta = 0.75;
+    cp->binned = 1;
+    cp->max_chains = 30;
+}
+
+int mpg_chain_anchors_dev(mpg_ctx* ctx, const mpg_chaining_params* cp, const int32_t* d_anchors,
+                          const int64_t* set_off, int32_t nsets, double* d_f, int32_t* d_pred,
+                          int32_t* d_idx, mpg_chain_out* d_top, int32_t* d_ntop) {
+    if (!ctx || nsets < 0 || (nsets > 0 && (!set_off || !d_top || !d_ntop))) return MPG_E_INVAL;
+    int rc = chaining_params_check(cp);
+    if (rc != MPG_OK) return rc;
+    if (nsets == 0) return MPG_OK;
+    if (set_off[0] != 0) return MPG_E_INVAL;
+    if (set_off[nsets] > 0 && (!d_anchors || !d_f || !d_pred || !d_idx)) return MPG_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    return chain_sets_dev(ctx->stream, ctx->ws, cp, d_anchors, set_off, nsets, d_f, d_pred, d_idx,
+                          d_top, d_ntop);
+}
+
+int mpg_chain_anchors(mpg_ctx* ctx, const mpg_chaining_params* cp, const int32_t* anchors,
+                      const int64_t* set_off, int32_t nsets, double* f, int32_t* pred,
+                      int32_t* idx, mpg_chain_out* top, int32_t* ntop) {
+    if (!ctx || nsets < 0 || (nsets > 0 && (!set_off || !top || !ntop))) return MPG_E_INVAL;
+    int rc = chaining_params_check(cp);
+    if (rc != MPG_OK) return rc;
+    if (nsets == 0) return MPG_OK;
+    if (set_off[0] != 0) return MPG_E_INVAL;
+    const int64_t total = set_off[nsets];
+    if (total > 0 && (!anchors || !f || !pred || !idx)) return MPG_E_INVAL;
+    for (int32_t t = 0; t < nsets; ++t) {
+        if (set_off[t + 1] < set_off[t]) return MPG_E_INVAL;
+        for (int64_t a = set_off[t] + 1; a < set_off[t + 1]; ++a) {
+            const int32_t* u = anchors + 2 * (a - 1);
+            const int32_t* v = anchors + 2 * a;
+            if (v[0] < u[0] || (v[0] == u[0] && v[1] < u[1])) return MPG_E_INVAL;
+        }
+    }
+    const size_t ab = 8 * (size_t)total, fb = 8 * (size_t)total, ib = 4 * (size_t)total;
+    const size_t tb = sizeof(mpg_chain_out) * (size_t)nsets * cp->max_chains, nb = 4 * (size_t)nsets;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_a = 0, o_f = al(ab), o_p = o_f + al(fb), o_i = o_p + al(ib), o_t = o_i + al(ib),
+                 o_n = o_t + al(tb), tot = o_n + al(nb);
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Workspace& ws = ctx->ws;
+    hipStream_t st = ctx->stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    if ((rc = ws.cio.ensure(tot + 64)) != MPG_OK) return rc;
+    uint8_t* d = (uint8_t*)ws.cio.p;
+    if (ab && hipMemcpyAsync(d + o_a, anchors, ab, hipMemcpyHostToDevice, st) != hipSuccess)
+        return MPG_E_DEVICE;
+    rc = chain_sets_dev(st, ws, cp, (const int32_t*)(d + o_a), set_off, nsets,
+                        (double*)(d + o_f), (int32_t*)(d + o_p), (int32_t*)(d + o_i),
+                        (mpg_chain_out*)(d + o_t), (int32_t*)(d + o_n));
+    if (rc != MPG_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (fb) e = hipMemcpyAsync(f, d + o_f, fb, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && ib) e = hipMemcpyAsync(pred, d + o_p, ib, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && ib) e = hipMemcpyAsync(idx, d + o_i, ib, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(top, d + o_t, tb, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ntop, d + o_n, nb, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    return MPG_OK;
 }
 
 int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs,

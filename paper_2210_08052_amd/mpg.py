@@ -70,6 +70,18 @@ class mpg_profile_seg(ctypes.Structure):
                 ("smax", ctypes.c_int32), ("pmax", ctypes.c_int32), ("_pad", ctypes.c_int32)]
 
 
+class mpg_chaining_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("G", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("binned", ctypes.c_int32), ("max_chains", ctypes.c_int32)]
+
+
+class mpg_chain_out(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_double), ("first", ctypes.c_int32), ("len", ctypes.c_int32)]
+
+
+CHAIN_OUT_DTYPE = np.dtype([("score", "<f8"), ("first", "<i4"), ("len", "<i4")])
+
+
 class mpg_seg(ctypes.Structure):
     _fields_ = [("prot_off", ctypes.c_int64), ("dna_off", ctypes.c_int64),
                 ("plen", ctypes.c_int32), ("dlen", ctypes.c_int32), ("flags", ctypes.c_uint32),
@@ -115,7 +127,8 @@ EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_de
            "mpg_autotune", "mpg_plan_create", "mpg_plan_launch", "mpg_plan_graph",
            "mpg_plan_destroy", "mpg_rescore_spliced", "mpg_align_chains",
            "mpg_chain_ops_capacity", "mpg_align_chains_dev", "mpg_align_profiles",
-           "mpg_profile_bytes", "mpg_align_profiles_dev"]
+           "mpg_profile_bytes", "mpg_align_profiles_dev", "mpg_chaining_params_default",
+           "mpg_chain_anchors", "mpg_chain_anchors_dev"]
 
 _lib = None
 
@@ -189,6 +202,13 @@ def lib():
                                              ctypes.c_void_p, P(mpg_profile_seg),
                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int64]
+        L.mpg_chaining_params_default.argtypes = [P(mpg_chaining_params)]
+        L.mpg_chaining_params_default.restype = None
+        L.mpg_chain_anchors.argtypes = [ctypes.c_void_p, P(mpg_chaining_params), ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+        L.mpg_chain_anchors_dev.argtypes = L.mpg_chain_anchors.argtypes
         L.mpg_strerror.argtypes = [ctypes.c_int]
         L.mpg_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -346,6 +366,47 @@ class Context:
                                            ctypes.c_void_p(d_dna), segs.arr, segs.n,
                                            ctypes.c_void_p(d_out), ctypes.c_void_p(d_ops),
                                            ops_cap), "mpg_align_profiles_dev")
+
+    def chain_anchors(self, sets, cp=None):
+        """sets: list of anchor lists [(x, y), ...] sorted by (x, y).  Returns per
+        set a dict: f, pred (numpy arrays), chains [(score, [indices])] best
+        first, and status (0, or a negative code for the set)."""
+        cp = cp or chaining_params()
+        arrs = [np.asarray(a, dtype=np.int32).reshape(-1, 2) for a in sets]
+        off = np.zeros(len(sets) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([len(a) for a in arrs])
+        allv = np.ascontiguousarray(np.concatenate(arrs) if arrs else np.zeros((0, 2), np.int32))
+        tot = int(off[-1])
+        f = np.zeros(max(tot, 1), np.float64)
+        pred = np.zeros(max(tot, 1), np.int32)
+        idx = np.zeros(max(tot, 1), np.int32)
+        top = np.zeros(max(len(sets) * cp.max_chains, 1), dtype=CHAIN_OUT_DTYPE)
+        ntop = np.zeros(max(len(sets), 1), np.int32)
+        check(lib().mpg_chain_anchors(self.ptr, ctypes.byref(cp), allv.ctypes.data,
+                                      off.ctypes.data, len(sets), f.ctypes.data,
+                                      pred.ctypes.data, idx.ctypes.data, top.ctypes.data,
+                                      ntop.ctypes.data), "mpg_chain_anchors")
+        out = []
+        for s_, a in enumerate(arrs):
+            lo, hi = int(off[s_]), int(off[s_ + 1])
+            nt = int(ntop[s_])
+            chains = []
+            for r in range(max(nt, 0)):
+                t = top[s_ * cp.max_chains + r]
+                first, ln = int(t["first"]), int(t["len"])
+                chains.append((float(t["score"]), [int(v) for v in idx[lo + first:lo + first + ln]]))
+            out.append({"f": f[lo:hi].copy(), "pred": pred[lo:hi].astype(np.int64),
+                        "chains": chains, "status": min(nt, 0)})
+        return out
+
+    def chain_anchors_dev(self, cp, d_anchors, set_off: np.ndarray, d_f, d_pred, d_idx, d_top,
+                          d_ntop):
+        """Enqueue on the context's stream (set_off: int64 host array)."""
+        check(lib().mpg_chain_anchors_dev(self.ptr, ctypes.byref(cp), ctypes.c_void_p(d_anchors),
+                                          set_off.ctypes.data, len(set_off) - 1,
+                                          ctypes.c_void_p(d_f), ctypes.c_void_p(d_pred),
+                                          ctypes.c_void_p(d_idx), ctypes.c_void_p(d_top),
+                                          ctypes.c_void_p(d_ntop)), "mpg_chain_anchors_dev")
 
     def rescore_spliced(self, pairs, results, p: mpg_params):
         """Pseudogene guard for traced results of align_batch on the same
@@ -567,6 +628,16 @@ def pack_profiles(pairs):
         do += len(dna)
         cap += 2 * (m + len(dna)) + 1 if tb else 1
     return b"".join(blocks), b"".join(dbs), ProfileSegs(arr, n), cap
+
+
+def chaining_params(**kw) -> mpg_chaining_params:
+    """The library's chaining defaults (k 6, G 200,000, beta 0.75, binned,
+    30 chains), with keyword overrides."""
+    cp = mpg_chaining_params()
+    lib().mpg_chaining_params_default(ctypes.byref(cp))
+    for k2, v in kw.items():
+        setattr(cp, k2, v)
+    return cp
 
 
 def pack_pairs(pairs):

@@ -480,6 +480,35 @@ def profile_jobs(n: int = 10000, seed: int = 2, profile_seed: int = 7) -> list:
     return [(p,) + family_profile(p.prot, rng) for p in pairs]
 
 
+def chaining_sets(n_sets: int = 10000, seed: int = 8, k: int = 6, keep: float = 0.5,
+                  noise: float = 1.0, spread: int = 2_000_000, binned: bool = True) -> list:
+    """Anchor sets for chaining, one per planted gene of the batch recipe
+    (seed `seed`): the true seed hits (true_anchors) kept with probability
+    `keep`, placed at a random locus of a 100-Mb genome, plus Poisson(noise x
+    hits + 5) spurious hits uniform within `spread` bases of the locus and
+    uniform in the protein.  x is the genome base, or its 256-bp bin when
+    binned.  Each set is sorted by (x, y).  Returns a list of int32 arrays of
+    shape (n, 2)."""
+    pairs = batch_pairs(n_sets, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 2000))
+    out = []
+    for p in pairs:
+        hits = true_anchors(p, k)
+        L = len(p.prot)
+        sel = [h for h, u in zip(hits, rng.random(len(hits))) if u < keep]
+        base = int(rng.integers(spread, 100_000_000 - spread))
+        nn = int(rng.poisson(noise * len(sel) + 5))
+        xs = [base + x for x, _ in sel] + [int(v) for v in
+                                           rng.integers(base - spread, base + spread, nn)]
+        ys = [y for _, y in sel] + [int(v) for v in rng.integers(0, max(1, L - k + 1), nn)]
+        a = np.array(list(zip(xs, ys)), dtype=np.int64).reshape(-1, 2)
+        if binned:
+            a[:, 0] //= 256
+        a = a[np.lexsort((a[:, 1], a[:, 0]))]
+        out.append(a.astype(np.int32))
+    return out
+
+
 def digest(pairs) -> str:
     """SHA-256 over the concatenated pairs (determinism checks)."""
     h = hashlib.sha256()

@@ -668,3 +668,56 @@ def test_profile_errors_and_dev_entry(ctx):
         if k % 2 == 0:
             o0 = int(out["ops_off"][k])
             assert ops[o0:o0 + int(out["ops_len"][k])].decode() == r["ops"]
+
+
+def _check_chaining(got, anchors, k, beta, G, binned, max_chains):
+    """f within fp64 rounding of the oracle's (log2 may differ in the last
+    bit); pred the oracle's, or an equally good predecessor; the chains
+    exactly the oracle's extraction applied to the GPU's own f and pred."""
+    from oracle import chaining as C
+    a = np.asarray(anchors, dtype=np.int64).reshape(-1, 2)
+    f_o, p_o = C.chain_dp(a[:, 0], a[:, 1], k, beta, G, binned)
+    f_g, p_g = got["f"], got["pred"]
+    tol = 1e-9 * np.maximum(1.0, np.abs(f_o))
+    assert np.all(np.abs(f_g - f_o) <= tol)
+    for j in np.nonzero(p_g != p_o)[0]:
+        i = int(p_g[j])
+        if i < 0:
+            assert abs(f_o[j] - k) <= tol[j]
+            continue
+        dx, dy = a[j, 0] - a[i, 0], a[j, 1] - a[i, 1]
+        v = f_o[i] + min(dy, k) - float(C.gamma(C.gap(dx, dy, binned), beta, G))
+        assert dx >= 0 and dy > 0 and abs(v - f_o[j]) <= tol[j], (j, i)
+    assert got["chains"] == C.extract(f_g, p_g, max_chains)
+
+
+@pytest.mark.parametrize("binned", [True, False])
+def test_chaining_sets(ctx, binned):
+    """Anchor sets of planted genes with spurious hits, both rounds, default
+    and stressed parameters (small G makes links impossible)."""
+    sets = W.chaining_sets(60, seed=12 + binned, binned=binned)
+    sets += [np.zeros((0, 2), np.int32), np.array([[5, 7]], np.int32),
+             np.array([[3, 1], [3, 1], [3, 2], [3, 9], [4, 4]], np.int32)]
+    for kw in (dict(), dict(k=4, beta=1.0, G=300, max_chains=5)):
+        print("case chaining binned=%d %s" % (binned, kw), flush=True)
+        cp = mpg.chaining_params(binned=int(binned), **kw)
+        got = ctx.chain_anchors(sets, cp)
+        for a, r in zip(sets, got):
+            assert r["status"] == 0
+            _check_chaining(r, a, cp.k, cp.beta, cp.G, binned, cp.max_chains)
+
+
+def test_chaining_limits(ctx):
+    rng = np.random.default_rng(3)
+    big = rng.integers(0, 50000, size=(6144, 2))
+    big = big[np.lexsort((big[:, 1], big[:, 0]))]
+    over = np.zeros((6145, 2), np.int32)
+    over[:, 0] = np.arange(6145)
+    cp = mpg.chaining_params(binned=0)
+    got = ctx.chain_anchors([big.astype(np.int32), over], cp)
+    _check_chaining(got[0], big, cp.k, cp.beta, cp.G, False, cp.max_chains)
+    assert got[1]["status"] == mpg.MPG_E_RANGE
+    with pytest.raises(RuntimeError):
+        ctx.chain_anchors([np.array([[5, 1], [4, 2]], np.int32)], cp)
+    with pytest.raises(RuntimeError):
+        ctx.chain_anchors([np.array([[5, 1]], np.int32)], mpg.chaining_params(k=0))

@@ -39,7 +39,9 @@ def test_struct_layouts(tmp_path):
                "mpg_timing": mpg.mpg_timing, "mpg_tuning": mpg.mpg_tuning,
                "mpg_chain": mpg.mpg_chain, "mpg_chain_seg": mpg.mpg_chain_seg,
                "mpg_profile_pair": mpg.mpg_profile_pair,
-               "mpg_profile_seg": mpg.mpg_profile_seg}
+               "mpg_profile_seg": mpg.mpg_profile_seg,
+               "mpg_chaining_params": mpg.mpg_chaining_params,
+               "mpg_chain_out": mpg.mpg_chain_out}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpg.h"', 'int main(void){']
     for nm, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (nm, nm))
@@ -123,3 +125,10 @@ def test_null_arguments_are_rejected():
     assert L.mpg_ctx_create(None, 0, 0, 0) == mpg.MPG_E_INVAL
     assert L.mpg_poll(None, None, 0, 0) == mpg.MPG_E_INVAL
     assert L.mpg_cancel(None, 1) == mpg.MPG_E_INVAL
+
+
+def test_chaining_defaults_are_the_papers():
+    """Methods, "Chaining": k-mers of 6 residues, G = 200 kb, beta = 0.75,
+    binned first round, top 30 chains."""
+    cp = mpg.chaining_params()
+    assert (cp.k, cp.G, cp.beta, cp.binned, cp.max_chains) == (6, 200000, 0.75, 1, 30)
