@@ -7,12 +7,13 @@
 #include "mpg_internal.h"
 #include "mpg_walk.h"
 
-// Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  The
-// score-only kernels with K <= 2 fit three waves per SIMD (168 VGPRs) with
-// spills only outside the step loop; K = 4 and the traceback kernels would
-// spill inside it, so they keep their registers.
+// Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  With
+// K <= 2 the kernels fit three waves per SIMD (168 VGPRs): the score-only ones
+// without spills, the traceback ones with a few spilled registers outside the
+// step loop, which three waves repay (4.9% on the traceback batch).  K = 4
+// keeps its registers.
 #ifndef MPG_TB_WAVES
-#define MPG_TB_WAVES 1
+#define MPG_TB_WAVES 3
 #endif
 template <int K, bool TB>
 struct WavesPerEu {
@@ -104,7 +105,7 @@ struct LdsLayout {
     static constexpr int RING = 128 * DS;      // two chunks of descriptors
     static constexpr int PROF = 25 * SW * PS;  // profile: 24 aa + poison row
     static constexpr int IN = 64 * 8;          // incoming boundary of the chunk
-    static constexpr int OUT = 64 * 8;         // outgoing boundary of the chunk
+    static constexpr int OUT = 128 * 8;        // outgoing boundary, then a dummy slot per lane
     static constexpr int WAVE = RING + PROF + IN + OUT;
 };
 
@@ -528,7 +529,10 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                     if (!TB) { ddm1 = dd0; dd0 = ds0.z; aam2 = aam1; aam1 = ds0.w; }
                     Hout = Hn[K - 1];
                     Iout = In[K - 1];
-                    if (lane == 63) outb[t] = make_int2(Hout, Iout);
+                    // lane 63 records the row; the other lanes write to slots
+                    // of their own, so the store needs no branch (a branch
+                    // splits the step's scheduling region and costs spills)
+                    outb[lane == 63 ? t : 64 + lane] = make_int2(Hout, Iout);
                     // rotate the pipeline
                     cd0 = nd0; cd1 = nd1; nd0 = fd0; nd1 = fd1;
 #pragma unroll

@@ -46,7 +46,7 @@ struct Lds16 {
     static constexpr int HALF = 25 * SW * 2;   // one pair's int16 profile
     static constexpr int PROF = 2 * HALF;      // A then B
     static constexpr int IN = 64 * 8;
-    static constexpr int OUT = 64 * 8;
+    static constexpr int OUT = 128 * 8;  // rows 0..63, then one dummy slot per lane
     static constexpr int WAVE = RING + PROF + IN + OUT;
 };
 
@@ -119,7 +119,8 @@ dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
     uint8_t* prof = smem + LY::RING;
     int2* inb = (int2*)(smem + LY::RING + LY::PROF);
     int2* outb = (int2*)(smem + LY::RING + LY::PROF + LY::IN);
-    const s2 cq = splat(P.q), ce = splat(P.e), cf = splat(P.f);
+    const s2 ce = splat(P.e), cf = splat(P.f);
+    const s2 cqe = splat(P.q + P.e);  // open and first extension
     const s2 neg2 = as_s2(kNeg2);
 
     for (;;) {
@@ -265,20 +266,26 @@ dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
                         const s2 L1 = c ? h1[c - 1] : hl1;
                         const s2 L2 = c ? h2[c - 1] : hl2;
                         const s2 L3 = c ? h3[c - 1] : hl3;
-                        const s2 D = psub(pmax(psub(h3[c], cq), d3[c]), ce);
-                        s2 H = pmax(D, z);
+                        // every candidate but I is known before the left
+                        // neighbour's H of this row: fold them in two
+                        // independent trees, so that dependent packed
+                        // instructions rarely follow each other
+                        // max(x - q, y) - e as max(x - (q+e), y - e): no
+                        // value reachable here saturates, so both are exact
+                        const s2 D = pmax(psub(h3[c], cqe), psub(d3[c], ce));
+                        s2 t0 = pmax(D, z);
+                        s2 t1 = padd(L3, csc[c]);
                         if (!NOI) {
                             const s2 A = pmax(psub(h1[c], ddm1), a1[c]);
                             const s2 B = pmax(psub(L1, dd0), b1[c]);
                             const s2 C = pmax(psub(L1, rdn), c1[c]);
-                            H = pmax(H, psub(A, acc));
-                            H = pmax(H, pmax(psub(B, aam2), psub(C, aam1)));
+                            t0 = pmax(t0, psub(A, acc));
+                            t1 = pmax(t1, pmax(psub(B, aam2), psub(C, aam1)));
                             An[c] = A; Bn[c] = B; Cn[c] = C;
                         }
-                        if (!NOF) H = pmax(H, psub(pmax(pmax(L1, L2), pmax(h1[c], h2[c])), cf));
-                        const s2 I = psub(pmax(psub(L0, cq), IL), ce);
-                        H = pmax(H, padd(L3, csc[c]));
-                        H = pmax(H, I);
+                        if (!NOF) t0 = pmax(t0, psub(pmax(pmax(L1, L2), pmax(h1[c], h2[c])), cf));
+                        const s2 I = pmax(psub(L0, cqe), psub(IL, ce));
+                        const s2 H = pmax(pmax(t0, t1), I);
                         Hn[c] = H; In[c] = I; Dn[c] = D;
                         // end-cell keys: value in the high half, 63 - step below
                         const int hv = as_i(H);
@@ -295,7 +302,10 @@ dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
                     ddm1 = dd0; dd0 = rdn; aam2 = aam1; aam1 = acc;
                     Hout = as_i(Hn[K - 1]);
                     Iout = as_i(In[K - 1]);
-                    if (lane == 63) outb[t] = make_int2(Hout, Iout);
+                    // lane 63 records the row; the other lanes write to slots of
+                    // their own, so the store needs no branch (a branch would
+                    // split the step's scheduling region)
+                    outb[lane == 63 ? t : 64 + lane] = make_int2(Hout, Iout);
                     cd0 = nd0; nd0 = fd0;
 #pragma unroll
                     for (int c = 0; c < K; ++c) csc[c] = nsc[c];

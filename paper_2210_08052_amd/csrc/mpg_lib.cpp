@@ -390,6 +390,32 @@ struct RunCfg {
     const int32_t* pro_bounds = nullptr;  // per pair: largest score, largest cost
 };
 
+// Stable sort of (key, index) entries by key, ascending or descending; the
+// entries arrive in index order, so equal keys stay in index order (the
+// order a comparison sort with an index tie-break gives).  LSD radix over
+// 16-bit digits: planning sorts up to ~10^5 entries per call.
+void sort_by_key(std::vector<std::pair<int64_t, int32_t>>& v, bool descending) {
+    if (v.size() < 2) return;
+    int64_t lo = v[0].first, hi = v[0].first;
+    for (const auto& e : v) {
+        lo = std::min(lo, e.first);
+        hi = std::max(hi, e.first);
+    }
+    auto digit_key = [&](int64_t k) -> uint64_t {
+        return descending ? (uint64_t)(hi - k) : (uint64_t)(k - lo);
+    };
+    const uint64_t span = (uint64_t)(hi - lo);
+    std::vector<std::pair<int64_t, int32_t>> tmp(v.size());
+    std::vector<uint32_t> cnt(65537);
+    for (int sh = 0; sh < 64 && (span >> sh) != 0; sh += 16) {
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (const auto& e : v) ++cnt[((digit_key(e.first) >> sh) & 0xFFFF) + 1];
+        for (int d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
+        for (const auto& e : v) tmp[cnt[(digit_key(e.first) >> sh) & 0xFFFF]++] = e;
+        v.swap(tmp);
+    }
+}
+
 // Build the plan for the pairs idx[0..cnt) of a call with n pairs.  Each
 // job writes result record idx[k] and its op string at ops_off[idx[k]].
 void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
@@ -465,12 +491,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     }
     // batches: longest pair first (the last pairs to finish are the short
     // ones); serving: shortest first (short results are out early)
-    std::sort(bysize.begin(), bysize.end(),
-              [shortest_first](const std::pair<int64_t, int32_t>& a,
-                               const std::pair<int64_t, int32_t>& b) {
-                  if (a.first != b.first) return shortest_first ? a.first < b.first : a.first > b.first;
-                  return a.second < b.second;
-              });
+    sort_by_key(bysize, !shortest_first);
     for (auto& e : bysize) {
         const PairJob& J = P.jobs[e.second];
         Group* g = nullptr;
@@ -485,10 +506,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     }
     // int16 pairs: neighbours in size order share a pack
     if (!e16.empty()) {
-        std::sort(e16.begin(), e16.end(),
-                  [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
-                      return a.first > b.first || (a.first == b.first && a.second < b.second);
-                  });
+        sort_by_key(e16, true);
         P.groups.push_back(Group{K16, false, true, MPG_LOCAL, {}});
         Group& g = P.groups.back();
         for (size_t q = 0; q < e16.size(); q += 2) {
