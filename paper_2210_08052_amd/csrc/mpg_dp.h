@@ -7,17 +7,17 @@
 #include "mpg_internal.h"
 #include "mpg_walk.h"
 
-// Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  With
-// K <= 2 the kernels fit three waves per SIMD (168 VGPRs): the score-only ones
-// without spills, the traceback ones with a few spilled registers outside the
-// step loop, which three waves repay (4.9% on the traceback batch).  K = 4
-// keeps its registers.
-#ifndef MPG_TB_WAVES
-#define MPG_TB_WAVES 3
-#endif
-template <int K, bool TB>
+// Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  Three
+// waves per SIMD (168 VGPRs) where the kernel fits them without spilling in
+// the step loop: the score-only kernels of width <= 2 that end anywhere
+// (LOCAL, EXTEND), and the width-2 traceback kernels (a few spilled registers
+// outside the step loop, which the third wave repays: 4.9% on the traceback
+// batch).  Fixed-end modes (GLOBAL, EXTEND_LEFT) track H(n, m) in every step,
+// and width 1 with traceback and width 4 need more registers: they keep them.
+template <int K, bool TB, bool FIXED_END>
 struct WavesPerEu {
-    static constexpr int value = K > 2 ? 1 : (TB ? MPG_TB_WAVES : 3);
+    static constexpr int value =
+        (K > 2 || FIXED_END) ? 1 : (TB ? (K == 2 ? 3 : 1) : 3);
 };
 
 namespace mpg {
@@ -207,7 +207,7 @@ __device__ __forceinline__ bool wait_prog(const int* flag, int target) {
 // prof_gaps) instead of protein letters and one matrix.
 template <int K, int MODE, bool TB, bool NOI, bool NOF, bool PRO>
 __global__ void __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(WavesPerEu<K, TB>::value)))
+__attribute__((amdgpu_waves_per_eu(WavesPerEu<K, TB, fixed_end_mode(MODE)>::value)))
 dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int nitems,
           int* __restrict__ qhead, PairState* __restrict__ pst, int* __restrict__ prog_g,
           const uint8_t* __restrict__ prot, const uint8_t* __restrict__ desc,

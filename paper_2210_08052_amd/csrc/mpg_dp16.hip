@@ -310,7 +310,9 @@ dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
 #pragma unroll
                     for (int c = 0; c < K; ++c) csc[c] = nsc[c];
                     cin = nin;
-                    __builtin_amdgcn_sched_barrier(0);
+                    // (no scheduling barrier between steps: the next step's
+                    // independent terms fill the wait states of this step's
+                    // dependent packed instructions)
                 }  // steps
 
                 // fold the chunk's best of each half into the strip's best
