@@ -156,34 +156,6 @@ int mpg_params_check(const mpg_params *p, int32_t max_plen, int32_t max_dlen);
 int mpg_align_batch(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pairs, int32_t n,
                     mpg_result *out);
 
-/*
- * Pseudogene guard (Methods, "Avoiding pseudogenes").  An unspliced copy of a
- * gene pays no intron penalty and can outscore the real, spliced gene; the
- * paper therefore aligns the protein a second time against the coding
- * sequence with the introns taken out, and charges a single-exon alignment
- * the intron penalty r once more.  For each k with res[k].status == MPG_OK
- * (res[k] a traced result of pairs[k], as mpg_align_batch returns it, with
- * params p), this call:
- *  - cuts the coding sequence out of the pair's region along res[k].ops: the
- *    bases of M, D, F and G tokens in path order, nothing of an N token, and
- *    of a U (V) token the split codon's first base and last two (first two
- *    and last one); a U/V token shorter than three bases keeps all of them;
- *  - aligns the protein segment [p_beg, p_end) to it end to end (MPG_GLOBAL)
- *    with the intron states removed (Eq. (fs)) and p's other scoring, in
- *    the GPU kernels, score only;
- *  - writes score[k] = that optimum, minus p->r when the path has no intron,
- *    exons[k] = number of N/U/V tokens + 1, status[k] = MPG_OK or the second
- *    alignment's status (MPG_E_NOALN when the end cell is unreachable, e.g.
- *    frameshifts off and a coding length not a multiple of 3).
- * Other k get status[k] = res[k].status, score 0, exons 0.  pairs, res and
- * the three output arrays (n entries each) are host memory, borrowed for the
- * call.  MPG_E_INVAL if an MPG_OK result has no op string or its op string
- * does not span exactly its [g_beg, g_end) x [p_beg, p_end); synchronous.
- */
-int mpg_rescore_spliced(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pairs,
-                        const mpg_result *res, int32_t n, int32_t *score, int32_t *exons,
-                        int32_t *status);
-
 /* ---- device-resident batch ---------------------------------------------- */
 
 /* One pair whose letters already sit in device memory (offsets into the
@@ -226,6 +198,48 @@ int mpg_align_batch_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot
 
 /* Wait for all work enqueued on the context's stream. */
 int mpg_sync(mpg_ctx *ctx);
+
+/*
+ * Pseudogene guard (Methods, "Avoiding pseudogenes").  An unspliced copy of a
+ * gene pays no intron penalty and can outscore the real, spliced gene; the
+ * paper therefore aligns the protein a second time against the coding
+ * sequence with the introns taken out, and charges a single-exon alignment
+ * the intron penalty r once more.  For each k with res[k].status == MPG_OK
+ * (res[k] a traced result of pairs[k], as mpg_align_batch returns it, with
+ * params p), this call:
+ *  - cuts the coding sequence out of the pair's region along res[k].ops, on
+ *    the GPU: the bases of M, D, F and G tokens in path order, nothing of an
+ *    N token, and of a U (V) token the split codon's first base and last two
+ *    (first two and last one); a U/V token shorter than three bases keeps all
+ *    of them;
+ *  - aligns the protein segment [p_beg, p_end) to it end to end (MPG_GLOBAL)
+ *    with the intron states removed (Eq. (fs)) and p's other scoring, in
+ *    the GPU kernels, score only;
+ *  - writes score[k] = that optimum, minus p->r when the path has no intron,
+ *    exons[k] = number of N/U/V tokens + 1, status[k] = MPG_OK or the second
+ *    alignment's status (MPG_E_NOALN when the end cell is unreachable, e.g.
+ *    frameshifts off and a coding length not a multiple of 3).
+ * Other k get status[k] = res[k].status, score 0, exons 0.  pairs, res and
+ * the three output arrays (n entries each) are host memory, borrowed for the
+ * call.  MPG_E_INVAL if an MPG_OK result has no op string or its op string
+ * does not span exactly its [g_beg, g_end) x [p_beg, p_end); synchronous.
+ */
+int mpg_rescore_spliced(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pairs,
+                        const mpg_result *res, int32_t n, int32_t *score, int32_t *exons,
+                        int32_t *status);
+
+/* As mpg_rescore_spliced for a traced batch still in device memory: the
+ * letters and segments given to mpg_align_batch_dev and its d_out / d_ops;
+ * score, exons and status are device arrays of n entries.  The coding
+ * sequences are cut on the GPU (one wavefront per pair); the call waits for
+ * the stream twice (the first pass's records and the coding lengths come to
+ * the host to plan the second alignment) and returns with the second
+ * alignment and the final scores enqueued.  A malformed op string gives
+ * status MPG_E_INVAL for its pair. */
+int mpg_rescore_spliced_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot,
+                            const uint8_t *d_dna, const mpg_seg *segs, int32_t n,
+                            const mpg_dev_result *d_res, const char *d_ops, int32_t *d_score,
+                            int32_t *d_exons, int32_t *d_status);
 
 /* ---- anchor-driven alignment ------------------------------------------- */
 

@@ -163,6 +163,29 @@ hipError_t launch_stitch(hipStream_t s, const ChainJob* chains, int nchains, con
 // Dynamic LDS bytes of one DP wavefront.
 int dp_lds_bytes(int K, bool tb);
 
+// Pseudogene guard (mpg_kernels.hip).  One traced pair's coding-sequence cut:
+// its op string, the region from the alignment's first base, and where the
+// cut goes.
+struct CdsJob {
+    int64_t ops_off;  // op string in the ops buffer
+    int64_t dna_off;  // region base g_beg in the DNA buffer
+    int64_t cds_off;  // output slot in the coding-sequence buffer
+    int32_t ops_len;
+    int32_t cap;      // g_end - g_beg: bases the path consumes
+    int32_t plen;     // p_end - p_beg: residues the path consumes
+    int32_t _pad;
+};
+// One wavefront per job: info[k] = {coding length, introns, MPG_OK or
+// MPG_E_INVAL for an op string that does not span exactly cap x plen}.
+hipError_t launch_cds(hipStream_t s, const CdsJob* jobs, int n, const char* ops, const uint8_t* dna,
+                      uint8_t* cds, int4* info);
+// Per pair: the first pass's status if it failed, else the coding-sequence
+// cut's, else the second alignment's; score = second score, minus r when the
+// path had no intron; exons = introns + 1.  j2[k] indexes res2 (-1: none).
+hipError_t launch_rescore_finish(hipStream_t s, int n, const mpg_dev_result* res1,
+                                 const int4* info, const int32_t* j2, const mpg_dev_result* res2,
+                                 int r, int32_t* score, int32_t* exons, int32_t* status);
+
 // Chaining (mpg_chain.hip): one wavefront per anchor set.
 struct ChainSetJob {
     int64_t off;     // first anchor of the set (in anchors, f, pred, idx and the records)

@@ -297,6 +297,109 @@ __global__ void __launch_bounds__(64) stitch_kernel(const ChainJob* __restrict__
     if (lane == 0) out[C.res] = R;
 }
 
+// ------------------------------------------------------------------ coding sequence
+// Methods, "Avoiding pseudogenes": the genome bases the path consumes, in
+// order, without the interior of any intron.  M/D/F/G tokens copy their
+// bases, N copies none, U copies the split codon's first base and last two,
+// V its first two and last one (a U/V token shorter than a codon copies its
+// bases).  Lane 0 reads the tokens; every lane copies each run of bases.
+__global__ void __launch_bounds__(64) cds_kernel(const CdsJob* __restrict__ jobs, int n,
+                                                 const char* __restrict__ ops,
+                                                 const uint8_t* __restrict__ dna,
+                                                 uint8_t* __restrict__ cds,
+                                                 int4* __restrict__ info) {
+    const int k = blockIdx.x;
+    if (k >= n) return;
+    const int lane = threadIdx.x;
+    const CdsJob J = jobs[k];
+    const char* s = ops + J.ops_off;
+    const uint8_t* T = dna + J.dna_off;
+    uint8_t* out = cds + J.cds_off;
+    int pos = 0, g = 0, res = 0, introns = 0, bad = 0;
+    int i = 0;
+    for (;;) {
+        // lane 0 reads the next token and names up to two runs to copy
+        int src0 = 0, len0 = 0, src1 = 0, len1 = 0, fin = 0;
+        if (lane == 0) {
+            if (i >= J.ops_len || bad) {
+                fin = 1;
+            } else {
+                int L = 0, d0 = i;
+                while (i < J.ops_len && s[i] >= '0' && s[i] <= '9' && L <= (1 << 27))
+                    L = L * 10 + (s[i++] - '0');
+                const char op = i < J.ops_len ? s[i++] : 0;
+                int nt = 0, aa = 0;
+                if (i - 1 == d0 || L <= 0) bad = 1;  // no length digits
+                switch (op) {
+                    case 'M': nt = 3 * L; aa = L; src0 = g; len0 = nt; break;
+                    case 'D': nt = 3 * L; src0 = g; len0 = nt; break;
+                    case 'I': aa = L; break;
+                    case 'F': nt = L; aa = 1; src0 = g; len0 = nt; break;
+                    case 'G': nt = L; src0 = g; len0 = nt; break;
+                    case 'N': nt = L; ++introns; break;
+                    case 'U':
+                    case 'V':
+                        nt = L;
+                        aa = 1;
+                        ++introns;
+                        if (L < 3) {
+                            src0 = g;
+                            len0 = L;
+                        } else {
+                            const int head = op == 'U' ? 1 : 2;
+                            src0 = g;
+                            len0 = head;
+                            src1 = g + L - (3 - head);
+                            len1 = 3 - head;
+                        }
+                        break;
+                    default: bad = 1;
+                }
+                if (g + nt > J.cap || res + aa > J.plen) bad = 1;
+                if (bad) len0 = len1 = 0;
+                g += nt;
+                res += aa;
+            }
+        }
+        fin = __shfl(fin, 0);
+        if (fin) break;
+        src0 = __shfl(src0, 0);
+        len0 = __shfl(len0, 0);
+        src1 = __shfl(src1, 0);
+        len1 = __shfl(len1, 0);
+        for (int q = lane; q < len0; q += 64) out[pos + q] = T[src0 + q];
+        for (int q = lane; q < len1; q += 64) out[pos + len0 + q] = T[src1 + q];
+        pos += len0 + len1;
+    }
+    if (lane == 0) {
+        if (g != J.cap || res != J.plen) bad = 1;
+        info[k] = make_int4(bad ? 0 : pos, introns, bad ? MPG_E_INVAL : MPG_OK, 0);
+    }
+}
+
+__global__ void rescore_finish_kernel(int n, const mpg_dev_result* __restrict__ res1,
+                                      const int4* __restrict__ info, const int32_t* __restrict__ j2,
+                                      const mpg_dev_result* __restrict__ res2, int r,
+                                      int32_t* __restrict__ score, int32_t* __restrict__ exons,
+                                      int32_t* __restrict__ status) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int st = res1[k].status, sc = 0, ex = 0;
+    if (st == MPG_OK) {
+        const int4 c = info[k];
+        ex = c.y + 1;
+        st = c.z;
+        if (st == MPG_OK) {
+            const mpg_dev_result& R = res2[j2[k]];
+            st = R.status;
+            if (st == MPG_OK) sc = R.score - (ex == 1 ? r : 0);
+        }
+    }
+    score[k] = sc;
+    exons[k] = ex;
+    status[k] = st;
+}
+
 }  // namespace dev
 
 hipError_t launch_dp_k1(hipStream_t, int, bool, const DevParams&, const PairJob*, const int2*, int,
@@ -374,6 +477,22 @@ hipError_t launch_stitch(hipStream_t s, const ChainJob* chains, int nchains, con
     if (nchains <= 0) return hipSuccess;
     hipLaunchKernelGGL(stitch_kernel, dim3(nchains), dim3(64), 0, s, chains, nchains, runs, pres,
                        pops, prot, dna, P, out, ops);
+    return hipGetLastError();
+}
+
+hipError_t launch_cds(hipStream_t s, const CdsJob* jobs, int n, const char* ops, const uint8_t* dna,
+                      uint8_t* cds, int4* info) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cds_kernel, dim3(n), dim3(64), 0, s, jobs, n, ops, dna, cds, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescore_finish(hipStream_t s, int n, const mpg_dev_result* res1,
+                                 const int4* info, const int32_t* j2, const mpg_dev_result* res2,
+                                 int r, int32_t* score, int32_t* exons, int32_t* status) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rescore_finish_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, res1,
+                       info, j2, res2, r, score, exons, status);
     return hipGetLastError();
 }
 

@@ -1579,59 +1579,92 @@ int chain_sets_dev(hipStream_t st, Workspace& ws, const mpg_chaining_params* cp,
     return MPG_OK;
 }
 
-// Coding sequence of one traced alignment (Methods, "Avoiding pseudogenes"):
-// the genome bases the op string consumes, in path order, without the
-// interior of any intron.  A phase-0 intron (N) contributes nothing; a
-// phase-1 intron with its split codon (U) keeps the codon's first base and
-// its last two, a phase-2 one (V) its first two and its last one; a U/V token
-// shorter than a codon keeps its bases.  Returns false for an op string that
-// does not span exactly [g_beg, g_end) x [p_beg, p_end) of the pair.
-bool coding_sequence(const mpg_pair& pr, const mpg_result& r, std::string& cds, int32_t& introns) {
-    cds.clear();
-    introns = 0;
-    if (r.g_beg < 0 || r.p_beg < 0 || r.g_end > pr.dlen || r.p_end > pr.plen ||
-        r.g_beg > r.g_end || r.p_beg > r.p_end)
-        return false;
-    int64_t g = r.g_beg, res = r.p_beg;
-    const char* s = r.ops;
-    const char* end = r.ops + r.ops_len;
-    while (s < end) {
-        int64_t L = 0;
-        const char* d0 = s;
-        while (s < end && *s >= '0' && *s <= '9' && L <= MPG_MAX_DNA) L = L * 10 + (*s++ - '0');
-        if (s == d0 || s == end || L <= 0 || L > MPG_MAX_DNA) return false;
-        const char op = *s++;
-        int64_t nt = 0, aa = 0;
-        switch (op) {
-            case 'M': nt = 3 * L; aa = L; break;
-            case 'D': nt = 3 * L; break;
-            case 'I': aa = L; break;
-            case 'F': nt = L; aa = 1; break;
-            case 'G': nt = L; break;
-            case 'N': nt = L; break;
-            case 'U': case 'V': nt = L; aa = 1; break;
-            default: return false;
-        }
-        if (g + nt > r.g_end || res + aa > r.p_end) return false;
-        const char* b = pr.dna + g;
-        if (op == 'M' || op == 'D' || op == 'F' || op == 'G') {
-            cds.append(b, (size_t)nt);
-        } else if (op != 'I') {
-            ++introns;
-            if (op == 'U' && L >= 3) {
-                cds.push_back(b[0]);
-                cds.append(b + L - 2, 2);
-            } else if (op == 'V' && L >= 3) {
-                cds.append(b, 2);
-                cds.push_back(b[L - 1]);
-            } else if (op != 'N') {
-                cds.append(b, (size_t)L);
-            }
-        }
-        g += nt;
-        res += aa;
+// Pseudogene guard on the device: cut each traced pair's coding sequence
+// (cds_kernel), align the aligned protein segment to it end to end without
+// intron states, score only, and finish the scores (rescore_finish_kernel).
+// The coding lengths come back to the host once, to plan the second batch.
+int rescore_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
+                const uint8_t* d_dna, const mpg_seg* segs, int32_t n, const mpg_dev_result* d_res,
+                const char* d_ops, int32_t* d_score, int32_t* d_exons, int32_t* d_status,
+                RunCfg cfg) {
+    std::vector<mpg_dev_result> rec(n);
+    if (hipMemcpyAsync(rec.data(), d_res, sizeof(mpg_dev_result) * (size_t)n,
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MPG_E_DEVICE;
+    std::vector<CdsJob> jobs(n);
+    int64_t cbytes = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const mpg_dev_result& r = rec[k];
+        CdsJob& J = jobs[k];
+        std::memset(&J, 0, sizeof(J));
+        J.cds_off = cbytes;
+        if (r.status != MPG_OK) continue;
+        if (r.g_beg < 0 || r.p_beg < 0 || r.g_end < r.g_beg || r.p_end < r.p_beg ||
+            r.g_end > segs[k].dlen || r.p_end > segs[k].plen || r.ops_len < 0)
+            return MPG_E_INVAL;  // not a traced result of these pairs
+        J.ops_off = r.ops_off;
+        J.ops_len = r.ops_len;
+        J.dna_off = segs[k].dna_off + r.g_beg;
+        J.cap = r.g_end - r.g_beg;
+        J.plen = r.p_end - r.p_beg;
+        cbytes += J.cap;
     }
-    return g == r.g_end && res == r.p_end;
+    const size_t jb = sizeof(CdsJob) * (size_t)n, ib = sizeof(int4) * (size_t)n;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_j = 0, o_i = al(jb), o_c = o_i + al(ib), o_2 = o_c + al((size_t)cbytes),
+                 o_m = o_2 + al(sizeof(mpg_dev_result) * (size_t)n), tot = o_m + al(4 * (size_t)n);
+    int rc;
+    if ((rc = ws.cset.ensure(tot + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hcset.ensure(jb + 64)) != MPG_OK) return rc;
+    std::memcpy(ws.hcset.p, jobs.data(), jb);
+    uint8_t* d = (uint8_t*)ws.cset.p;
+    if (hipMemcpyAsync(d + o_j, ws.hcset.p, jb, hipMemcpyHostToDevice, st) != hipSuccess)
+        return MPG_E_DEVICE;
+    int4* d_info = (int4*)(d + o_i);
+    uint8_t* d_cds = d + o_c;
+    if (launch_cds(st, (const CdsJob*)(d + o_j), n, d_ops, d_dna, d_cds, d_info) != hipSuccess)
+        return MPG_E_DEVICE;
+    std::vector<int4> info(n);
+    if (hipMemcpyAsync(info.data(), d_info, ib, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MPG_E_DEVICE;
+    // the second alignment: end to end, no intron states, score only
+    mpg_params p2 = *p;
+    p2.mode = MPG_GLOBAL;
+    p2.flags = (p->flags | MPG_NO_INTRON) & ~(uint32_t)(MPG_WANT_TB | MPG_ALLOW_I16);
+    std::vector<mpg_seg> s2;
+    std::vector<int32_t> j2(n, -1);
+    for (int32_t k = 0; k < n; ++k) {
+        if (rec[k].status != MPG_OK || info[k].z != MPG_OK) continue;
+        mpg_seg q;
+        q.prot_off = segs[k].prot_off + rec[k].p_beg;
+        q.plen = jobs[k].plen;
+        q.dna_off = jobs[k].cds_off;
+        q.dlen = info[k].x;
+        q.flags = 0;
+        q._pad = 0;
+        j2[k] = (int32_t)s2.size();
+        s2.push_back(q);
+    }
+    mpg_dev_result* d_res2 = (mpg_dev_result*)(d + o_2);
+    int32_t* d_j2 = (int32_t*)(d + o_m);
+    if ((rc = ws.hchain.ensure(4 * (size_t)n + 64)) != MPG_OK) return rc;
+    std::memcpy(ws.hchain.p, j2.data(), 4 * (size_t)n);
+    if (hipMemcpyAsync(d_j2, ws.hchain.p, 4 * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess)
+        return MPG_E_DEVICE;
+    if (!s2.empty()) {
+        char* d_ops2 = nullptr;  // score only: one byte per pair
+        if ((rc = ws.piece_ops.ensure(s2.size() + 64)) != MPG_OK) return rc;
+        d_ops2 = (char*)ws.piece_ops.p;
+        rc = run_dev_waves(st, ws, &p2, d_prot, d_cds, s2.data(), (int32_t)s2.size(), d_res2,
+                           d_ops2, cfg);
+        if (rc != MPG_OK) return rc;
+    }
+    if (launch_rescore_finish(st, n, d_res, d_info, d_j2, d_res2, p->r, d_score, d_exons,
+                              d_status) != hipSuccess)
+        return MPG_E_DEVICE;
+    return MPG_OK;
 }
 
 extern "C" {
@@ -1959,46 +1992,15 @@ int mpg_chain_anchors(mpg_ctx* ctx, const mpg_chaining_params* cp, const int32_t
     return MPG_OK;
 }
 
-int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs,
-                        const mpg_result* res, int32_t n, int32_t* score, int32_t* exons,
-                        int32_t* status) {
-    if (!ctx || !p || n < 0 || (n > 0 && (!pairs || !res || !score || !exons || !status)))
+int mpg_rescore_spliced_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot,
+                            const uint8_t* d_dna, const mpg_seg* segs, int32_t n,
+                            const mpg_dev_result* d_res, const char* d_ops, int32_t* d_score,
+                            int32_t* d_exons, int32_t* d_status) {
+    if (!ctx || !p || n < 0 || (n > 0 && (!segs || !d_res || !d_score || !d_exons || !d_status)))
         return MPG_E_INVAL;
     int rc = params_check_impl(p);
     if (rc != MPG_OK) return rc;
-    mpg_params p2 = *p;  // the second alignment: end to end, no intron states
-    p2.mode = MPG_GLOBAL;
-    p2.flags = (p->flags | MPG_NO_INTRON) & ~(uint32_t)(MPG_WANT_TB | MPG_ALLOW_I16);
-    std::vector<std::string> cds;
-    std::vector<int32_t> idx;
-    std::vector<mpg_pair> sub;
-    cds.reserve((size_t)n);
-    for (int32_t k = 0; k < n; ++k) {
-        score[k] = 0;
-        exons[k] = 0;
-        status[k] = res[k].status;
-        if (res[k].status != MPG_OK) continue;
-        if (!res[k].ops || (pairs[k].dlen && !pairs[k].dna) || (pairs[k].plen && !pairs[k].prot))
-            return MPG_E_INVAL;
-        std::string c;
-        int32_t introns = 0;
-        if (!coding_sequence(pairs[k], res[k], c, introns)) return MPG_E_INVAL;
-        exons[k] = introns + 1;
-        cds.push_back(std::move(c));
-        idx.push_back(k);
-    }
-    for (size_t t = 0; t < idx.size(); ++t) {
-        const mpg_result& r = res[idx[t]];
-        mpg_pair q;
-        q.prot = pairs[idx[t]].prot + r.p_beg;
-        q.plen = r.p_end - r.p_beg;
-        q.dna = cds[t].data();
-        q.dlen = (int32_t)cds[t].size();
-        q.flags = 0;
-        sub.push_back(q);
-    }
-    if (sub.empty()) return MPG_OK;
-    std::vector<mpg_result> out(sub.size());
+    if (n == 0) return MPG_OK;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
@@ -2009,12 +2011,94 @@ int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs
     cfg.tm = ctx->timing ? &tm : nullptr;
     cfg.ncu = g_num_cu;
     cfg.tune = &ctx->tune;
-    rc = align_host(ctx->stream, ctx->ws, &p2, sub.data(), (int32_t)sub.size(), out.data(), cfg);
+    return rescore_dev(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, n, d_res, d_ops, d_score,
+                       d_exons, d_status, cfg);
+}
+
+int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs,
+                        const mpg_result* res, int32_t n, int32_t* score, int32_t* exons,
+                        int32_t* status) {
+    if (!ctx || !p || n < 0 || (n > 0 && (!pairs || !res || !score || !exons || !status)))
+        return MPG_E_INVAL;
+    int rc = params_check_impl(p);
     if (rc != MPG_OK) return rc;
-    for (size_t t = 0; t < idx.size(); ++t) {
-        const int32_t k = idx[t];
-        status[k] = out[t].status;
-        if (out[t].status == MPG_OK) score[k] = out[t].score - (exons[k] == 1 ? p->r : 0);
+    if (n == 0) return MPG_OK;
+    // stage letters, first-pass records and op strings as the device entry
+    // point takes them
+    std::vector<mpg_seg> segs(n);
+    std::vector<mpg_dev_result> rec(n);
+    int64_t pbytes = 0, dbytes = 0, obytes = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const mpg_pair& q = pairs[k];
+        if (q.plen < 0 || q.dlen < 0 || (q.plen && !q.prot) || (q.dlen && !q.dna)) return MPG_E_INVAL;
+        const mpg_result& r = res[k];
+        if (r.status == MPG_OK &&
+            (!r.ops || r.ops_len < 0 || r.g_beg < 0 || r.p_beg < 0 || r.g_beg > r.g_end ||
+             r.p_beg > r.p_end || r.g_end > q.dlen || r.p_end > q.plen))
+            return MPG_E_INVAL;
+        segs[k].prot_off = pbytes;
+        segs[k].dna_off = dbytes;
+        segs[k].plen = q.plen;
+        segs[k].dlen = q.dlen;
+        segs[k].flags = 0;
+        segs[k]._pad = 0;
+        mpg_dev_result& d = rec[k];
+        d.status = r.status;
+        d.score = r.score;
+        d.g_beg = r.g_beg;
+        d.g_end = r.g_end;
+        d.p_beg = r.p_beg;
+        d.p_end = r.p_end;
+        d.ops_off = obytes;
+        d.ops_len = r.status == MPG_OK ? r.ops_len : 0;
+        d._pad = 0;
+        pbytes += q.plen;
+        dbytes += q.dlen;
+        obytes += d.ops_len;
+    }
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    hipSetDevice(ctx->device);
+    Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
+             &ctx->n_cells};
+    ctx->n_calls++;
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.tm = ctx->timing ? &tm : nullptr;
+    cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
+    Workspace& ws = ctx->ws;
+    hipStream_t st = ctx->stream;
+    const size_t rb = sizeof(mpg_dev_result) * (size_t)n, ob = 12 * (size_t)n;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_p = 0, o_d = al(pbytes), o_r = o_d + al(dbytes), o_o = o_r + al(rb),
+                 o_f = o_o + al(obytes), tot = o_f + al(ob);
+    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    if ((rc = ws.seq.ensure(tot + 64)) != MPG_OK) return rc;
+    if ((rc = ws.hseq.ensure(tot + 64)) != MPG_OK) return rc;
+    uint8_t* h = (uint8_t*)ws.hseq.p;
+    for (int32_t k = 0; k < n; ++k) {
+        if (pairs[k].plen) std::memcpy(h + o_p + segs[k].prot_off, pairs[k].prot, pairs[k].plen);
+        if (pairs[k].dlen) std::memcpy(h + o_d + segs[k].dna_off, pairs[k].dna, pairs[k].dlen);
+        if (rec[k].ops_len)
+            std::memcpy(h + o_o + rec[k].ops_off, res[k].ops, (size_t)rec[k].ops_len);
+    }
+    std::memcpy(h + o_r, rec.data(), rb);
+    uint8_t* d = (uint8_t*)ws.seq.p;
+    if (hipMemcpyAsync(d, h, o_f, hipMemcpyHostToDevice, st) != hipSuccess) return MPG_E_DEVICE;
+    int32_t* d_fin = (int32_t*)(d + o_f);
+    rc = rescore_dev(st, ws, p, d + o_p, d + o_d, segs.data(), n, (const mpg_dev_result*)(d + o_r),
+                     (const char*)(d + o_o), d_fin, d_fin + n, d_fin + 2 * n, cfg);
+    if (rc != MPG_OK) return rc;
+    std::vector<int32_t> fin(3 * (size_t)n);
+    if (hipMemcpyAsync(fin.data(), d_fin, ob, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MPG_E_DEVICE;
+    for (int32_t k = 0; k < n; ++k) {
+        // a malformed op string is the caller's error
+        if (res[k].status == MPG_OK && fin[2 * n + k] == MPG_E_INVAL) return MPG_E_INVAL;
+        score[k] = fin[k];
+        exons[k] = fin[n + k];
+        status[k] = fin[2 * n + k];
     }
     return MPG_OK;
 }

@@ -128,7 +128,7 @@ EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_de
            "mpg_plan_destroy", "mpg_rescore_spliced", "mpg_align_chains",
            "mpg_chain_ops_capacity", "mpg_align_chains_dev", "mpg_align_profiles",
            "mpg_profile_bytes", "mpg_align_profiles_dev", "mpg_chaining_params_default",
-           "mpg_chain_anchors", "mpg_chain_anchors_dev"]
+           "mpg_chain_anchors", "mpg_chain_anchors_dev", "mpg_rescore_spliced_dev"]
 
 _lib = None
 
@@ -209,6 +209,10 @@ def lib():
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]
         L.mpg_chain_anchors_dev.argtypes = L.mpg_chain_anchors.argtypes
+        L.mpg_rescore_spliced_dev.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p]
         L.mpg_strerror.argtypes = [ctypes.c_int]
         L.mpg_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -407,6 +411,15 @@ class Context:
                                           ctypes.c_void_p(d_f), ctypes.c_void_p(d_pred),
                                           ctypes.c_void_p(d_idx), ctypes.c_void_p(d_top),
                                           ctypes.c_void_p(d_ntop)), "mpg_chain_anchors_dev")
+
+    def rescore_spliced_dev(self, p: mpg_params, d_prot, d_dna, segs: np.ndarray, d_res, d_ops,
+                            d_score, d_exons, d_status):
+        """Pseudogene guard on a traced device batch (see mpg_rescore_spliced_dev)."""
+        check(lib().mpg_rescore_spliced_dev(self.ptr, ctypes.byref(p), ctypes.c_void_p(d_prot),
+                                            ctypes.c_void_p(d_dna), segs.ctypes.data, len(segs),
+                                            ctypes.c_void_p(d_res), ctypes.c_void_p(d_ops),
+                                            ctypes.c_void_p(d_score), ctypes.c_void_p(d_exons),
+                                            ctypes.c_void_p(d_status)), "mpg_rescore_spliced_dev")
 
     def rescore_spliced(self, pairs, results, p: mpg_params):
         """Pseudogene guard for traced results of align_batch on the same

@@ -721,3 +721,32 @@ def test_chaining_limits(ctx):
         ctx.chain_anchors([np.array([[5, 1], [4, 2]], np.int32)], cp)
     with pytest.raises(RuntimeError):
         ctx.chain_anchors([np.array([[5, 1]], np.int32)], mpg.chaining_params(k=0))
+
+
+def test_rescore_spliced_device_resident(ctx):
+    """The device entry point on a traced device batch gives the host entry
+    point's (oracle-checked) results pair by pair."""
+    import torch
+    g, o = scorings(0, 0)
+    pairs = [(p.prot, p.dna) for p in W.batch_pairs(40, seed=77)]
+    pairs += _pairs(78, n=20, max_prot=150, max_dna=800)
+    host = ctx.rescore_spliced(pairs, ctx.align_batch(pairs, g, want_tb=True), g)
+    pb, db, segs = mpg.pack_pairs([(pr, d, True) for pr, d in pairs])
+    dev = torch.device("cuda:0")
+    d_prot = torch.frombuffer(bytearray(pb), dtype=torch.uint8).to(dev)
+    d_dna = torch.frombuffer(bytearray(db), dtype=torch.uint8).to(dev)
+    cap = mpg.lib().mpg_ops_capacity(segs.ctypes.data, len(segs))
+    d_ops = torch.zeros(cap, dtype=torch.uint8, device=dev)
+    d_out = torch.zeros(len(pairs) * mpg.DEV_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    ctx.align_batch_dev(g, d_prot.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
+                        d_ops.data_ptr(), cap)
+    fin = torch.zeros(3 * len(pairs), dtype=torch.int32, device=dev)
+    n = len(pairs)
+    for rep in range(2):
+        ctx.rescore_spliced_dev(g, d_prot.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
+                                d_ops.data_ptr(), fin.data_ptr(), fin.data_ptr() + 4 * n,
+                                fin.data_ptr() + 8 * n)
+        ctx.sync()
+        f = fin.cpu().numpy()
+        got = [(int(f[2 * n + k]), int(f[k]), int(f[n + k])) for k in range(n)]
+        assert got == [tuple(h) for h in host]
