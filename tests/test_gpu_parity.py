@@ -750,3 +750,22 @@ def test_rescore_spliced_device_resident(ctx):
         f = fin.cpu().numpy()
         got = [(int(f[2 * n + k]), int(f[k]), int(f[n + k])) for k in range(n)]
         assert got == [tuple(h) for h in host]
+
+
+def test_long_tail_full_size_properties(ctx):
+    """Long-tail pairs at full size (3,000-8,000 residues, 100-300 kb): too large
+    for the oracle's full DP, so every traced path is rescored by the oracle's
+    rescorer (the path must score exactly the reported score and end at the
+    reported end cell), and the score-only run must agree with the traced
+    one."""
+    from oracle.rescore import rescore
+    pairs = W.long_tail(4, 12, seed=21)
+    g, o = scorings(0, 0)
+    tb = ctx.align_batch([(p.prot, p.dna, True) for p in pairs], g)
+    so = ctx.align_batch([(p.prot, p.dna, False) for p in pairs], g)
+    for p, a, b in zip(pairs, tb, so):
+        assert a["status"] == b["status"] == 0
+        assert (a["score"], a["g_end"], a["p_end"]) == (b["score"], b["g_end"], b["p_end"])
+        s, ge, pe = rescore(p.prot.decode(), p.dna.decode(), o, a["g_beg"], a["p_beg"], a["ops"])
+        assert (s, ge, pe) == (a["score"], a["g_end"], a["p_end"]), (len(p.prot), len(p.dna))
+    assert max(len(p.dna) for p in pairs) > 100000
