@@ -7,17 +7,21 @@
 #include "mpg_internal.h"
 #include "mpg_walk.h"
 
-// Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  Three
-// waves per SIMD (168 VGPRs) where the kernel fits them without spilling in
-// the step loop: the score-only kernels of width <= 2 that end anywhere
-// (LOCAL, EXTEND), and the width-2 traceback kernels (a few spilled registers
-// outside the step loop, which the third wave repays: 4.9% on the traceback
-// batch).  Fixed-end modes (GLOBAL, EXTEND_LEFT) track H(n, m) in every step,
-// and width 1 with traceback and width 4 need more registers: they keep them.
+// Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  The
+// score-only kernels of width <= 2 that end anywhere (LOCAL, EXTEND) run four
+// waves per SIMD (128 VGPRs: a few spills per 64-step chunk, none in the
+// steps; 3.4% faster than three waves on the 10k batch); the width-2
+// traceback kernels run three (a few spilled registers outside the step
+// loop, which the third wave repays: 4.9% on the traceback batch).
+// Fixed-end modes (GLOBAL, EXTEND_LEFT) track H(n, m) in every step, and
+// width 1 with traceback and width 4 need more registers: they keep them.
+#ifndef MPG_SCORE_WAVES
+#define MPG_SCORE_WAVES 4
+#endif
 template <int K, bool TB, bool FIXED_END>
 struct WavesPerEu {
     static constexpr int value =
-        (K > 2 || FIXED_END) ? 1 : (TB ? (K == 2 ? 3 : 1) : 3);
+        (K > 2 || FIXED_END) ? 1 : (TB ? (K == 2 ? 3 : 1) : MPG_SCORE_WAVES);
 };
 
 namespace mpg {
