@@ -59,14 +59,31 @@ __global__ void __launch_bounds__(256) prepass16_kernel(const PairJob* __restric
                                                         const uint8_t* __restrict__ dna,
                                                         uint8_t* __restrict__ desc,
                                                         int* __restrict__ prog, DevParams P) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total_rows) return;
-    int lo = 0, hi = npacks - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (row_start[mid] <= g) lo = mid;
-        else hi = mid - 1;
+    // one binary search per block (a pack owns at least 256 rows, so a block
+    // spans at most two packs), then each thread steps forward
+    __shared__ int first_owner;
+    // the codon and splice tables, looked up with per-thread indices, in LDS
+    __shared__ uint8_t s_gcode[64], s_donor[128], s_acceptor[128];
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    if (threadIdx.x < 64) s_gcode[threadIdx.x] = P.gcode[threadIdx.x];
+    if (threadIdx.x < 125) {
+        s_donor[threadIdx.x] = P.donor[threadIdx.x];
+        s_acceptor[threadIdx.x] = P.acceptor[threadIdx.x];
     }
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = npacks - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (row_start[mid] <= g0) lo = mid;
+            else hi = mid - 1;
+        }
+        first_owner = lo;
+    }
+    __syncthreads();
+    const int64_t g = g0 + threadIdx.x;
+    if (g >= total_rows) return;
+    int lo = first_owner;
+    while (lo + 1 < npacks && row_start[lo + 1] <= g) ++lo;
     const PackJob& X = packs[lo];
     const int i = (int)(g - row_start[lo]) - kDescLo;
     if (i == -kDescLo)
@@ -86,10 +103,10 @@ __global__ void __launch_bounds__(256) prepass16_kernel(const PairJob* __restric
         int tr;
         if (i > n || i < 0) tr = 24;
         else if (i < 3 || b[2] == 4 || b[3] == 4 || b[4] == 4) tr = 22;
-        else tr = P.gcode[16 * b[2] + 4 * b[3] + b[4]];
+        else tr = s_gcode[16 * b[2] + 4 * b[3] + b[4]];
         // d(i+1) reads T[i+2..i+4]; a(i) reads T[i-2..i]
-        const int dn = P.donor[25 * b[6] + 5 * b[7] + b[8]];
-        const int ac = P.acceptor[25 * b[2] + 5 * b[3] + b[4]];
+        const int dn = s_donor[25 * b[6] + 5 * b[7] + b[8]];
+        const int ac = s_acceptor[25 * b[2] + 5 * b[3] + b[4]];
         f[h][0] = tr;
         f[h][1] = (i >= 0 && i <= n) ? 0 : kNeg16;
         f[h][2] = P.r + dn;

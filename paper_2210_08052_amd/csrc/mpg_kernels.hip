@@ -42,14 +42,32 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
                                                       int npairs, int64_t total_rows,
                                                       const uint8_t* __restrict__ dna,
                                                       uint8_t* __restrict__ desc, DevParams P) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total_rows) return;
-    int lo = 0, hi = npairs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (row_start[mid] <= g) lo = mid;
-        else hi = mid - 1;
+    // one binary search per block for the owner of its first row; a block
+    // spans few pairs (a pair owns at least 192 rows), so each thread then
+    // steps forward from there
+    __shared__ int first_owner;
+    // the codon and splice tables, looked up with per-thread indices, in LDS
+    __shared__ uint8_t s_gcode[64], s_donor[128], s_acceptor[128];
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = npairs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (row_start[mid] <= g0) lo = mid;
+            else hi = mid - 1;
+        }
+        first_owner = lo;
     }
+    if (threadIdx.x < 64) s_gcode[threadIdx.x] = P.gcode[threadIdx.x];
+    if (threadIdx.x < 125) {
+        s_donor[threadIdx.x] = P.donor[threadIdx.x];
+        s_acceptor[threadIdx.x] = P.acceptor[threadIdx.x];
+    }
+    __syncthreads();
+    const int64_t g = g0 + threadIdx.x;
+    if (g >= total_rows) return;
+    int lo = first_owner;
+    while (lo + 1 < npairs && row_start[lo + 1] <= g) ++lo;
     const PairJob& J = jobs[lo];
     const int i = (int)(g - row_start[lo]) - kDescLo;
     const int n = J.n;
@@ -62,15 +80,15 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
     int tr;
     if (i > n || i < 0) tr = 24;  // poison row
     else if (i < 3 || b[2] == 4 || b[3] == 4 || b[4] == 4) tr = 22;
-    else tr = P.gcode[16 * b[2] + 4 * b[3] + b[4]];
+    else tr = s_gcode[16 * b[2] + 4 * b[3] + b[4]];
     // d(x) uses T[x+1..x+3], a(x) uses T[x-2..x]; b[k] = T[i-4+k]
     auto dpen = [&](int x) -> int {  // x in i-1 .. i+1
         const int o = x - i + 4;
-        return P.donor[25 * b[o + 1] + 5 * b[o + 2] + b[o + 3]];
+        return s_donor[25 * b[o + 1] + 5 * b[o + 2] + b[o + 3]];
     };
     auto apen = [&](int x) -> int {  // x in i-2 .. i
         const int o = x - i + 4;
-        return P.acceptor[25 * b[o - 2] + 5 * b[o - 1] + b[o]];
+        return s_acceptor[25 * b[o - 2] + 5 * b[o - 1] + b[o]];
     };
     const bool valid = (i >= 0 && i <= n);
     int z;

@@ -266,8 +266,6 @@ struct Tuning {
     int K16 = 0;  // int16 kernel
 };
 
-int strip_cols(int m, int K) { return ((m + 1 + 64 * K - 1) / (64 * K)) * 64 * K; }
-
 // Columns per lane: one width for the pairs of a call wider than 64 columns
 // (pairs of one width share a launch; mixed widths would split the device
 // between concurrent persistent launches): a forced width, else the tuned
