@@ -8,20 +8,18 @@
 #include "mpg_walk.h"
 
 // Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  The
-// score-only kernels of width <= 2 that end anywhere (LOCAL, EXTEND) run four
-// waves per SIMD (128 VGPRs: a few spills per 64-step chunk, none in the
-// steps; 3.4% faster than three waves on the 10k batch); the width-2
-// traceback kernels run three (a few spilled registers outside the step
-// loop, which the third wave repays: 4.9% on the traceback batch).
-// Fixed-end modes (GLOBAL, EXTEND_LEFT) track H(n, m) in every step, and
-// width 1 with traceback and width 4 need more registers: they keep them.
+// score-only kernels of width <= 2 run four waves per SIMD (128 VGPRs: a few
+// spills per 64-step chunk, none in the steps; 3.4% faster than three waves
+// on the 10k batch); the width-2 traceback kernels run three (a few spilled
+// registers outside the step loop, which the third wave repays: 4.9% on the
+// traceback batch).  Width 1 with traceback (about 190 VGPRs, two waves) and
+// width 4 keep the registers they need.
 #ifndef MPG_SCORE_WAVES
 #define MPG_SCORE_WAVES 4
 #endif
-template <int K, bool TB, bool FIXED_END>
+template <int K, bool TB>
 struct WavesPerEu {
-    static constexpr int value =
-        (K > 2 || FIXED_END) ? 1 : (TB ? (K == 2 ? 3 : 1) : MPG_SCORE_WAVES);
+    static constexpr int value = K > 2 ? 1 : (TB ? (K == 2 ? 3 : 1) : MPG_SCORE_WAVES);
 };
 
 namespace mpg {
@@ -110,7 +108,8 @@ struct LdsLayout {
     static constexpr int PROF = 25 * SW * PS;  // profile: 24 aa + poison row
     static constexpr int IN = 64 * 8;          // incoming boundary of the chunk
     static constexpr int OUT = 128 * 8;        // outgoing boundary, then a dummy slot per lane
-    static constexpr int WAVE = RING + PROF + IN + OUT;
+    static constexpr int MAT = 640;            // substitution matrix, then the letter codes
+    static constexpr int WAVE = RING + PROF + IN + OUT + MAT;
 };
 
 // Sentinels per layout.  The floor modes keep -infinity small enough that a
@@ -182,7 +181,8 @@ __device__ __forceinline__ void publish(mpg_dev_result* rec, const mpg_dev_resul
         __threadfence_system();
         __hip_atomic_store(&rec->status, R.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     } else {
-        __threadfence();
+        // read only after the kernel has ended (by later kernels or the
+        // host): no fence
         rec->status = R.status;
     }
 }
@@ -211,7 +211,7 @@ __device__ __forceinline__ bool wait_prog(const int* flag, int target) {
 // prof_gaps) instead of protein letters and one matrix.
 template <int K, int MODE, bool TB, bool NOI, bool NOF, bool PRO>
 __global__ void __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(WavesPerEu<K, TB, fixed_end_mode(MODE)>::value)))
+__attribute__((amdgpu_waves_per_eu(WavesPerEu<K, TB>::value)))
 dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int nitems,
           int* __restrict__ qhead, PairState* __restrict__ pst, int* __restrict__ prog_g,
           const uint8_t* __restrict__ prot, const uint8_t* __restrict__ desc,
@@ -226,6 +226,18 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
     uint8_t* prof = smem + LY::RING;
     int2* inb = (int2*)(smem + LY::RING + LY::PROF);
     int2* outb = (int2*)(smem + LY::RING + LY::PROF + LY::IN);
+    int8_t* smat = (int8_t*)(smem + LY::RING + LY::PROF + LY::IN + LY::OUT);
+    uint8_t* saa = (uint8_t*)(smat + 24 * 24);
+    // the matrix and the letter codes, read with per-lane indices when a
+    // strip's profile is built, are staged in LDS once per launch
+    for (int k = lane; k < 24 * 24; k += 64) smat[k] = P.mat[k];
+    if (lane < 26) saa[lane] = kAaOfLetter[lane];
+    __syncthreads();
+    auto aa_lds = [&](uint32_t ch) -> int {
+        if (ch == '*') return 23;
+        const uint32_t u = (ch | 0x20u) - 'a';
+        return u < 26u ? saa[u] : 22;
+    };
 
     // penalties in the layout of this variant
     const int cq = TB ? 16 * (P.q + P.e) - 13 : P.q;   // I open  (TB: nibble 13)
@@ -233,6 +245,8 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
     const int ce = TB ? 16 * P.e : P.e;
     const int cf = TB ? 16 * P.f : P.f;
 
+    // Items are taken when the previous one is done (claiming ahead would
+    // hold a strip that the next strip of its pair then waits for).
     for (;;) {
         // take the next item without a divergent branch: lane 0 adds 1, the
         // other lanes add 0, so lane 0 always receives the old head; its value
@@ -263,17 +277,24 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
 #pragma unroll
             for (int c = 0; c < K; ++c) {
                 const int j = col0 + c;
-                const int pc = (j >= 1 && j <= m) ? (PRO ? 0 : aa_code(Pa[j - 1])) : -1;
+                const int pc = (j >= 1 && j <= m) ? (PRO ? 0 : aa_lds(Pa[j - 1])) : -1;
+                // all 24 entries are read before any is stored, so the reads
+                // overlap
+                int sv[24];
+#pragma unroll
+                for (int tr = 0; tr < 24; ++tr)
+                    sv[tr] = pc < 0 ? 0
+                                    : (PRO ? (int)prof_scores(Pa)[24 * (j - 1) + tr]
+                                           : (int)smat[tr * 24 + pc]);
+#pragma unroll
                 for (int tr = 0; tr < 25; ++tr) {
                     const bool poison = pc < 0 || tr == 24;
-                    const int sv = poison ? 0
-                                          : (PRO ? (int)prof_scores(Pa)[24 * (j - 1) + tr]
-                                                 : (int)P.mat[tr * 24 + pc]);
+                    const int v = tr < 24 ? sv[tr < 24 ? tr : 0] : 0;
                     if (TB)
                         ((int16_t*)prof)[tr * LY::SW + lane * K + c] =
-                            (int16_t)(poison ? -32768 : 16 * sv + 14);
+                            (int16_t)(poison ? -32768 : 16 * v + 14);
                     else
-                        ((int8_t*)prof)[tr * LY::SW + lane * K + c] = (int8_t)(poison ? -128 : sv);
+                        ((int8_t*)prof)[tr * LY::SW + lane * K + c] = (int8_t)(poison ? -128 : v);
                 }
             }
             inb[lane] = make_int2(NEG, NEG);
@@ -329,12 +350,21 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         // descriptor ring: rows -64..-1 then 0..63
         int4 pf0 = make_int4(0, 0, 0, 0), pf1 = make_int4(0, 0, 0, 0);
         if (act) {
+            // all loads first, then the stores
             const uint8_t* src = dsc_g + (int64_t)(lane - 64 + kDescLo) * LY::DS;
-            *(int4*)(ring + lane * LY::DS) = *(const int4*)src;
-            if (TB) *(int4*)(ring + lane * LY::DS + 16) = *(const int4*)(src + 16);
             const uint8_t* src2 = dsc_g + (int64_t)(lane + kDescLo) * LY::DS;
-            *(int4*)(ring + (64 + lane) * LY::DS) = *(const int4*)src2;
-            if (TB) *(int4*)(ring + (64 + lane) * LY::DS + 16) = *(const int4*)(src2 + 16);
+            const int4 r0 = *(const int4*)src, r2 = *(const int4*)src2;
+            int4 r1 = make_int4(0, 0, 0, 0), r3 = make_int4(0, 0, 0, 0);
+            if (TB) {
+                r1 = *(const int4*)(src + 16);
+                r3 = *(const int4*)(src2 + 16);
+            }
+            *(int4*)(ring + lane * LY::DS) = r0;
+            *(int4*)(ring + (64 + lane) * LY::DS) = r2;
+            if (TB) {
+                *(int4*)(ring + lane * LY::DS + 16) = r1;
+                *(int4*)(ring + (64 + lane) * LY::DS + 16) = r3;
+            }
         }
         int2 nb = make_int2(NEG, NEG);
         // the left strip's last column arrives from HBM as that strip
@@ -491,7 +521,14 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                     if (fixed_end_mode(MODE)) {
                         const bool at_n = (lane == t + srow_n);
 #pragma unroll
-                        for (int c = 0; c < K; ++c) hn[c] = at_n ? Hn[c] : hn[c];
+                        for (int c = 0; c < K; ++c) {
+                            hn[c] = at_n ? Hn[c] : hn[c];
+                            // keep the select in this step: left free, the
+                            // compiler defers all 64 of them to the chunk's
+                            // end, holding every step's H and mask live
+                            // (about 100 more VGPRs, one wave per SIMD)
+                            asm volatile("" : "+v"(hn[c]));
+                        }
                     } else if (MODE == MPG_LOCAL) {
 #pragma unroll
                         for (int c = 0; c < K; ++c)
@@ -582,12 +619,28 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
             }
         }
 
-        // ---- strip epilogue: best cell of the strip, folded into the pair
+        // ---- strip epilogue: best cell of the strip, folded into the pair.
+        // A pair of one strip keeps it in registers: no pair state, no
+        // atomics.
+        const bool solo = nstrips == 1;
+        unsigned long long solo_key = 0;
+        int solo_gsc = NEG;
         if (!failed) {
             if (fixed_end_mode(MODE)) {
+                if (solo) {
+                    int v = NEG;
 #pragma unroll
-                for (int c = 0; c < K; ++c)
-                    if (col0 + c == m) st_dev(&ps->gsc, hn[c]);
+                    for (int c = 0; c < K; ++c)
+                        if (col0 + c == m) v = hn[c];
+                    // one lane holds column m
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) v = imax(v, __shfl_xor(v, o, 64));
+                    solo_gsc = v;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < K; ++c)
+                        if (col0 + c == m) st_dev(&ps->gsc, hn[c]);
+                }
             } else {
                 uint64_t key = 0;
 #pragma unroll
@@ -602,23 +655,35 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 }
                 key = wave_max_u64(key);
                 best_key = key > best_key ? key : best_key;
-                if (lane == 0 && best_key) atomicMax(&ps->key, (unsigned long long)best_key);
+                if (solo) solo_key = best_key;
+                else if (lane == 0 && best_key)
+                    atomicMax(&ps->key, (unsigned long long)best_key);
             }
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        // the wave that finishes the pair's last strip writes the result; the
-        // count is acquire-release, so that wave sees every other strip's end
-        // key and direction bits
+        // the wave that finishes the pair's last strip writes the result.
+        // Its end key and H(n, m) are device-scope atomics that completed
+        // before the count (the wait), so the finishing wave reads them
+        // after its own count; when the traceback is walked in this kernel
+        // the count is also acquire-release, so that the walking wave sees
+        // every strip's direction bits.
         int done = 0;
-        if (lane == 0)
-            done = __hip_atomic_fetch_add(&ps->done, 1, __ATOMIC_ACQ_REL,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        done = __builtin_amdgcn_readfirstlane(done);
+        if (!solo) {
+            __builtin_amdgcn_s_waitcnt(0);
+            if (lane == 0)
+                done = (TB && sink.walk)
+                           ? __hip_atomic_fetch_add(&ps->done, 1, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT)
+                           : __hip_atomic_fetch_add(&ps->done, 1, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+            done = __builtin_amdgcn_readfirstlane(done);
+        }
         if (done == nstrips - 1) {
-            const unsigned long long k = __hip_atomic_load(&ps->key, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-            const int gv = __builtin_amdgcn_readfirstlane(ld_dev(&ps->gsc));
-            const int bad = __builtin_amdgcn_readfirstlane(ld_dev(&ps->bad));
+            const unsigned long long k =
+                solo ? solo_key
+                     : __hip_atomic_load(&ps->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int gv =
+                __builtin_amdgcn_readfirstlane(solo ? solo_gsc : ld_dev(&ps->gsc));
+            const int bad = solo ? 0 : __builtin_amdgcn_readfirstlane(ld_dev(&ps->bad));
             mpg_dev_result R;
             R.g_beg = -1;
             R.p_beg = -1;
@@ -652,6 +717,12 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 R.p_end = (1 << 15) - 1 - (int)(ku & ((1u << 15) - 1));
             }
             if (TB && sink.walk) {
+                if (solo) {
+                    // this wave's own direction bits: complete, then read
+                    // past the vector cache
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
                 // walk the traceback now: the pair completes without a second kernel
                 char* txt = sink.ops + J.ops_off;
                 if (R.status == MPG_OK) {

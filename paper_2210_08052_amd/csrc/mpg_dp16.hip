@@ -382,7 +382,10 @@ dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
             }
         }
         __builtin_amdgcn_s_waitcnt(0);
-        // the wave that finishes a pair's last strip writes its result
+        // the wave that finishes a pair's last strip writes its result; the
+        // end keys are device-scope atomics completed before the count (the
+        // wait), and nothing else of the other strips is read here, so the
+        // count needs no cache-wide release or acquire
         if (lane == 0) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -391,7 +394,7 @@ dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
                 const int jx = h ? X.b : X.a;
                 if (strip >= J.nstrips) continue;
                 PairState* ps = pst + jx;
-                const int done = __hip_atomic_fetch_add(&ps->done, 1, __ATOMIC_ACQ_REL,
+                const int done = __hip_atomic_fetch_add(&ps->done, 1, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
                 if (done != J.nstrips - 1) continue;
                 mpg_dev_result R;

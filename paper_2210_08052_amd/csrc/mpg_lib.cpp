@@ -490,16 +490,31 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     // batches: longest pair first (the last pairs to finish are the short
     // ones); serving: shortest first (short results are out early)
     sort_by_key(bysize, !shortest_first);
+    // one group per (width, traceback, mode), in order of first appearance;
+    // its items are counted first so that each list is allocated once
+    auto gkey = [](const PairJob& J) {
+        return ((J.K == 1 ? 0 : J.K == 2 ? 1 : 2) * 2 + (J.tb ? 1 : 0)) * 4 + J.mode;
+    };
+    int gidx[24];
+    int64_t gcount[24] = {0};
+    std::fill(gidx, gidx + 24, -1);
+    int64_t nwalk = 0;
     for (auto& e : bysize) {
         const PairJob& J = P.jobs[e.second];
-        Group* g = nullptr;
-        for (auto& gg : P.groups)
-            if (gg.K == J.K && gg.tb == (J.tb != 0) && !gg.i16 && gg.mode == J.mode) g = &gg;
-        if (!g) {
+        const int key = gkey(J);
+        if (gidx[key] < 0) {
+            gidx[key] = (int)P.groups.size();
             P.groups.push_back(Group{J.K, J.tb != 0, false, J.mode, {}});
-            g = &P.groups.back();
         }
-        for (int st = 0; st < J.nstrips; ++st) g->items.push_back(make_int2(e.second, st));
+        gcount[gidx[key]] += J.nstrips;
+        nwalk += J.tb ? 1 : 0;
+    }
+    for (size_t g = 0; g < P.groups.size(); ++g) P.groups[g].items.reserve(gcount[g]);
+    P.walk.reserve(nwalk);
+    for (auto& e : bysize) {
+        const PairJob& J = P.jobs[e.second];
+        Group& g = P.groups[gidx[gkey(J)]];
+        for (int st = 0; st < J.nstrips; ++st) g.items.push_back(make_int2(e.second, st));
         if (J.tb) P.walk.push_back(e.second);
     }
     // int16 pairs: neighbours in size order share a pack
@@ -680,17 +695,23 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     X.d_dna = d_dna;
     X.d_out = d_out;
     X.d_ops = d_ops;
-    // prepass list: planned pairs only, row_start ascending
+    // prepass list: planned pairs only, row_start ascending; when every pair
+    // is planned in int32 lanes, the job list itself
+    bool all_int32 = true;
+    for (int32_t k = 0; k < cnt && all_int32; ++k)
+        all_int32 = P.jobs[k].status == MPG_OK && !P.jobs[k].i16;
     std::vector<PairJob> pjobs;
     std::vector<int64_t> pstarts;
-    pjobs.reserve(cnt);
-    pstarts.reserve(cnt);
-    for (int32_t k = 0; k < cnt; ++k)
-        if (P.jobs[k].status == MPG_OK && !P.jobs[k].i16) {
-            pjobs.push_back(P.jobs[k]);
-            pstarts.push_back(P.row_start[k]);
-        }
-    X.npjobs = pjobs.size();
+    if (!all_int32) {
+        pjobs.reserve(cnt);
+        pstarts.reserve(cnt);
+        for (int32_t k = 0; k < cnt; ++k)
+            if (P.jobs[k].status == MPG_OK && !P.jobs[k].i16) {
+                pjobs.push_back(P.jobs[k]);
+                pstarts.push_back(P.row_start[k]);
+            }
+    }
+    X.npjobs = all_int32 ? (size_t)cnt : pjobs.size();
     const size_t npacks = P.packs.size();
     X.npacks = npacks;
     if (tm && tm->i16)
@@ -700,6 +721,9 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
             if (J.status == MPG_OK) *tm->cells += (uint64_t)J.n * (uint64_t)J.m;
     // work items of every launch, then the walk order (local job indices)
     std::vector<int2> items;
+    size_t nitems = 0;
+    for (auto& g : P.groups) nitems += g.items.size();
+    items.reserve(nitems);
     X.goff.clear();
     for (auto& g : P.groups) {
         X.goff.push_back(items.size());
@@ -709,7 +733,7 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
 
     const size_t jobs_b = sizeof(PairJob) * (size_t)cnt;
     const size_t pj_b = sizeof(PairJob) * pjobs.size();
-    const size_t ps_b = sizeof(int64_t) * pstarts.size();
+    const size_t ps_b = sizeof(int64_t) * X.npjobs;
     const size_t it_b = sizeof(int2) * items.size();
     const size_t wk_b = sizeof(int32_t) * P.walk.size();
     const size_t pk_b = sizeof(PackJob) * npacks;
@@ -734,16 +758,16 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     if ((rc = ws.hplan.ensure(plan_b)) != MPG_OK) return rc;
     uint8_t* h = (uint8_t*)ws.hplan.p;
     std::memcpy(h, P.jobs.data(), jobs_b);
-    std::memcpy(h + jobs_b, pjobs.data(), pj_b);
+    if (pj_b) std::memcpy(h + jobs_b, pjobs.data(), pj_b);
     std::memcpy(h + jobs_b + pj_b, P.packs.data(), pk_b);
     uint8_t* h2 = h + jobs_b + pj_b + pk_b;
-    std::memcpy(h2, pstarts.data(), ps_b);
+    std::memcpy(h2, all_int32 ? P.row_start.data() : pstarts.data(), ps_b);
     std::memcpy(h2 + ps_b, P.pack_row_start.data(), pks_b);
     uint8_t* h3 = h2 + ps_b + pks_b;
     std::memcpy(h3, items.data(), it_b);
     std::memcpy(h3 + it_b, P.walk.data(), wk_b);
     X.d_jobs = (PairJob*)ws.jobs.p;
-    X.d_pjobs = (PairJob*)((uint8_t*)ws.jobs.p + jobs_b);
+    X.d_pjobs = all_int32 ? (PairJob*)ws.jobs.p : (PairJob*)((uint8_t*)ws.jobs.p + jobs_b);
     X.d_packs = (PackJob*)((uint8_t*)ws.jobs.p + jobs_b + pj_b);
     X.d_starts = (int64_t*)ws.row_start.p;
     X.d_pkstarts = (int64_t*)((uint8_t*)ws.row_start.p + ps_b);
