@@ -323,12 +323,16 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         int zl[K], best[K], bstep[K], bk[K], bkt[K], hn[K];
         uint32_t nacc[K];
         uint32_t xacc[5][K];  // extension decisions of the last steps, per lane
+        // The fixed-end kernel also runs EXTEND_LEFT pairs: their start term
+        // is the row's own (0 on every valid row), so the column term is
+        // lifted out of the minimum.
+        const bool floor0 = fixed_end_mode(MODE) && J.mode == MPG_EXTEND_LEFT;
 #pragma unroll
         for (int c = 0; c < K; ++c) {
             h1[c] = h2[c] = h3[c] = NEG;
             d1[c] = d2[c] = d3[c] = NEG;
             a1[c] = b1[c] = c1[c] = NEG;
-            zl[c] = (col0 + c == 0) ? ZN : NEG + ZN;
+            zl[c] = floor0 ? INT_MAX : ((col0 + c == 0) ? ZN : NEG + ZN);
             best[c] = NEG;
             bstep[c] = 0;
             bk[c] = INT_MIN;
@@ -794,8 +798,7 @@ hipError_t launch_dp_k(hipStream_t s, int ncu, bool tb, const DevParams& P, cons
     switch (P.mode) {
         case MPG_LOCAL: MPG_MODE(MPG_LOCAL);
         case MPG_EXTEND: MPG_MODE(MPG_EXTEND);
-        case MPG_EXTEND_LEFT: MPG_MODE(MPG_EXTEND_LEFT);
-        default: MPG_MODE(MPG_GLOBAL);
+        default: MPG_MODE(MPG_GLOBAL);  // GLOBAL and EXTEND_LEFT (per-pair start term)
     }
 #undef MPG_MODE
 }

@@ -171,6 +171,30 @@ struct HostBuf {  // pinned host memory
     }
 };
 
+// One DP launch: the strips of every pair sharing (K, traceback, kernel
+// mode), as a queue of (job, strip) items, longest pair first, strips in
+// order.  The int16 group's items are (pack, strip).
+struct Group {
+    int K;
+    bool tb;
+    bool i16;
+    int mode;  // kernel variant of the group's pairs (EXTEND_LEFT pairs run in GLOBAL's)
+    size_t off, cnt;  // its work items in Plan::items
+};
+
+struct Plan {
+    std::vector<int2> items;  // work items of every group, group after group
+    std::vector<PairJob> jobs;
+    std::vector<int64_t> row_start;
+    std::vector<Group> groups;
+    std::vector<int32_t> walk;
+    std::vector<PackJob> packs;
+    std::vector<int64_t> pack_row_start;
+    int64_t desc_bytes = 0, bnd_elems = 0, tb_bytes = 0;
+    int64_t total_rows = 0, pack_rows = 0;
+    int64_t nprog = 0;
+};
+
 // Everything one in-flight batch needs on the device.  The DP launches of a
 // batch (one per kernel variant) run concurrently on side streams forked
 // from the batch stream and joined back with events.
@@ -180,6 +204,15 @@ struct Workspace {
         piece_ops, cset, cio;
     HostBuf hplan, hseq, hout, hops, hchain, hcset;
     HostBuf prec, pops;  // serving: host-mapped records and op strings the host polls
+    // host-side planning storage kept from call to call, so that large plans
+    // reuse memory that is already mapped instead of faulting in new pages
+    Plan plan_cache;
+    std::vector<mpg_seg> psegs;
+    std::vector<int8_t> pmodes;
+    std::vector<int4> cruns;
+    std::vector<ChainJob> cjobs;
+    std::vector<int64_t> wave_ops_off;
+    std::vector<int32_t> wave_idx;
     void defer_frees(Retired* r) {
         DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state,
                        &chain, &piece_out, &piece_ops, &cset, &cio};
@@ -222,28 +255,6 @@ struct Workspace {
 };
 
 // ------------------------------------------------------------------ planning
-// One DP launch: the strips of every pair sharing (K, traceback), as a
-// queue of (job, strip) items, longest pair first, strips in order.  The
-// int16 group's items are (pack, strip).
-struct Group {
-    int K;
-    bool tb;
-    bool i16;
-    int mode;  // every pair of a group has this boundary mode
-    std::vector<int2> items;
-};
-
-struct Plan {
-    std::vector<PairJob> jobs;
-    std::vector<int64_t> row_start;
-    std::vector<Group> groups;
-    std::vector<int32_t> walk;
-    std::vector<PackJob> packs;
-    std::vector<int64_t> pack_row_start;
-    int64_t desc_bytes = 0, bnd_elems = 0, tb_bytes = 0;
-    int64_t total_rows = 0, pack_rows = 0;
-    int64_t nprog = 0;
-};
 
 int g_max_lds = 65536;
 
@@ -423,8 +434,12 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     P.jobs.assign(cnt, PairJob{});
     P.row_start.assign(cnt, 0);
     P.groups.clear();
+    P.items.clear();
     P.walk.clear();
+    P.packs.clear();
+    P.pack_row_start.clear();
     P.desc_bytes = P.bnd_elems = P.tb_bytes = P.total_rows = 0;
+    P.pack_rows = P.nprog = 0;
     std::vector<std::pair<int64_t, int32_t>> bysize;
     bysize.reserve(cnt);
     const Overrides ov;
@@ -490,10 +505,13 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     // batches: longest pair first (the last pairs to finish are the short
     // ones); serving: shortest first (short results are out early)
     sort_by_key(bysize, !shortest_first);
-    // one group per (width, traceback, mode), in order of first appearance;
-    // its items are counted first so that each list is allocated once
-    auto gkey = [](const PairJob& J) {
-        return ((J.K == 1 ? 0 : J.K == 2 ? 1 : 2) * 2 + (J.tb ? 1 : 0)) * 4 + J.mode;
+    // one group per (width, traceback, mode), in order of first appearance,
+    // its items counted first and then written in place; the two fixed-end
+    // modes share a kernel (EXTEND_LEFT's start term is
+    // read per pair), so a chain's three piece kinds fill two groups per width
+    auto gmode = [](int mode) { return mode == MPG_EXTEND_LEFT ? MPG_GLOBAL : mode; };
+    auto gkey = [&](const PairJob& J) {
+        return ((J.K == 1 ? 0 : J.K == 2 ? 1 : 2) * 2 + (J.tb ? 1 : 0)) * 4 + gmode(J.mode);
     };
     int gidx[24];
     int64_t gcount[24] = {0};
@@ -504,24 +522,29 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         const int key = gkey(J);
         if (gidx[key] < 0) {
             gidx[key] = (int)P.groups.size();
-            P.groups.push_back(Group{J.K, J.tb != 0, false, J.mode, {}});
+            P.groups.push_back(Group{J.K, J.tb != 0, false, gmode(J.mode), 0, 0});
         }
         gcount[gidx[key]] += J.nstrips;
         nwalk += J.tb ? 1 : 0;
     }
-    for (size_t g = 0; g < P.groups.size(); ++g) P.groups[g].items.reserve(gcount[g]);
+    size_t total = 0;
+    for (size_t g = 0; g < P.groups.size(); ++g) {
+        P.groups[g].off = total;
+        total += (size_t)gcount[g];
+    }
+    P.items.resize(total);
     P.walk.reserve(nwalk);
     for (auto& e : bysize) {
         const PairJob& J = P.jobs[e.second];
         Group& g = P.groups[gidx[gkey(J)]];
-        for (int st = 0; st < J.nstrips; ++st) g.items.push_back(make_int2(e.second, st));
+        for (int st = 0; st < J.nstrips; ++st)
+            P.items[g.off + g.cnt++] = make_int2(e.second, st);
         if (J.tb) P.walk.push_back(e.second);
     }
     // int16 pairs: neighbours in size order share a pack
     if (!e16.empty()) {
         sort_by_key(e16, true);
-        P.groups.push_back(Group{K16, false, true, MPG_LOCAL, {}});
-        Group& g = P.groups.back();
+        P.groups.push_back(Group{K16, false, true, MPG_LOCAL, P.items.size(), 0});
         for (size_t q = 0; q < e16.size(); q += 2) {
             const PairJob& A = P.jobs[e16[q].second];
             const bool hasB = q + 1 < e16.size();
@@ -551,8 +574,12 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
             return (int64_t)P.packs[a].nstrips * P.packs[a].nchunks >
                    (int64_t)P.packs[b].nstrips * P.packs[b].nchunks;
         });
+        Group& g = P.groups.back();
         for (int32_t xi : ord)
-            for (int st = 0; st < P.packs[xi].nstrips; ++st) g.items.push_back(make_int2(xi, st));
+            for (int st = 0; st < P.packs[xi].nstrips; ++st) {
+                P.items.push_back(make_int2(xi, st));
+                ++g.cnt;
+            }
     }
 }
 
@@ -720,15 +747,9 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
         for (const PairJob& J : P.jobs)
             if (J.status == MPG_OK) *tm->cells += (uint64_t)J.n * (uint64_t)J.m;
     // work items of every launch, then the walk order (local job indices)
-    std::vector<int2> items;
-    size_t nitems = 0;
-    for (auto& g : P.groups) nitems += g.items.size();
-    items.reserve(nitems);
+    const std::vector<int2>& items = P.items;
     X.goff.clear();
-    for (auto& g : P.groups) {
-        X.goff.push_back(items.size());
-        items.insert(items.end(), g.items.begin(), g.items.end());
-    }
+    for (auto& g : P.groups) X.goff.push_back(g.off);
     if (P.groups.size() > 15) return MPG_E_INVAL;
 
     const size_t jobs_b = sizeof(PairJob) * (size_t)cnt;
@@ -816,7 +837,7 @@ int enqueue(hipStream_t st, Workspace& ws, const Prepared& X, const RunCfg& cfg,
     if (tm) tm->begin(st, 1);
     auto launch_group = [&](hipStream_t s2, size_t g) -> hipError_t {
         const Group& G = P.groups[g];
-        const int nit = (int)G.items.size();
+        const int nit = (int)G.cnt;
         DevParams DG = DP;
         DG.mode = G.mode;
         if (G.i16)
@@ -863,6 +884,13 @@ int run_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
             const std::vector<int64_t>& ops_off, mpg_dev_result* d_out, char* d_ops,
             const RunCfg& cfg) {
     Prepared X;
+    // plan in the workspace's storage, handed back on every return
+    struct Lend {
+        Plan& a;
+        Plan& b;
+        Lend(Plan& x, Plan& y) : a(x), b(y) { std::swap(a, b); }
+        ~Lend() { std::swap(a, b); }
+    } lend(X.P, ws.plan_cache);
     int rc = prepare(st, ws, p, d_prot, d_dna, segs, idx, cnt, ops_off, d_out, d_ops, cfg, X);
     if (rc != MPG_OK) return rc;
     return enqueue(st, ws, X, cfg, true);
@@ -879,7 +907,8 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
                   const uint8_t* d_dna, const mpg_seg* segs, int32_t n, mpg_dev_result* d_out,
                   char* d_ops, const RunCfg& cfg) {
     const uint64_t tb_budget = cfg.tb_budget;
-    std::vector<int64_t> ops_off(n);
+    std::vector<int64_t>& ops_off = ws.wave_ops_off;
+    ops_off.resize(n);
     int64_t o = 0;
     for (int32_t k = 0; k < n; ++k) {
         ops_off[k] = o;
@@ -887,7 +916,8 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
                                        std::max(0, segs[k].plen)) + 1
                                 : 1;
     }
-    std::vector<int32_t> idx;
+    std::vector<int32_t>& idx = ws.wave_idx;
+    idx.clear();
     idx.reserve(n);
     int64_t acc = 0;
     // waves are sized with each pair's largest direction-bit need over the
@@ -1453,10 +1483,15 @@ bool chain_tb(const mpg_chain_seg& c, const mpg_params* p) {
 int chains_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
                const uint8_t* d_dna, const mpg_chain_seg* chains, int32_t n,
                mpg_dev_result* d_out, char* d_ops, int64_t ops_cap, RunCfg cfg) {
-    std::vector<int4> runs, cr;
-    std::vector<ChainJob> cj(n);
-    std::vector<mpg_seg> psegs;
-    std::vector<int8_t> modes;
+    std::vector<int4> cr;
+    std::vector<int4>& runs = ws.cruns;
+    std::vector<ChainJob>& cj = ws.cjobs;
+    std::vector<mpg_seg>& psegs = ws.psegs;
+    std::vector<int8_t>& modes = ws.pmodes;
+    runs.clear();
+    cj.resize(n);
+    psegs.clear();
+    modes.clear();
     int64_t cops = 0;
     for (int32_t c = 0; c < n; ++c) {
         const mpg_chain_seg& ch = chains[c];
