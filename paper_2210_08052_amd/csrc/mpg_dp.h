@@ -217,8 +217,11 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
           const uint8_t* __restrict__ prot, const uint8_t* __restrict__ desc,
           int2* __restrict__ bnd, uint8_t* __restrict__ tbbuf, DpSink sink, DevParams P) {
     using LY = LdsLayout<K, TB>;
-    constexpr int NEG = Sentinel<MODE, TB>::NEG;
-    constexpr int UNREACH = Sentinel<MODE, TB>::UNREACH;
+    // the mixed variant runs EXTEND and fixed-end pairs (per-pair modes)
+    constexpr bool MIXED = MODE == kModeMixed;
+    constexpr int SM = MIXED ? (int)MPG_GLOBAL : MODE;  // mode of the sentinels and the floor
+    constexpr int NEG = Sentinel<SM, TB>::NEG;
+    constexpr int UNREACH = Sentinel<SM, TB>::UNREACH;
     constexpr int ZN = TB ? 15 : 0;  // nibble of the start candidate
     extern __shared__ __align__(16) uint8_t smem[];
     const int lane = threadIdx.x & 63;
@@ -326,7 +329,9 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         // The fixed-end kernel also runs EXTEND_LEFT pairs: their start term
         // is the row's own (0 on every valid row), so the column term is
         // lifted out of the minimum.
-        const bool floor0 = fixed_end_mode(MODE) && J.mode == MPG_EXTEND_LEFT;
+        const bool floor0 = (MIXED || fixed_end_mode(MODE)) && J.mode == MPG_EXTEND_LEFT;
+        // the pair ends at (n, m) (a compile-time constant but in the mixed variant)
+        const bool fixed = MIXED ? J.mode != MPG_EXTEND : fixed_end_mode(MODE);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
             h1[c] = h2[c] = h3[c] = NEG;
@@ -469,7 +474,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         const int L1 = c ? h1[c - 1] : hl1;
                         const int L2 = c ? h2[c - 1] : hl2;
                         const int L3 = c ? h3[c - 1] : hl3;
-                        const int z = floor_mode(MODE) ? zr : imin(zr, zl[c]);
+                        const int z = floor_mode(SM) ? zr : imin(zr, zl[c]);
                         if (!TB) {
                             const int D = imax(h3[c] - cqDv[c], d3[c]) - ceDv[c];
                             int H = D;
@@ -522,7 +527,18 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         }
                     }
                     // end-cell tracking (chunk-local, merged after the chunk)
-                    if (fixed_end_mode(MODE)) {
+                    if constexpr (MIXED) {
+                        // the best cell, over every cell (EXTEND) or the
+                        // cells of row n (fixed end)
+                        const bool take = !fixed || lane == t + srow_n;
+#pragma unroll
+                        for (int c = 0; c < K; ++c) {
+                            const int v = take ? Hn[c] : NEG;
+                            const bool gt = v > bk[c];
+                            bk[c] = gt ? v : bk[c];
+                            bkt[c] = gt ? t : bkt[c];
+                        }
+                    } else if (fixed_end_mode(MODE)) {
                         const bool at_n = (lane == t + srow_n);
 #pragma unroll
                         for (int c = 0; c < K; ++c) {
@@ -587,7 +603,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 }  // steps
 
                 // merge the chunk's best into the strip's best (first maximum)
-                if (!fixed_end_mode(MODE)) {
+                if (MIXED || !fixed_end_mode(MODE)) {
 #pragma unroll
                     for (int c = 0; c < K; ++c) {
                         int v, tt;
@@ -630,12 +646,17 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         unsigned long long solo_key = 0;
         int solo_gsc = NEG;
         if (!failed) {
-            if (fixed_end_mode(MODE)) {
+            if (fixed) {
+                // H(n, m): tracked on its own, or (mixed variant) the best
+                // cell of row n
+                int hv[K];
+#pragma unroll
+                for (int c = 0; c < K; ++c) hv[c] = MIXED ? best[c] : hn[c];
                 if (solo) {
                     int v = NEG;
 #pragma unroll
                     for (int c = 0; c < K; ++c)
-                        if (col0 + c == m) v = hn[c];
+                        if (col0 + c == m) v = hv[c];
                     // one lane holds column m
 #pragma unroll
                     for (int o = 32; o >= 1; o >>= 1) v = imax(v, __shfl_xor(v, o, 64));
@@ -643,7 +664,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 } else {
 #pragma unroll
                     for (int c = 0; c < K; ++c)
-                        if (col0 + c == m) st_dev(&ps->gsc, hn[c]);
+                        if (col0 + c == m) st_dev(&ps->gsc, hv[c]);
                 }
             } else {
                 uint64_t key = 0;
@@ -699,7 +720,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 R.score = 0;
                 R.g_end = -1;
                 R.p_end = -1;
-            } else if (fixed_end_mode(MODE)) {
+            } else if (fixed) {
                 if (gv < UNREACH) {
                     R.status = MPG_E_NOALN;
                     R.score = 0;
@@ -798,6 +819,9 @@ hipError_t launch_dp_k(hipStream_t s, int ncu, bool tb, const DevParams& P, cons
     switch (P.mode) {
         case MPG_LOCAL: MPG_MODE(MPG_LOCAL);
         case MPG_EXTEND: MPG_MODE(MPG_EXTEND);
+        case kModeMixed:
+            if constexpr (!PRO) MPG_MODE(kModeMixed);
+            return hipErrorInvalidValue;  // profile queries come in one mode per call
         default: MPG_MODE(MPG_GLOBAL);  // GLOBAL and EXTEND_LEFT (per-pair start term)
     }
 #undef MPG_MODE

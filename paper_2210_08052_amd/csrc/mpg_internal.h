@@ -26,6 +26,10 @@ constexpr int kBndHi = 128;
 // 8 nibble dwords x 64 lanes (2048 B: the H winner of 8 steps per dword) +
 // 5 states x 2 halves x 64 lanes x 4 B (2560 B: one extension bit per step).
 constexpr int kTbBlockBytes = 4608;
+// Kernel variant for calls with per-pair boundary modes (not LOCAL): each
+// item runs the EXTEND code or the fixed-end code (GLOBAL, EXTEND_LEFT) by
+// its pair's mode, so such a call needs one launch per strip width.
+constexpr int kModeMixed = 8;
 
 // Scoring parameters passed by value to the kernels.
 struct DevParams {

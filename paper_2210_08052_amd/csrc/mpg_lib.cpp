@@ -306,8 +306,17 @@ int choose_K16(const Overrides& ov, const Tuning* tu, int force = 0) {
 
 int g_num_cu = 256;  // compute units of the device (the DP grid is sized per CU)
 
+// Steps every strip of a pair runs (a multiple of 64).  Lane L reaches row
+// n at step n + L: a pair of one strip stops once the lane of column m has,
+// the strips of a wider pair run all 64 lanes to row n.
+int pair_nsteps(int n, int m, int K) {
+    const int nstrips = (m + 1 + 64 * K - 1) / (64 * K);
+    const int lanes = nstrips == 1 ? m / K + 1 : 64;
+    return ((n + lanes + 63) / 64) * 64;
+}
+
 int64_t tb_bytes_of(int n, int m, int K) {
-    const int nsteps = ((n + 64 + 63) / 64) * 64;
+    const int nsteps = pair_nsteps(n, m, K);
     const int nstrips = (m + 1 + 64 * K - 1) / (64 * K);
     return (int64_t)nstrips * (nsteps / 64) * kTbBlockBytes * K;
 }
@@ -473,7 +482,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         int K = (mm + 1 <= 64 && !ov.K && !cfg.force_K) ? 1 : kc.K[want_tb ? 1 : 0];
         if (cfg.pro && K > 2) K = 2;  // profile kernels come in widths 1 and 2
         J.K = K;
-        const int nsteps = ((nn + 64 + 63) / 64) * 64;
+        const int nsteps = pair_nsteps(nn, mm, K);
         J.nchunks = nsteps / 64;
         J.nstrips = (mm + 1 + 64 * K - 1) / (64 * K);
         if (J.tb && J.status == MPG_OK && (uint64_t)tb_bytes_of(nn, mm, K) > tb_budget)
@@ -485,6 +494,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
             J.i16 = 1;
             J.K = K16;
             J.nstrips = (mm + 1 + 64 * K16 - 1) / (64 * K16);
+            J.nchunks = pair_nsteps(nn, mm, K16) / 64;
             // pairs are matched by shape: strips first, then chunks
             e16.push_back({(int64_t)J.nstrips * (1LL << 32) + J.nchunks, k});
             continue;
@@ -505,13 +515,19 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     // batches: longest pair first (the last pairs to finish are the short
     // ones); serving: shortest first (short results are out early)
     sort_by_key(bysize, !shortest_first);
-    // one group per (width, traceback, mode), in order of first appearance,
-    // its items counted first and then written in place; the two fixed-end
-    // modes share a kernel (EXTEND_LEFT's start term is
-    // read per pair), so a chain's three piece kinds fill two groups per width
-    auto gmode = [](int mode) { return mode == MPG_EXTEND_LEFT ? MPG_GLOBAL : mode; };
+    // one group per (width, traceback, kernel mode), in order of first
+    // appearance, its items counted first and then written in place.  The
+    // two fixed-end modes share a kernel (EXTEND_LEFT's start term is read
+    // per pair); with per-pair modes every mode but LOCAL runs in the mixed
+    // kernel, so a chain's three piece kinds fill one group per width.
+    const bool per_pair = cfg.modes != nullptr && !cfg.pro;
+    auto gmode = [&](int mode) {
+        if (per_pair && mode != MPG_LOCAL) return kModeMixed;
+        return mode == MPG_EXTEND_LEFT ? (int)MPG_GLOBAL : mode;
+    };
     auto gkey = [&](const PairJob& J) {
-        return ((J.K == 1 ? 0 : J.K == 2 ? 1 : 2) * 2 + (J.tb ? 1 : 0)) * 4 + gmode(J.mode);
+        const int gm = gmode(J.mode) == kModeMixed ? 3 : gmode(J.mode);  // 0, 1, 2 or 3
+        return ((J.K == 1 ? 0 : J.K == 2 ? 1 : 2) * 2 + (J.tb ? 1 : 0)) * 4 + gm;
     };
     int gidx[24];
     int64_t gcount[24] = {0};
@@ -853,14 +869,18 @@ int enqueue(hipStream_t st, Workspace& ws, const Prepared& X, const RunCfg& cfg,
         for (size_t g = 0; g < ngroups; ++g)
             if (launch_group(st, g) != hipSuccess) return MPG_E_DEVICE;
     } else if (ngroups > 1) {
-        // fork: every variant's launch starts after the prepass, concurrently
+        // fork: every variant's launch starts after the prepass, concurrently;
+        // the first runs on the batch stream itself (one hardware queue fewer
+        // to share with the side streams)
         if ((rc = ws.ensure_streams()) != MPG_OK) return rc;
         if (hipEventRecord(ws.fork_ev, st) != hipSuccess) return MPG_E_DEVICE;
-        const int ng = (int)std::min<size_t>(ngroups, kSideStreams);
+        const int ng = (int)std::min<size_t>(ngroups - 1, kSideStreams);
         for (int k = 0; k < ng; ++k)
             if (hipStreamWaitEvent(ws.side[k], ws.fork_ev, 0) != hipSuccess) return MPG_E_DEVICE;
-        for (size_t g = 0; g < ngroups; ++g)
-            if (launch_group(ws.side[g % kSideStreams], g) != hipSuccess) return MPG_E_DEVICE;
+        if (launch_group(st, 0) != hipSuccess) return MPG_E_DEVICE;
+        for (size_t g = 1; g < ngroups; ++g)
+            if (launch_group(ws.side[(g - 1) % kSideStreams], g) != hipSuccess)
+                return MPG_E_DEVICE;
         // join
         for (int k = 0; k < ng; ++k) {
             if (hipEventRecord(ws.join_ev[k], ws.side[k]) != hipSuccess) return MPG_E_DEVICE;
