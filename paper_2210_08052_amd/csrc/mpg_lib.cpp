@@ -184,6 +184,11 @@ struct Group {
 
 struct Plan {
     std::vector<int2> items;  // work items of every group, group after group
+    // planning scratch: per job group key, traceback and strips; the queue
+    // orders and the sort's buffers
+    std::vector<uint32_t> ginfo;
+    std::vector<std::pair<int64_t, int32_t>> bysize, e16, sort_tmp;
+    std::vector<uint32_t> sort_cnt;
     std::vector<PairJob> jobs;
     std::vector<int64_t> row_start;
     std::vector<Group> groups;
@@ -412,7 +417,8 @@ struct RunCfg {
 // entries arrive in index order, so equal keys stay in index order (the
 // order a comparison sort with an index tie-break gives).  LSD radix over
 // 16-bit digits: planning sorts up to ~10^5 entries per call.
-void sort_by_key(std::vector<std::pair<int64_t, int32_t>>& v, bool descending) {
+void sort_by_key(std::vector<std::pair<int64_t, int32_t>>& v, bool descending,
+                 std::vector<std::pair<int64_t, int32_t>>& tmp, std::vector<uint32_t>& cnt) {
     if (v.size() < 2) return;
     int64_t lo = v[0].first, hi = v[0].first;
     for (const auto& e : v) {
@@ -423,8 +429,8 @@ void sort_by_key(std::vector<std::pair<int64_t, int32_t>>& v, bool descending) {
         return descending ? (uint64_t)(hi - k) : (uint64_t)(k - lo);
     };
     const uint64_t span = (uint64_t)(hi - lo);
-    std::vector<std::pair<int64_t, int32_t>> tmp(v.size());
-    std::vector<uint32_t> cnt(65537);
+    tmp.resize(v.size());
+    cnt.resize(65537);
     for (int sh = 0; sh < 64 && (span >> sh) != 0; sh += 16) {
         std::fill(cnt.begin(), cnt.end(), 0u);
         for (const auto& e : v) ++cnt[((digit_key(e.first) >> sh) & 0xFFFF) + 1];
@@ -449,14 +455,33 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     P.pack_row_start.clear();
     P.desc_bytes = P.bnd_elems = P.tb_bytes = P.total_rows = 0;
     P.pack_rows = P.nprog = 0;
-    std::vector<std::pair<int64_t, int32_t>> bysize;
+    std::vector<std::pair<int64_t, int32_t>>& bysize = P.bysize;
+    bysize.clear();
     bysize.reserve(cnt);
     const Overrides ov;
     const BoundInfo bound(p);
     const bool allow16 = (p->flags & MPG_ALLOW_I16) != 0 && !cfg.pro;
     const int K16 = choose_K16(ov, cfg.tune, cfg.force_K16);
     const KChoice kc = choose_widths(ov, cfg.tune, cfg.force_K);
-    std::vector<std::pair<int64_t, int32_t>> e16;
+    std::vector<std::pair<int64_t, int32_t>>& e16 = P.e16;
+    e16.clear();
+    // One group per (width, traceback, kernel mode), in order of first
+    // appearance in the queue order, its items counted first and then written
+    // in place.  The two fixed-end modes share a kernel (EXTEND_LEFT's start term is read
+    // per pair); with per-pair modes every mode but LOCAL runs in the mixed
+    // kernel, so a chain's three piece kinds fill one group per width.
+    const bool per_pair = cfg.modes != nullptr && !cfg.pro;
+    auto gmode = [&](int mode) {
+        if (per_pair && mode != MPG_LOCAL) return kModeMixed;
+        return mode == MPG_EXTEND_LEFT ? (int)MPG_GLOBAL : mode;
+    };
+    auto gkey = [&](const PairJob& J) {
+        const int gm = gmode(J.mode) == kModeMixed ? 3 : gmode(J.mode);  // 0, 1, 2 or 3
+        return ((J.K == 1 ? 0 : J.K == 2 ? 1 : 2) * 2 + (J.tb ? 1 : 0)) * 4 + gm;
+    };
+    // per job: group key << 24 | traceback << 23 | strips (a compact copy for
+    // the passes in queue order, which visit the jobs out of order)
+    P.ginfo.resize(cnt);
     for (int32_t k = 0; k < cnt; ++k) {
         const mpg_seg& s = segs[idx[k]];
         PairJob& J = P.jobs[k];
@@ -510,38 +535,26 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         if (J.tb) P.tb_bytes += tb_bytes_of(nn, mm, K);
         J.prog_off = (int32_t)P.nprog;
         P.nprog += J.nstrips;
+        P.ginfo[k] = (uint32_t)gkey(J) << 24 | (uint32_t)(J.tb ? 1 : 0) << 23 | (uint32_t)J.nstrips;
         bysize.push_back({(int64_t)J.nstrips * J.nchunks, k});
     }
     // batches: longest pair first (the last pairs to finish are the short
     // ones); serving: shortest first (short results are out early)
-    sort_by_key(bysize, !shortest_first);
-    // one group per (width, traceback, kernel mode), in order of first
-    // appearance, its items counted first and then written in place.  The
-    // two fixed-end modes share a kernel (EXTEND_LEFT's start term is read
-    // per pair); with per-pair modes every mode but LOCAL runs in the mixed
-    // kernel, so a chain's three piece kinds fill one group per width.
-    const bool per_pair = cfg.modes != nullptr && !cfg.pro;
-    auto gmode = [&](int mode) {
-        if (per_pair && mode != MPG_LOCAL) return kModeMixed;
-        return mode == MPG_EXTEND_LEFT ? (int)MPG_GLOBAL : mode;
-    };
-    auto gkey = [&](const PairJob& J) {
-        const int gm = gmode(J.mode) == kModeMixed ? 3 : gmode(J.mode);  // 0, 1, 2 or 3
-        return ((J.K == 1 ? 0 : J.K == 2 ? 1 : 2) * 2 + (J.tb ? 1 : 0)) * 4 + gm;
-    };
+    sort_by_key(bysize, !shortest_first, P.sort_tmp, P.sort_cnt);
     int gidx[24];
     int64_t gcount[24] = {0};
     std::fill(gidx, gidx + 24, -1);
     int64_t nwalk = 0;
     for (auto& e : bysize) {
-        const PairJob& J = P.jobs[e.second];
-        const int key = gkey(J);
+        const uint32_t gi = P.ginfo[e.second];
+        const int key = (int)(gi >> 24);
         if (gidx[key] < 0) {
+            const PairJob& J = P.jobs[e.second];
             gidx[key] = (int)P.groups.size();
             P.groups.push_back(Group{J.K, J.tb != 0, false, gmode(J.mode), 0, 0});
         }
-        gcount[gidx[key]] += J.nstrips;
-        nwalk += J.tb ? 1 : 0;
+        gcount[gidx[key]] += gi & 0x7FFFFF;
+        nwalk += (gi >> 23) & 1;
     }
     size_t total = 0;
     for (size_t g = 0; g < P.groups.size(); ++g) {
@@ -551,15 +564,15 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     P.items.resize(total);
     P.walk.reserve(nwalk);
     for (auto& e : bysize) {
-        const PairJob& J = P.jobs[e.second];
-        Group& g = P.groups[gidx[gkey(J)]];
-        for (int st = 0; st < J.nstrips; ++st)
-            P.items[g.off + g.cnt++] = make_int2(e.second, st);
-        if (J.tb) P.walk.push_back(e.second);
+        const uint32_t gi = P.ginfo[e.second];
+        Group& g = P.groups[gidx[gi >> 24]];
+        const int ns = (int)(gi & 0x7FFFFF);
+        for (int st = 0; st < ns; ++st) P.items[g.off + g.cnt++] = make_int2(e.second, st);
+        if ((gi >> 23) & 1) P.walk.push_back(e.second);
     }
     // int16 pairs: neighbours in size order share a pack
     if (!e16.empty()) {
-        sort_by_key(e16, true);
+        sort_by_key(e16, true, P.sort_tmp, P.sort_cnt);
         P.groups.push_back(Group{K16, false, true, MPG_LOCAL, P.items.size(), 0});
         for (size_t q = 0; q < e16.size(); q += 2) {
             const PairJob& A = P.jobs[e16[q].second];

@@ -497,6 +497,26 @@ def test_chains(ctx, tb, flags, rs):
         assert any(r["status"] == mpg.MPG_E_NOALN for r in got)
 
 
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_chains_forced_width(ctx, K, monkeypatch):
+    """The mixed-mode kernel (EXTEND, GLOBAL and EXTEND_LEFT pieces in one
+    launch) at every forced width, with and without traceback."""
+    monkeypatch.setenv("MPG_FORCE_K", str(K))
+    g, o = scorings(0, 0)
+    cases = [(p.prot, p.dna, a, 6) for p, a in W.chain_jobs(16, seed=90 + K)]
+    cases += _chain_edge_cases()
+    for tb in (False, True):
+        print("case chains forced K=%d tb=%d" % (K, tb), flush=True)
+        got = ctx.align_chains([c + (tb,) for c in cases], g)
+        bad = []
+        for k, (c, r) in enumerate(zip(cases, got)):
+            want = ochain.align_chain(c[0].decode(), c[1].decode(), c[2], c[3], o, want_tb=tb)
+            if _chain_key(r, tb, True) != _chain_key(want, tb, False):
+                bad.append((k, _chain_key(r, tb, True), _chain_key(want, tb, False)))
+        assert not bad, "K=%d tb=%d: %d/%d mismatches, first: %s" % (K, tb, len(bad), len(cases),
+                                                                      bad[:2])
+
+
 def test_chains_long_genes(ctx):
     """Long planted genes (3-8k residues in 100-300 kb regions, long introns)
     with sparse true anchors: many uneven pieces per chain."""
