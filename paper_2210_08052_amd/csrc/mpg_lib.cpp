@@ -411,7 +411,18 @@ struct RunCfg {
                                      // (NULL: params.mode for every pair)
     bool pro = false;                // position-specific queries (prot_off: profile block)
     const int32_t* pro_bounds = nullptr;  // per pair: largest score, largest cost
+    // set: the workspace is free once this event has completed, so the host
+    // waits for it instead of for the whole stream (and plans while earlier
+    // work still runs); it covers the call's first use of the workspace only
+    hipEvent_t ws_ready = nullptr;
 };
+
+// Wait until the workspace may be reused: its readiness event when the call
+// has one, else everything on the stream.
+int wait_workspace(hipStream_t st, const RunCfg& cfg) {
+    const hipError_t e = cfg.ws_ready ? hipEventSynchronize(cfg.ws_ready) : hipStreamSynchronize(st);
+    return e == hipSuccess ? MPG_OK : MPG_E_DEVICE;
+}
 
 // Stable sort of (key, index) entries by key, ascending or descending; the
 // entries arrive in index order, so equal keys stay in index order (the
@@ -621,6 +632,10 @@ struct mpg_ctx {
     hipStream_t stream = nullptr;
     uint64_t tb_budget = 64ull << 30;
     Workspace ws;
+    // anchor-driven calls in sub-batches: two workspaces, each with the event
+    // that marks the end of its last use
+    Workspace chain_ws[2];
+    hipEvent_t chain_ev[2] = {nullptr, nullptr};
     std::mutex batch_mu;
     // optional kernel timing (hipEvents on the batch stream)
     bool timing = false;
@@ -791,7 +806,7 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     int rc;
     // the wait is device time, not host time
     const auto tw0 = std::chrono::steady_clock::now();
-    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    if ((rc = wait_workspace(st, cfg)) != MPG_OK) return rc;
     host_clock.t0 += std::chrono::steady_clock::now() - tw0;
     if ((rc = ws.jobs.ensure(jobs_b + pj_b + pk_b + 256)) != MPG_OK) return rc;
     if ((rc = ws.row_start.ensure(ps_b + pks_b + 64)) != MPG_OK) return rc;
@@ -938,7 +953,8 @@ bool seg_tb(const mpg_seg& s, const mpg_params* p) {
 // the stream; each wave writes straight into the caller's records and ops.
 int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
                   const uint8_t* d_dna, const mpg_seg* segs, int32_t n, mpg_dev_result* d_out,
-                  char* d_ops, const RunCfg& cfg) {
+                  char* d_ops, const RunCfg& cfg_in) {
+    RunCfg cfg = cfg_in;  // after the first wave, later waves wait for the stream
     const uint64_t tb_budget = cfg.tb_budget;
     std::vector<int64_t>& ops_off = ws.wave_ops_off;
     ops_off.resize(n);
@@ -964,6 +980,7 @@ int run_dev_waves(hipStream_t st, Workspace& ws, const mpg_params* p, const uint
             int rc = run_dev(st, ws, p, d_prot, d_dna, segs, idx.data(), (int32_t)idx.size(),
                              ops_off, d_out, d_ops, cfg);
             if (rc != MPG_OK) return rc;
+            cfg.ws_ready = nullptr;
             idx.clear();
             acc = 0;
         }
@@ -1508,14 +1525,29 @@ bool chain_tb(const mpg_chain_seg& c, const mpg_params* p) {
     return ((c.flags | p->flags) & MPG_WANT_TB) != 0;
 }
 
+// A chain's fields, and every anchor inside the sequences (what chain_runs
+// checks as it goes).
+bool chain_valid(const mpg_chain_seg& ch) {
+    if (ch.plen < 0 || ch.dlen < 0 || ch.prot_off < 0 || ch.dna_off < 0 || ch.k <= 0 ||
+        ch.nanchors <= 0 || !ch.anchors)
+        return false;
+    const int64_t k = ch.k;
+    for (int32_t a = 0; a < ch.nanchors; ++a) {
+        const int64_t x = ch.anchors[2 * a], y = ch.anchors[2 * a + 1];
+        if (x < 0 || y < 0 || x + 3 * k > ch.dlen || y + k > ch.plen) return false;
+    }
+    return true;
+}
+
 // Enqueue the alignment of n chains whose letters are on the device: plan
 // the runs and pieces, run every piece in one batch (per-pair modes), then
 // the stitch kernel writes chain c's record d_out[c] and op string (slot at
-// the prefix sum of mpg_chain_ops_capacity).  Waits for earlier work on st
-// before reusing the staging buffers.
+// ops_base plus the prefix sum of mpg_chain_ops_capacity).  Waits for the
+// workspace (cfg.ws_ready, else earlier work on st) before reusing it.
 int chains_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
                const uint8_t* d_dna, const mpg_chain_seg* chains, int32_t n,
-               mpg_dev_result* d_out, char* d_ops, int64_t ops_cap, RunCfg cfg) {
+               mpg_dev_result* d_out, char* d_ops, int64_t ops_cap, RunCfg cfg,
+               int64_t ops_base = 0) {
     std::vector<int4> cr;
     std::vector<int4>& runs = ws.cruns;
     std::vector<ChainJob>& cj = ws.cjobs;
@@ -1525,7 +1557,7 @@ int chains_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t
     cj.resize(n);
     psegs.clear();
     modes.clear();
-    int64_t cops = 0;
+    int64_t cops = ops_base;
     for (int32_t c = 0; c < n; ++c) {
         const mpg_chain_seg& ch = chains[c];
         if (ch.plen < 0 || ch.dlen < 0 || ch.prot_off < 0 || ch.dna_off < 0 || ch.k <= 0 ||
@@ -1574,7 +1606,7 @@ int chains_dev(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t
     const int64_t pops_cap = mpg_ops_capacity(psegs.data(), np);
     const size_t cj_b = sizeof(ChainJob) * (size_t)n, run_b = sizeof(int4) * runs.size();
     int rc;
-    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+    if ((rc = wait_workspace(st, cfg)) != MPG_OK) return rc;
     if ((rc = ws.piece_out.ensure(sizeof(mpg_dev_result) * (size_t)np + 64)) != MPG_OK) return rc;
     if ((rc = ws.piece_ops.ensure((size_t)pops_cap + 64)) != MPG_OK) return rc;
     if ((rc = ws.chain.ensure(cj_b + run_b + 64)) != MPG_OK) return rc;
@@ -1805,8 +1837,37 @@ int mpg_align_chains_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_pro
     cfg.tm = ctx->timing ? &tm : nullptr;
     cfg.ncu = g_num_cu;
     cfg.tune = &ctx->tune;
-    return chains_dev(ctx->stream, ctx->ws, p, d_prot, d_dna, chains, n, d_out, d_ops, ops_cap,
-                      cfg);
+    // Large calls run as two sub-batches on two workspaces of their own: the
+    // host plans the second while the device runs the first (each waits only
+    // for its workspace's previous use, marked by an event).  Both go to the
+    // context stream in order; every chain is checked before either is
+    // enqueued, so an invalid call does no work.  (Four sub-batches cost more
+    // in the tails of their DP launches than the overlap gains.)
+    const int nsub = n >= 2048 ? 2 : 1;
+    if (nsub == 1)
+        return chains_dev(ctx->stream, ctx->ws, p, d_prot, d_dna, chains, n, d_out, d_ops,
+                          ops_cap, cfg);
+    for (int32_t c = 0; c < n; ++c)
+        if (!chain_valid(chains[c])) return MPG_E_INVAL;
+    if (mpg_chain_ops_capacity(p, chains, n) > ops_cap) return MPG_E_RANGE;
+    for (int k = 0; k < 2; ++k)
+        if (!ctx->chain_ev[k] &&
+            hipEventCreateWithFlags(&ctx->chain_ev[k], hipEventDisableTiming) != hipSuccess)
+            return MPG_E_DEVICE;
+    int64_t ops_base = 0;
+    for (int sb = 0; sb < nsub; ++sb) {
+        const int32_t lo = (int32_t)((int64_t)n * sb / nsub);
+        const int32_t hi = (int32_t)((int64_t)n * (sb + 1) / nsub);
+        Workspace& w = ctx->chain_ws[sb & 1];
+        RunCfg c = cfg;
+        c.ws_ready = ctx->chain_ev[sb & 1];  // never recorded yet: complete
+        rc = chains_dev(ctx->stream, w, p, d_prot, d_dna, chains + lo, hi - lo, d_out + lo, d_ops,
+                        ops_cap, c, ops_base);
+        if (rc != MPG_OK) return rc;
+        if (hipEventRecord(ctx->chain_ev[sb & 1], ctx->stream) != hipSuccess) return MPG_E_DEVICE;
+        ops_base += mpg_chain_ops_capacity(p, chains + lo, hi - lo);
+    }
+    return MPG_OK;
 }
 
 int mpg_align_chains(mpg_ctx* ctx, const mpg_params* p, const mpg_chain* chains, int32_t n,
@@ -2591,6 +2652,10 @@ void mpg_ctx_destroy(mpg_ctx* ctx) {
         hipStreamDestroy(ctx->own_stream);
     }
     ctx->ws.release();
+    for (int k = 0; k < 2; ++k) {
+        ctx->chain_ws[k].release();
+        if (ctx->chain_ev[k]) hipEventDestroy(ctx->chain_ev[k]);
+    }
     for (auto* v : {&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk})
         for (auto& pr : *v) {
             hipEventDestroy(pr.first);
