@@ -233,7 +233,8 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
     uint8_t* saa = (uint8_t*)(smat + 24 * 24);
     // the matrix and the letter codes, read with per-lane indices when a
     // strip's profile is built, are staged in LDS once per launch
-    for (int k = lane; k < 24 * 24; k += 64) smat[k] = P.mat[k];
+    for (int k = lane; k < 24 * 24 / 4; k += 64)
+        ((int*)smat)[k] = ((const int*)P.mat)[k];  // 4-byte aligned in both
     if (lane < 26) saa[lane] = kAaOfLetter[lane];
     __syncthreads();
     auto aa_lds = [&](uint32_t ch) -> int {

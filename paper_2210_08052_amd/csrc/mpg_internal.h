@@ -40,6 +40,7 @@ struct DevParams {
     uint8_t donor[128];
     uint8_t acceptor[128];
 };
+static_assert(offsetof(DevParams, mat) % 4 == 0, "the DP kernel copies mat in dwords");
 
 // Per-pair launch plan (device copy; 96 bytes).
 struct PairJob {
