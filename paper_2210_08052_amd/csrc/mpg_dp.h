@@ -89,6 +89,37 @@ __device__ __forceinline__ int neg_for(int mode, bool tb) {
     return floor_mode(mode) ? (tb ? -(1 << 29) : -(1 << 25)) : -(1 << 30);
 }
 
+// ------------------------------------------------------------ prepasses
+// Rows per thread: a block covers 256 * kPrepassRows consecutive rows, so its
+// owner search and table staging are shared by that many rows, and a thread
+// reads one window of bases for its consecutive rows.
+constexpr int kPrepassRows = 4;
+static_assert(64 % kPrepassRows == 0 && kDescLo % kPrepassRows == 0 &&
+                  kDescHi % kPrepassRows == 0,
+              "a thread's rows must lie in one pair");
+
+// The last index p in [0, n) with start[p] <= g (start ascending, start[0] <=
+// g), found by wave 0 of the block 64 probes at a time: each round reads 64
+// positions spread over the remaining range at once and keeps the part between
+// the last probe at or below g and the next one, so 10^5 entries take 3 rounds
+// of dependent loads instead of 17.  Must be called by all 64 lanes of a wave.
+__device__ __forceinline__ int wave_find_owner(const int64_t* __restrict__ start, int n, int64_t g) {
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n - 1;  // start[lo] <= g; the answer is in [lo, hi]
+    while (hi > lo) {
+        const int64_t span = hi - lo;
+        // probe l: lo + ceil(span * (l + 1) / 64), ascending in l, probe 63 = hi
+        const int pl = lo + (int)((span * (lane + 1) + 63) / 64);
+        const unsigned long long ok = __ballot(start[pl] <= g);
+        const int nk = __popcll(ok);  // ok holds for probes 0 .. nk-1
+        const int nlo = nk ? lo + (int)((span * nk + 63) / 64) : lo;
+        const int nhi = nk < 64 ? lo + (int)((span * (nk + 1) + 63) / 64) - 1 : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------- DP
 //
 // Score-only layout (TB = false): plain values, descriptor {tr, z, r+d(i+1),

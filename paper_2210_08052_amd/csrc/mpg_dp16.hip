@@ -59,67 +59,73 @@ __global__ void __launch_bounds__(256) prepass16_kernel(const PairJob* __restric
                                                         const uint8_t* __restrict__ dna,
                                                         uint8_t* __restrict__ desc,
                                                         int* __restrict__ prog, DevParams P) {
-    // one binary search per block (a pack owns at least 256 rows, so a block
-    // spans at most two packs), then each thread steps forward
+    // the owner of the block's first row, then each thread steps forward (a
+    // pack owns at least 256 rows, so a block spans few packs)
     __shared__ int first_owner;
     // the codon and splice tables, looked up with per-thread indices, in LDS
     __shared__ uint8_t s_gcode[64], s_donor[128], s_acceptor[128];
-    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x * kPrepassRows;
     if (threadIdx.x < 64) s_gcode[threadIdx.x] = P.gcode[threadIdx.x];
     if (threadIdx.x < 125) {
         s_donor[threadIdx.x] = P.donor[threadIdx.x];
         s_acceptor[threadIdx.x] = P.acceptor[threadIdx.x];
     }
-    if (threadIdx.x == 0) {
-        int lo = 0, hi = npacks - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (row_start[mid] <= g0) lo = mid;
-            else hi = mid - 1;
-        }
-        first_owner = lo;
+    if (threadIdx.x < 64) {
+        const int o = wave_find_owner(row_start, npacks, g0);
+        if (threadIdx.x == 0) first_owner = o;
     }
     __syncthreads();
-    const int64_t g = g0 + threadIdx.x;
-    if (g >= total_rows) return;
+    // kPrepassRows consecutive rows per thread, all of one pack (a pack's rows
+    // start at a multiple of 64 and number a multiple of 64)
+    const int64_t q = g0 + (int64_t)threadIdx.x * kPrepassRows;
+    if (q >= total_rows) return;
     int lo = first_owner;
-    while (lo + 1 < npacks && row_start[lo + 1] <= g) ++lo;
+    while (lo + 1 < npacks && row_start[lo + 1] <= q) ++lo;
     const PackJob& X = packs[lo];
-    const int i = (int)(g - row_start[lo]) - kDescLo;
-    if (i == -kDescLo)
+    const int i0 = (int)(q - row_start[lo]) - kDescLo;
+    if (i0 == -kDescLo)
         for (int s = 0; s < X.nstrips; ++s) prog[X.prog_off + s] = 0;
-    int f[2][4];
+    constexpr int W = kPrepassRows + 8;
+    int f[kPrepassRows][2][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int jx = h ? X.b : X.a;
         const int n = jx >= 0 ? jobs[jx].n : -1;  // an idle half has no valid row
         const uint8_t* T = dna + (jx >= 0 ? jobs[jx].dna_off : 0);
-        int b[9];  // bases i-4 .. i+4
+        int b[W];  // bases i0-4 .. i0+kPrepassRows+3
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const int x = i - 4 + k;
+        for (int k = 0; k < W; ++k) {
+            const int x = i0 - 4 + k;
             b[k] = (x >= 1 && x <= n) ? dna_code(T[x - 1]) : 4;
         }
-        int tr;
-        if (i > n || i < 0) tr = 24;
-        else if (i < 3 || b[2] == 4 || b[3] == 4 || b[4] == 4) tr = 22;
-        else tr = s_gcode[16 * b[2] + 4 * b[3] + b[4]];
-        // d(i+1) reads T[i+2..i+4]; a(i) reads T[i-2..i]
-        const int dn = s_donor[25 * b[6] + 5 * b[7] + b[8]];
-        const int ac = s_acceptor[25 * b[2] + 5 * b[3] + b[4]];
-        f[h][0] = tr;
-        f[h][1] = (i >= 0 && i <= n) ? 0 : kNeg16;
-        f[h][2] = P.r + dn;
-        f[h][3] = ac;
+#pragma unroll
+        for (int rr = 0; rr < kPrepassRows; ++rr) {
+            const int i = i0 + rr;
+            const int* bb = b + rr;  // bb[k] = T[i-4+k]
+            int tr;
+            if (i > n || i < 0) tr = 24;
+            else if (i < 3 || bb[2] == 4 || bb[3] == 4 || bb[4] == 4) tr = 22;
+            else tr = s_gcode[16 * bb[2] + 4 * bb[3] + bb[4]];
+            // d(i+1) reads T[i+2..i+4]; a(i) reads T[i-2..i]
+            const int dn = s_donor[25 * bb[6] + 5 * bb[7] + bb[8]];
+            const int ac = s_acceptor[25 * bb[2] + 5 * bb[3] + bb[4]];
+            f[rr][h][0] = tr;
+            f[rr][h][1] = (i >= 0 && i <= n) ? 0 : kNeg16;
+            f[rr][h][2] = P.r + dn;
+            f[rr][h][3] = ac;
+        }
     }
     // profile offsets in bytes from the start of the profile area; B's table
     // follows A's
     const int sw2 = (int)(X.K * 64 * 2);
-    const int offA = f[0][0] * sw2;
-    const int offB = 25 * sw2 + f[1][0] * sw2;
-    int4* out = (int4*)(desc + X.desc_off + (int64_t)(i + kDescLo) * 16);
-    out[0] = make_int4(pack16(offA, offB), pack16(f[0][1], f[1][1]), pack16(f[0][2], f[1][2]),
-                       pack16(f[0][3], f[1][3]));
+    int4* out = (int4*)(desc + X.desc_off + (int64_t)(i0 + kDescLo) * 16);
+#pragma unroll
+    for (int rr = 0; rr < kPrepassRows; ++rr) {
+        const int offA = f[rr][0][0] * sw2;
+        const int offB = 25 * sw2 + f[rr][1][0] * sw2;
+        out[rr] = make_int4(pack16(offA, offB), pack16(f[rr][0][1], f[rr][1][1]),
+                            pack16(f[rr][0][2], f[rr][1][2]), pack16(f[rr][0][3], f[rr][1][3]));
+    }
 }
 
 template <int K, bool NOI, bool NOF>
@@ -456,7 +462,8 @@ hipError_t launch_prepass16(hipStream_t s, const PairJob* jobs, const PackJob* p
                             const int64_t* row_start, int npacks, int64_t total_rows,
                             const uint8_t* dna, uint8_t* desc, int* prog, const DevParams& P) {
     if (total_rows <= 0) return hipSuccess;
-    const int64_t blocks = (total_rows + 255) / 256;
+    const int64_t per_block = 256 * dev::kPrepassRows;
+    const int64_t blocks = (total_rows + per_block - 1) / per_block;
     hipLaunchKernelGGL(dev::prepass16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, jobs, packs,
                        row_start, npacks, total_rows, dna, desc, prog, P);
     return hipGetLastError();

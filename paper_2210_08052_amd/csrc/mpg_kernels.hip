@@ -42,21 +42,27 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
                                                       int npairs, int64_t total_rows,
                                                       const uint8_t* __restrict__ dna,
                                                       uint8_t* __restrict__ desc, DevParams P) {
-    // one binary search per block for the owner of its first row; a block
-    // spans few pairs (a pair owns at least 192 rows), so each thread then
-    // steps forward from there
+    // the owner of the block's first row, then each thread steps forward from
+    // there (a pair owns at least 192 rows, so a block spans few pairs)
     __shared__ int first_owner;
     // the codon and splice tables, looked up with per-thread indices, in LDS
     __shared__ uint8_t s_gcode[64], s_donor[128], s_acceptor[128];
-    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
-    if (threadIdx.x == 0) {
-        int lo = 0, hi = npairs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (row_start[mid] <= g0) lo = mid;
-            else hi = mid - 1;
+    // The block's rows are one contiguous byte range of the descriptor table
+    // (pairs are laid out in row order).  Each thread writes its rows here,
+    // then the block copies the range out in consecutive 16-byte pieces, so
+    // the stores coalesce although a thread owns several consecutive rows.
+    __shared__ __align__(16) uint8_t s_out[256 * kPrepassRows * 32];
+    __shared__ int64_t s_base;  // byte offset in desc of the block's first row
+    __shared__ int s_len;       // bytes of the block's rows
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x * kPrepassRows;
+    if (threadIdx.x < 64) {
+        const int o = wave_find_owner(row_start, npairs, g0);
+        if (threadIdx.x == 0) {
+            first_owner = o;
+            const PairJob& J0 = jobs[o];
+            s_base = J0.desc_off + (g0 - row_start[o]) * (J0.tb ? 32 : 16);
+            s_len = 0;
         }
-        first_owner = lo;
     }
     if (threadIdx.x < 64) s_gcode[threadIdx.x] = P.gcode[threadIdx.x];
     if (threadIdx.x < 125) {
@@ -64,45 +70,65 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
         s_acceptor[threadIdx.x] = P.acceptor[threadIdx.x];
     }
     __syncthreads();
-    const int64_t g = g0 + threadIdx.x;
-    if (g >= total_rows) return;
-    int lo = first_owner;
-    while (lo + 1 < npairs && row_start[lo + 1] <= g) ++lo;
-    const PairJob& J = jobs[lo];
-    const int i = (int)(g - row_start[lo]) - kDescLo;
-    const int n = J.n;
-    const uint8_t* T = dna + J.dna_off;
-    auto base = [&](int x) -> int { return (x >= 1 && x <= n) ? dna_code(T[x - 1]) : 4; };
-    int b[9];  // bases i-4 .. i+4
+    // kPrepassRows consecutive rows per thread: a pair's rows start at a
+    // multiple of 64 and number a multiple of 64, so they share one pair, one
+    // window of bases and one run of stores
+    const int64_t q = g0 + (int64_t)threadIdx.x * kPrepassRows;
+    const bool active = q < total_rows;
+    if (active) {
+        int lo = first_owner;
+        while (lo + 1 < npairs && row_start[lo + 1] <= q) ++lo;
+        const PairJob& J = jobs[lo];
+        const int i0 = (int)(q - row_start[lo]) - kDescLo;
+        const int n = J.n;
+        const uint8_t* T = dna + J.dna_off;
+        constexpr int W = kPrepassRows + 8;
+        int b[W];  // bases i0-4 .. i0+kPrepassRows+3 (code 4 outside 1..n)
 #pragma unroll
-    for (int k = 0; k < 9; ++k) b[k] = base(i - 4 + k);
-    // codon ending at i: T[i-2..i]
-    int tr;
-    if (i > n || i < 0) tr = 24;  // poison row
-    else if (i < 3 || b[2] == 4 || b[3] == 4 || b[4] == 4) tr = 22;
-    else tr = s_gcode[16 * b[2] + 4 * b[3] + b[4]];
-    // d(x) uses T[x+1..x+3], a(x) uses T[x-2..x]; b[k] = T[i-4+k]
-    auto dpen = [&](int x) -> int {  // x in i-1 .. i+1
-        const int o = x - i + 4;
-        return s_donor[25 * b[o + 1] + 5 * b[o + 2] + b[o + 3]];
-    };
-    auto apen = [&](int x) -> int {  // x in i-2 .. i
-        const int o = x - i + 4;
-        return s_acceptor[25 * b[o - 2] + 5 * b[o - 1] + b[o]];
-    };
-    const bool valid = (i >= 0 && i <= n);
-    int z;
-    const int neg = neg_for(J.mode, J.tb != 0);
-    if (floor_mode(J.mode)) z = valid ? 0 : neg;
-    else z = (i == 0) ? 0 : neg;
-    int4* out = (int4*)(desc + J.desc_off + (int64_t)(i + kDescLo) * (J.tb ? 32 : 16));
-    if (!J.tb) {
-        out[0] = make_int4(tr, z, P.r + dpen(i + 1), apen(i));
-    } else {
-        out[0] = make_int4(tr, z + 15, 16 * (P.r + dpen(i - 1)) - 7, 16 * (P.r + dpen(i)) - 6);
-        out[1] = make_int4(16 * (P.r + dpen(i + 1)) - 5, 16 * apen(i), 16 * apen(i - 2),
-                           16 * apen(i - 1));
+        for (int k = 0; k < W; ++k) {
+            const int x = i0 - 4 + k;
+            b[k] = (x >= 1 && x <= n) ? dna_code(T[x - 1]) : 4;
+        }
+        const int neg = neg_for(J.mode, J.tb != 0);
+        const bool floor = floor_mode(J.mode);
+        const int64_t at = J.desc_off + (int64_t)(i0 + kDescLo) * (J.tb ? 32 : 16) - s_base;
+        uint8_t* rowp = s_out + at;
+#pragma unroll
+        for (int rr = 0; rr < kPrepassRows; ++rr) {
+            const int i = i0 + rr;
+            const int* bb = b + rr;  // bb[k] = T[i-4+k]
+            // codon ending at i: T[i-2..i]
+            int tr;
+            if (i > n || i < 0) tr = 24;  // poison row
+            else if (i < 3 || bb[2] == 4 || bb[3] == 4 || bb[4] == 4) tr = 22;
+            else tr = s_gcode[16 * bb[2] + 4 * bb[3] + bb[4]];
+            // d(x) uses T[x+1..x+3], a(x) uses T[x-2..x]
+            auto dpen = [&](int x) -> int {  // x in i-1 .. i+1
+                const int o = x - i + 4;
+                return s_donor[25 * bb[o + 1] + 5 * bb[o + 2] + bb[o + 3]];
+            };
+            auto apen = [&](int x) -> int {  // x in i-2 .. i
+                const int o = x - i + 4;
+                return s_acceptor[25 * bb[o - 2] + 5 * bb[o - 1] + bb[o]];
+            };
+            const bool valid = (i >= 0 && i <= n);
+            const int z = floor ? (valid ? 0 : neg) : (i == 0 ? 0 : neg);
+            if (!J.tb) {
+                ((int4*)rowp)[rr] = make_int4(tr, z, P.r + dpen(i + 1), apen(i));
+            } else {
+                int4* out = (int4*)rowp + 2 * rr;
+                out[0] = make_int4(tr, z + 15, 16 * (P.r + dpen(i - 1)) - 7,
+                                   16 * (P.r + dpen(i)) - 6);
+                out[1] = make_int4(16 * (P.r + dpen(i + 1)) - 5, 16 * apen(i), 16 * apen(i - 2),
+                                   16 * apen(i - 1));
+            }
+        }
+        atomicMax(&s_len, (int)at + kPrepassRows * (J.tb ? 32 : 16));
     }
+    __syncthreads();
+    const int len = s_len;
+    for (int off = threadIdx.x * 16; off < len; off += 256 * 16)
+        *(int4*)(desc + s_base + off) = *(const int4*)(s_out + off);
 }
 
 // ------------------------------------------------------------------- init
@@ -445,7 +471,8 @@ int dp_lds_bytes(int K, bool tb) {
 hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row_start, int npairs,
                           int64_t total_rows, const uint8_t* dna, uint8_t* desc, const DevParams& P) {
     if (total_rows <= 0) return hipSuccess;
-    const int64_t blocks = (total_rows + 255) / 256;
+    const int64_t per_block = 256 * dev::kPrepassRows;
+    const int64_t blocks = (total_rows + per_block - 1) / per_block;
     hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)blocks), dim3(256), 0, s, jobs, row_start,
                        npairs, total_rows, dna, desc, P);
     return hipGetLastError();
