@@ -772,6 +772,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="batch")
+    ap.add_argument("--tb-budget-gib", type=float, default=None,
+                    help="traceback budget of the context in GiB (default: 128 for longtail, "
+                         "whose direction bits total ~250 GB, so it runs in two waves; else "
+                         "the library's 64)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibrate", action="store_true",
@@ -838,7 +842,10 @@ def main():
     d_ops = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
     d_out = torch.empty(len(pairs) * mpg.DEV_RESULT_DTYPE.itemsize, dtype=torch.uint8,
                         device=dev)
-    ctx = mpg.Context(0)
+    budget_gib = args.tb_budget_gib
+    if budget_gib is None:
+        budget_gib = 128.0 if args.config == "longtail" else 0.0
+    ctx = mpg.Context(0, tb_budget_bytes=int(budget_gib * (1 << 30)))
     stream = torch.cuda.Stream(device=dev)
     ctx.set_stream(stream.cuda_stream)
     i16 = args.config == "batch16"
