@@ -312,7 +312,11 @@ int64_t mpg_chain_ops_capacity(const mpg_params *p, const mpg_chain_seg *chains,
  * waiting.  d_out (device, n records) and d_ops (device, ops_cap bytes)
  * receive the results; each record's ops_off locates its op string.  The
  * device buffers must stay valid until the stream has finished; the anchors
- * are read before the call returns.  MPG_E_RANGE if ops_cap is too small. */
+ * are read before the call returns.  MPG_E_RANGE if ops_cap is too small.
+ * A call of 2,048 chains or more runs in two halves on two workspaces of its
+ * own: the host plans the second half while the device runs the first, and
+ * waits only for the previous call's use of each workspace, not for the whole
+ * stream.  Every chain is checked before any work is enqueued. */
 int mpg_align_chains_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot,
                          const uint8_t *d_dna, const mpg_chain_seg *chains, int32_t n,
                          mpg_dev_result *d_out, char *d_ops, int64_t ops_cap);
