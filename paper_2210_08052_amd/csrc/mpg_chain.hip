@@ -27,7 +27,7 @@ __device__ __forceinline__ long long chain_gap(long long dx, long long dy, int b
 
 // Eq. (gap-pen) for |g| < G.  Each operation rounds on its own (no fused
 // multiply-add), in the order the equation is written.
-__device__ __attribute__((noinline)) double chain_gamma(long long g, double beta) {
+__device__ __forceinline__ double chain_gamma(long long g, double beta) {
 #pragma clang fp contract(off)
     if (g == 0) return 0.0;
     const double a = (double)(g < 0 ? -g : g);
@@ -57,14 +57,23 @@ __global__ void __launch_bounds__(64) chain_kernel(const ChainSetJob* __restrict
                                                    int* __restrict__ idx_out,
                                                    mpg_chain_out* __restrict__ top,
                                                    int* __restrict__ ntop) {
-    const int s = blockIdx.x;
-    if (s >= nsets) return;
+    if ((int)blockIdx.x >= nsets) return;
     const int lane = threadIdx.x;
-    const ChainSetJob S = sets[s];
+    // the jobs come largest set first (the launch's makespan is the largest
+    // sets' sequential work); id is the set's own index
+    const ChainSetJob S = sets[blockIdx.x];
+    const int s = S.id;
     const int n = S.n;
     extern __shared__ __align__(16) uint8_t smem[];
+    // LDS: f, then (staged) the anchors and the predecessors, then the used
+    // flags.  The anchor reads of the candidate loop and the predecessor walk
+    // of the extraction are on the set's sequential path, so staging them
+    // takes a global-memory latency off every step of it.
+    const bool stage = cfg.stage != 0;
     double* f = (double*)smem;
-    uint8_t* used = smem + 8 * (size_t)cfg.max_n;
+    int2* sA = (int2*)(smem + 8 * (size_t)cfg.max_n);
+    int* spo = (int*)(smem + 16 * (size_t)cfg.max_n);
+    uint8_t* used = smem + (stage ? 20 : 8) * (size_t)cfg.max_n;
     const int2* A = anchors + S.off;
     double* fo = f_out + S.off;
     int* po = pred_out + S.off;
@@ -72,14 +81,19 @@ __global__ void __launch_bounds__(64) chain_kernel(const ChainSetJob* __restrict
         if (lane == 0) ntop[s] = S.status;
         return;
     }
+    if (stage) {
+        for (int i = lane; i < n; i += 64) sA[i] = A[i];
+        __syncthreads();
+    }
+    const int2* AA = stage ? (const int2*)sA : A;
     const double kd = (double)cfg.k;
     // ---- the DP, anchor by anchor
     for (int j = 0; j < n; ++j) {
-        const int2 aj = A[j];
+        const int2 aj = AA[j];
         double bv = 0.0;
         int bi = -1;
         for (int i = lane; i < j; i += 64) {
-            const int2 ai = A[i];
+            const int2 ai = AA[i];
             const long long dx = (long long)aj.x - ai.x, dy = (long long)aj.y - ai.y;
             if (dx < 0 || dy <= 0) continue;
             const long long g = chain_gap(dx, dy, cfg.binned);
@@ -96,6 +110,7 @@ __global__ void __launch_bounds__(64) chain_kernel(const ChainSetJob* __restrict
             f[j] = link ? bv : kd;
             fo[j] = f[j];
             po[j] = link ? bi : -1;
+            if (stage) spo[j] = link ? bi : -1;
         }
         __syncthreads();
     }
@@ -119,16 +134,17 @@ __global__ void __launch_bounds__(64) chain_kernel(const ChainSetJob* __restrict
         int len = 0;
         if (lane == 0) {
             int t = bi;
+            const int* P = stage ? (const int*)spo : po;
             while (t >= 0 && !used[t]) {
                 used[t] = 1;
                 ++len;
-                t = po[t];
+                t = P[t];
             }
             // indices ascending: write from the end of the chain's range
             int u = bi;
             for (int q = len - 1; q >= 0; --q) {
                 idx[pos + q] = u;
-                u = po[u];
+                u = P[u];
             }
             ChainRec c;
             c.score = f[bi] - (t >= 0 ? f[t] : 0.0);
@@ -171,7 +187,8 @@ hipError_t launch_chain(hipStream_t st, const ChainSetJob* sets, int nsets, cons
                         const ChainCfg& cfg, double* f, int* pred, ChainRec* recs, int* idx,
                         mpg_chain_out* top, int* ntop) {
     if (nsets <= 0) return hipSuccess;
-    const size_t lds = ((size_t)9 * cfg.max_n + 15) & ~(size_t)15;
+    const size_t lds =
+        ((size_t)(cfg.stage ? kChainStageBytes : kChainBaseBytes) * cfg.max_n + 15) & ~(size_t)15;
     hipLaunchKernelGGL(dev::chain_kernel, dim3(nsets), dim3(64), lds, st, sets, nsets, anchors,
                        cfg, f, pred, recs, idx, top, ntop);
     return hipGetLastError();

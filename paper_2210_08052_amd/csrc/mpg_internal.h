@@ -196,11 +196,17 @@ struct ChainSetJob {
     int64_t off;     // first anchor of the set (in anchors, f, pred, idx and the records)
     int32_t n;       // anchors
     int32_t status;  // MPG_OK, or the set's error (the kernel writes it to ntop)
+    int32_t id;      // the set's index in the call (its ntop and top slots)
+    int32_t _pad;
 };
+// LDS bytes per anchor of the chaining kernel: f (8) and the used flag (1),
+// plus, when they fit in 64 KB, the anchor (8) and its predecessor (4).
+constexpr int kChainBaseBytes = 9;
+constexpr int kChainStageBytes = 21;
 struct ChainCfg {
     int32_t k, G, binned, max_chains;
     int32_t max_n;   // largest set of the launch (sizes the LDS)
-    int32_t _pad;
+    int32_t stage;   // 1: anchors and predecessors also staged in LDS
     double beta;
 };
 struct ChainRec {    // one extracted chain (scratch)

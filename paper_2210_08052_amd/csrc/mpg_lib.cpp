@@ -1674,8 +1674,16 @@ int chain_sets_dev(hipStream_t st, Workspace& ws, const mpg_chaining_params* cp,
         jobs[t].off = set_off[t];
         jobs[t].n = (int32_t)std::min<int64_t>(n, MPG_MAX_ANCHORS);
         jobs[t].status = n > MPG_MAX_ANCHORS ? MPG_E_RANGE : MPG_OK;
+        jobs[t].id = t;
+        jobs[t]._pad = 0;
         if (jobs[t].status == MPG_OK) max_n = std::max<int32_t>(max_n, (int32_t)n);
     }
+    // largest sets first: a set's work is sequential over its anchors, so the
+    // launch lasts at least as long as its largest set, which should start at
+    // once (stable: equal sizes keep their order)
+    std::stable_sort(jobs.begin(), jobs.end(), [](const ChainSetJob& a, const ChainSetJob& b) {
+        return a.n > b.n;
+    });
     const int64_t total = set_off[nsets];
     const size_t jb = sizeof(ChainSetJob) * (size_t)nsets;
     const size_t rb = sizeof(ChainRec) * (size_t)std::max<int64_t>(total, 1);
@@ -1692,7 +1700,7 @@ int chain_sets_dev(hipStream_t st, Workspace& ws, const mpg_chaining_params* cp,
     cfg.binned = cp->binned;
     cfg.max_chains = cp->max_chains;
     cfg.max_n = max_n;
-    cfg._pad = 0;
+    cfg.stage = kChainStageBytes * (int64_t)max_n + 16 <= 65536 ? 1 : 0;
     cfg.beta = cp->beta;
     ChainRec* recs = (ChainRec*)((uint8_t*)ws.cset.p + ((jb + 15) & ~(size_t)15));
     if (launch_chain(st, (const ChainSetJob*)ws.cset.p, nsets, (const int2*)d_anchors, cfg, d_f,
