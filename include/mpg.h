@@ -199,6 +199,40 @@ int mpg_align_batch_dev(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot
 /* Wait for all work enqueued on the context's stream. */
 int mpg_sync(mpg_ctx *ctx);
 
+/* Bytes of the fixed device scratch array behind mpg_align_batch_dev_noalloc
+ * (one per GPU, reserved when the library's code is loaded on that GPU and
+ * held until the process ends). */
+#define MPG_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * For callers that cannot allocate device memory (code that runs under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mpg_align_batch_dev without any allocation.  Arguments, layouts, ownership
+ * and results are those of mpg_align_batch_dev, and the results are
+ * identical.  Every device buffer of the call beyond the caller's inputs and
+ * outputs (the uploaded plan, row descriptors, strip boundaries, progress
+ * counters, pair states, traceback direction bits) is carved out of the
+ * GPU's fixed scratch array of MPG_NOALLOC_SCRATCH_BYTES; the call allocates
+ * no device or pinned host memory (host planning storage of the context is
+ * reused from call to call), creates no stream, and runs all its kernels on
+ * the context's stream.
+ *  - MPG_E_RANGE: the call needs more scratch than MPG_NOALLOC_SCRATCH_BYTES
+ *    (about 24 bytes per genome row of each score-only pair and 1.2 bytes
+ *    per cell of each traceback pair, plus ~100 bytes per pair), or ops_cap
+ *    is too small; nothing is enqueued then.  Traceback pairs are never split
+ *    into waves here.
+ *  - MPG_E_DEVICE: the scratch array's address could not be obtained when
+ *    the context was created, or a HIP call failed.
+ * The call waits for earlier work on the context's stream before it reuses
+ * the scratch array, and clears the counters and states that must start at
+ * zero with a kernel.  All calls on one GPU share its array: calls that
+ * overlap in time on one GPU (other streams, contexts or threads, or work of
+ * this call still running while another context calls it) race and give
+ * wrong results. */
+int mpg_align_batch_dev_noalloc(mpg_ctx *ctx, const mpg_params *p, const uint8_t *d_prot,
+                                const uint8_t *d_dna, const mpg_seg *segs, int32_t n,
+                                mpg_dev_result *d_out, char *d_ops, int64_t ops_cap);
+
 /*
  * Pseudogene guard (Methods, "Avoiding pseudogenes").  An unspliced copy of a
  * gene pays no intron penalty and can outscore the real, spliced gene; the

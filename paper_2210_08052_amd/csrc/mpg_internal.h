@@ -230,4 +230,10 @@ hipError_t launch_dp16(hipStream_t s, int K, int ncu, const DevParams& P, const 
                        const DpSink& sink);
 int dp16_lds_bytes(int K);
 
+// The fixed scratch array of the allocation-free batch entry point, on the
+// current device: its device address (taken with hipGetSymbolAddress once
+// per device, with that device current, and kept) and its size.
+hipError_t scratch_address(int device, uint8_t** ptr);
+constexpr size_t kScratchBytes = MPG_NOALLOC_SCRATCH_BYTES;
+
 }  // namespace mpg

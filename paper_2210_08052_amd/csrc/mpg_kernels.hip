@@ -28,6 +28,8 @@
 //  * walk: one wavefront per traced pair follows the stored choices back from
 //    the end cell, reading each run of the path in parallel, and writes the
 //    run-length op string.
+#include <mutex>
+
 #include "mpg_dp.h"
 
 namespace mpg {
@@ -546,6 +548,43 @@ hipError_t launch_status(hipStream_t s, const PairJob* jobs, int npairs, const D
     hipLaunchKernelGGL(status_kernel, dim3((npairs + 255) / 256), dim3(256), 0, s, jobs, npairs,
                        sink);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------ fixed scratch array
+// Device memory of the allocation-free batch entry point: every buffer of
+// such a call beyond the caller's inputs and outputs is carved out of this
+// array.  Each GPU holds its own copy from the time the library's code is
+// loaded on it until the process ends.  In host code `scratch` only names
+// the symbol: its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is ever passed
+// to a kernel or a copy.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(int device, uint8_t** ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller sets the device
+        void* a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !a) {
+            (void)hipGetLastError();
+            return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        }
+        g_scratch_ptr[device] = (uint8_t*)a;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace mpg

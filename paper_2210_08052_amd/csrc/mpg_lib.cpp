@@ -632,6 +632,16 @@ struct mpg_ctx {
     hipStream_t stream = nullptr;
     uint64_t tb_budget = 64ull << 30;
     Workspace ws;
+    // allocation-free entry point: the device's fixed scratch array (its
+    // address taken at creation) and the host storage its calls reuse
+    uint8_t* scratch = nullptr;
+    int scratch_rc = MPG_E_DEVICE;
+    struct NoAllocHost {
+        Plan plan;
+        std::vector<uint8_t> stage;
+        std::vector<int64_t> ops_off;
+        std::vector<int32_t> idx;
+    } noalloc;
     // anchor-driven calls in sub-batches: two workspaces, each with the event
     // that marks the end of its last use
     Workspace chain_ws[2];
@@ -734,18 +744,31 @@ struct Prepared {
     int32_t* d_walk = nullptr;
     void* d_pst = nullptr;
     int *d_qhead = nullptr, *d_prog = nullptr;
+    uint8_t *d_desc = nullptr, *d_tb = nullptr;
+    int2* d_bnd = nullptr;
     const uint8_t *d_prot = nullptr, *d_dna = nullptr;
     mpg_dev_result* d_out = nullptr;
     char* d_ops = nullptr;
 };
 
+// The fixed scratch array of the allocation-free entry point, and the
+// context's pageable host storage the plan is staged in for it.
+struct FixedScratch {
+    uint8_t* dev = nullptr;
+    size_t cap = 0;
+    std::vector<uint8_t>* stage = nullptr;
+};
+
 // Host part of a call: plan the pairs idx[0..cnt), size the workspace and
 // upload the plan (asynchronously on st).  Waits for earlier work on st,
-// since the staging buffer and workspace may still be in use.
+// since the staging buffer and workspace may still be in use.  With `fx` the
+// device buffers are carved out of the fixed scratch array instead of the
+// workspace's (MPG_E_RANGE if they do not fit) and the plan is staged in
+// fx's host storage: nothing is allocated on the device or pinned.
 int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d_prot,
             const uint8_t* d_dna, const mpg_seg* segs, const int32_t* idx, int32_t cnt,
             const std::vector<int64_t>& ops_off, mpg_dev_result* d_out, char* d_ops,
-            const RunCfg& cfg, Prepared& X) {
+            const RunCfg& cfg, Prepared& X, const FixedScratch* fx = nullptr) {
     Timer* tm = cfg.tm;
     const auto th0 = std::chrono::steady_clock::now();
     struct HostClock {
@@ -808,20 +831,51 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     const auto tw0 = std::chrono::steady_clock::now();
     if ((rc = wait_workspace(st, cfg)) != MPG_OK) return rc;
     host_clock.t0 += std::chrono::steady_clock::now() - tw0;
-    if ((rc = ws.jobs.ensure(jobs_b + pj_b + pk_b + 256)) != MPG_OK) return rc;
-    if ((rc = ws.row_start.ensure(ps_b + pks_b + 64)) != MPG_OK) return rc;
-    if ((rc = ws.order.ensure(it_b + wk_b + 64)) != MPG_OK) return rc;
-    if ((rc = ws.desc.ensure((size_t)P.desc_bytes + 64)) != MPG_OK) return rc;
-    if ((rc = ws.bnd.ensure(sizeof(int2) * (size_t)P.bnd_elems + 64)) != MPG_OK) return rc;
-    if ((rc = ws.tb.ensure((size_t)P.tb_bytes + 64)) != MPG_OK) return rc;
-    if ((rc = ws.state.ensure((size_t)kPairStateBytes * cnt + sizeof(int) * (P.nprog + 64))) !=
-        MPG_OK)
-        return rc;
+    const size_t b_jobs = jobs_b + pj_b + pk_b + 256, b_rs = ps_b + pks_b + 64,
+                 b_order = it_b + wk_b + 64, b_desc = (size_t)P.desc_bytes + 64,
+                 b_bnd = sizeof(int2) * (size_t)P.bnd_elems + 64,
+                 b_tb = (size_t)P.tb_bytes + 64,
+                 b_state = (size_t)kPairStateBytes * cnt + sizeof(int) * (P.nprog + 64);
     // staging layout: jobs, prepass jobs, packs | row starts, pack row
     // starts | items, walk list
     const size_t plan_b = jobs_b + pj_b + pk_b + ps_b + pks_b + it_b + wk_b + 1024;
-    if ((rc = ws.hplan.ensure(plan_b)) != MPG_OK) return rc;
-    uint8_t* h = (uint8_t*)ws.hplan.p;
+    uint8_t *p_jobs, *p_rs, *p_order, *p_desc, *p_bnd, *p_tb, *p_state;
+    uint8_t* h;
+    if (fx) {
+        size_t off = 0;
+        auto carve = [&](size_t bytes) {
+            uint8_t* q = fx->dev + off;
+            off += (bytes + 255) & ~(size_t)255;
+            return q;
+        };
+        p_jobs = carve(b_jobs);
+        p_rs = carve(b_rs);
+        p_order = carve(b_order);
+        p_desc = carve(b_desc);
+        p_bnd = carve(b_bnd);
+        p_tb = carve(b_tb);
+        p_state = carve(b_state);
+        if (off > fx->cap) return MPG_E_RANGE;
+        if (fx->stage->size() < plan_b) fx->stage->resize(plan_b);
+        h = fx->stage->data();
+    } else {
+        if ((rc = ws.jobs.ensure(b_jobs)) != MPG_OK) return rc;
+        if ((rc = ws.row_start.ensure(b_rs)) != MPG_OK) return rc;
+        if ((rc = ws.order.ensure(b_order)) != MPG_OK) return rc;
+        if ((rc = ws.desc.ensure(b_desc)) != MPG_OK) return rc;
+        if ((rc = ws.bnd.ensure(b_bnd)) != MPG_OK) return rc;
+        if ((rc = ws.tb.ensure(b_tb)) != MPG_OK) return rc;
+        if ((rc = ws.state.ensure(b_state)) != MPG_OK) return rc;
+        if ((rc = ws.hplan.ensure(plan_b)) != MPG_OK) return rc;
+        p_jobs = (uint8_t*)ws.jobs.p;
+        p_rs = (uint8_t*)ws.row_start.p;
+        p_order = (uint8_t*)ws.order.p;
+        p_desc = (uint8_t*)ws.desc.p;
+        p_bnd = (uint8_t*)ws.bnd.p;
+        p_tb = (uint8_t*)ws.tb.p;
+        p_state = (uint8_t*)ws.state.p;
+        h = (uint8_t*)ws.hplan.p;
+    }
     std::memcpy(h, P.jobs.data(), jobs_b);
     if (pj_b) std::memcpy(h + jobs_b, pjobs.data(), pj_b);
     std::memcpy(h + jobs_b + pj_b, P.packs.data(), pk_b);
@@ -831,24 +885,26 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     uint8_t* h3 = h2 + ps_b + pks_b;
     std::memcpy(h3, items.data(), it_b);
     std::memcpy(h3 + it_b, P.walk.data(), wk_b);
-    X.d_jobs = (PairJob*)ws.jobs.p;
-    X.d_pjobs = all_int32 ? (PairJob*)ws.jobs.p : (PairJob*)((uint8_t*)ws.jobs.p + jobs_b);
-    X.d_packs = (PackJob*)((uint8_t*)ws.jobs.p + jobs_b + pj_b);
-    X.d_starts = (int64_t*)ws.row_start.p;
-    X.d_pkstarts = (int64_t*)((uint8_t*)ws.row_start.p + ps_b);
-    X.d_items = (int2*)ws.order.p;
-    X.d_walk = (int32_t*)((uint8_t*)ws.order.p + it_b);
-    uint8_t* d_state = (uint8_t*)ws.state.p;
-    X.d_pst = d_state;
-    X.d_qhead = (int*)(d_state + (size_t)kPairStateBytes * cnt);  // one per launch
+    X.d_jobs = (PairJob*)p_jobs;
+    X.d_pjobs = all_int32 ? (PairJob*)p_jobs : (PairJob*)(p_jobs + jobs_b);
+    X.d_packs = (PackJob*)(p_jobs + jobs_b + pj_b);
+    X.d_starts = (int64_t*)p_rs;
+    X.d_pkstarts = (int64_t*)(p_rs + ps_b);
+    X.d_items = (int2*)p_order;
+    X.d_walk = (int32_t*)(p_order + it_b);
+    X.d_desc = p_desc;
+    X.d_bnd = (int2*)p_bnd;
+    X.d_tb = p_tb;
+    X.d_pst = p_state;
+    X.d_qhead = (int*)(p_state + (size_t)kPairStateBytes * cnt);  // one per launch
     X.d_prog = X.d_qhead + 16;
     hipError_t e = hipSuccess;
     if (jobs_b + pj_b + pk_b)
-        e = hipMemcpyAsync(ws.jobs.p, h, jobs_b + pj_b + pk_b, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(p_jobs, h, jobs_b + pj_b + pk_b, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && ps_b + pks_b)
         e = hipMemcpyAsync(X.d_starts, h2, ps_b + pks_b, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && it_b + wk_b)
-        e = hipMemcpyAsync(ws.order.p, h3, it_b + wk_b, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(p_order, h3, it_b + wk_b, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return MPG_E_DEVICE;
     return MPG_OK;
 }
@@ -871,11 +927,11 @@ int enqueue(hipStream_t st, Workspace& ws, const Prepared& X, const RunCfg& cfg,
         return MPG_E_DEVICE;
     if (tm) tm->begin(st, 0);
     if (launch_prepass(st, X.d_pjobs, X.d_starts, (int)X.npjobs, P.total_rows, X.d_dna,
-                       (uint8_t*)ws.desc.p, DP) != hipSuccess)
+                       X.d_desc, DP) != hipSuccess)
         return MPG_E_DEVICE;
     if (X.npacks &&
         launch_prepass16(st, X.d_jobs, X.d_packs, X.d_pkstarts, (int)X.npacks, P.pack_rows,
-                         X.d_dna, (uint8_t*)ws.desc.p, X.d_prog, DP) != hipSuccess)
+                         X.d_dna, X.d_desc, X.d_prog, DP) != hipSuccess)
         return MPG_E_DEVICE;
     if (tm) tm->end(st, 0);
     if (tm) tm->begin(st, 1);
@@ -887,11 +943,11 @@ int enqueue(hipStream_t st, Workspace& ws, const Prepared& X, const RunCfg& cfg,
         if (G.i16)
             return launch_dp16(s2, G.K, cfg.ncu, DG, X.d_jobs, X.d_packs, X.d_items + X.goff[g],
                                nit, X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot,
-                               (const uint8_t*)ws.desc.p, (int2*)ws.bnd.p, sink);
+                               X.d_desc, X.d_bnd, sink);
         return launch_dp(s2, G.K, G.tb, cfg.pro, cfg.ncu, DG, X.d_jobs, X.d_items + X.goff[g],
                          nit,
-                         X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot, (const uint8_t*)ws.desc.p,
-                         (int2*)ws.bnd.p, (uint8_t*)ws.tb.p, sink);
+                         X.d_qhead + g, X.d_pst, X.d_prog, X.d_prot, X.d_desc, X.d_bnd,
+                         X.d_tb, sink);
     };
     if (ngroups == 1 || (ngroups > 1 && !fork)) {
         for (size_t g = 0; g < ngroups; ++g)
@@ -918,7 +974,7 @@ int enqueue(hipStream_t st, Workspace& ws, const Prepared& X, const RunCfg& cfg,
     if (tm) tm->end(st, 1);
     if (!P.walk.empty() && !cfg.serve) {
         if (tm) tm->begin(st, 2);
-        if (launch_walk(st, X.d_jobs, X.d_walk, (int)P.walk.size(), (const uint8_t*)ws.tb.p,
+        if (launch_walk(st, X.d_jobs, X.d_walk, (int)P.walk.size(), X.d_tb,
                         X.d_out, X.d_ops) != hipSuccess)
             return MPG_E_DEVICE;
         if (tm) tm->end(st, 2);
@@ -1014,7 +1070,9 @@ const char* mpg_strerror(int status) {
     switch (status) {
         case MPG_OK: return "ok";
         case MPG_E_INVAL: return "invalid argument";
-        case MPG_E_RANGE: return "length or score bound out of range";
+        case MPG_E_RANGE:
+            return "out of range: a length, the score bound, the traceback budget, the ops buffer "
+                   "or the fixed scratch size";
         case MPG_E_NOMEM: return "out of memory";
         case MPG_E_AGAIN: return "queue full, try again";
         case MPG_E_DEVICE: return "device error";
@@ -1092,6 +1150,9 @@ int mpg_ctx_create(mpg_ctx** out, int device, uint64_t tb_budget_bytes, uint32_t
     }
     c->stream = c->own_stream;
     c->stats.tb_budget = c->tb_budget;
+    // the fixed scratch array of the allocation-free entry point, with this
+    // device current (its address is taken once per device and kept)
+    c->scratch_rc = scratch_address(device, &c->scratch) == hipSuccess ? MPG_OK : MPG_E_DEVICE;
     *out = c;
     return MPG_OK;
 }
@@ -1145,6 +1206,45 @@ int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot
     cfg.ncu = g_num_cu;
     cfg.tune = &ctx->tune;
     return run_dev_waves(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, n, d_out, d_ops, cfg);
+}
+
+int mpg_align_batch_dev_noalloc(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot,
+                                const uint8_t* d_dna, const mpg_seg* segs, int32_t n,
+                                mpg_dev_result* d_out, char* d_ops, int64_t ops_cap) {
+    if (!ctx || !p || (n > 0 && (!segs || !d_out))) return MPG_E_INVAL;
+    if (n < 0) return MPG_E_INVAL;
+    int rc = params_check_impl(p);
+    if (rc != MPG_OK) return rc;
+    if (n == 0) return MPG_OK;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    if (ctx->scratch_rc != MPG_OK || !ctx->scratch) return MPG_E_DEVICE;
+    mpg_ctx::NoAllocHost& na = ctx->noalloc;
+    // op-string slots in input order, as mpg_align_batch_dev lays them out
+    na.ops_off.resize(n);
+    na.idx.resize(n);
+    int64_t need = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        na.ops_off[k] = need;
+        na.idx[k] = k;
+        need += seg_tb(segs[k], p) ? 2 * ((int64_t)std::max(0, segs[k].dlen) +
+                                          std::max(0, segs[k].plen)) + 1
+                                   : 1;
+    }
+    if (need > 0 && (!d_ops || ops_cap < need)) return MPG_E_RANGE;
+    hipSetDevice(ctx->device);
+    RunCfg cfg;
+    cfg.tb_budget = ctx->tb_budget;
+    cfg.ncu = g_num_cu;
+    cfg.tune = &ctx->tune;
+    Prepared X;
+    std::swap(X.P, na.plan);  // plan in the context's storage, handed back below
+    const FixedScratch fx{ctx->scratch, kScratchBytes, &na.stage};
+    rc = prepare(ctx->stream, ctx->ws, p, d_prot, d_dna, segs, na.idx.data(), n, na.ops_off,
+                 d_out, d_ops, cfg, X, &fx);
+    // every kernel variant on the context's stream, one after another
+    if (rc == MPG_OK) rc = enqueue(ctx->stream, ctx->ws, X, cfg, false);
+    std::swap(X.P, na.plan);
+    return rc;
 }
 
 }  // extern "C"

@@ -21,6 +21,7 @@ MPG_E_AGAIN, MPG_E_DEVICE, MPG_E_NOALN, MPG_E_CANCELLED = -4, -5, -6, -7
 MPG_LOCAL, MPG_EXTEND, MPG_GLOBAL, MPG_EXTEND_LEFT = 0, 1, 2, 3
 MPG_NO_INTRON, MPG_NO_FRAMESHIFT, MPG_WANT_TB, MPG_ALLOW_I16 = 1, 2, 4, 8
 MPG_MAX_DNA, MPG_MAX_PROT = 1040000, 32000
+MPG_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class mpg_params(ctypes.Structure):
@@ -128,7 +129,8 @@ EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_de
            "mpg_plan_destroy", "mpg_rescore_spliced", "mpg_align_chains",
            "mpg_chain_ops_capacity", "mpg_align_chains_dev", "mpg_align_profiles",
            "mpg_profile_bytes", "mpg_align_profiles_dev", "mpg_chaining_params_default",
-           "mpg_chain_anchors", "mpg_chain_anchors_dev", "mpg_rescore_spliced_dev"]
+           "mpg_chain_anchors", "mpg_chain_anchors_dev", "mpg_rescore_spliced_dev",
+           "mpg_align_batch_dev_noalloc"]
 
 _lib = None
 
@@ -163,6 +165,7 @@ def lib():
         L.mpg_align_batch_dev.argtypes = [ctypes.c_void_p, P(mpg_params), ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.mpg_align_batch_dev_noalloc.argtypes = L.mpg_align_batch_dev.argtypes
         L.mpg_sync.argtypes = [ctypes.c_void_p]
         L.mpg_submit.argtypes = [ctypes.c_void_p, P(mpg_params), P(mpg_pair),
                                  P(ctypes.c_uint64)]
@@ -457,6 +460,16 @@ class Context:
                                         ctypes.c_void_p(d_dna), segs.ctypes.data, len(segs),
                                         ctypes.c_void_p(d_out), ctypes.c_void_p(d_ops),
                                         int(ops_cap)), "mpg_align_batch_dev")
+
+    def align_batch_dev_noalloc(self, p: mpg_params, d_prot, d_dna, segs: np.ndarray, d_out,
+                                d_ops, ops_cap: int) -> int:
+        """As align_batch_dev through the allocation-free entry point; returns
+        its status (MPG_E_RANGE when the call exceeds the fixed scratch)."""
+        segs = np.ascontiguousarray(segs, dtype=SEG_DTYPE)
+        return lib().mpg_align_batch_dev_noalloc(self.ptr, ctypes.byref(p), ctypes.c_void_p(d_prot),
+                                                 ctypes.c_void_p(d_dna), segs.ctypes.data,
+                                                 len(segs), ctypes.c_void_p(d_out),
+                                                 ctypes.c_void_p(d_ops), int(ops_cap))
 
     def sync(self):
         check(lib().mpg_sync(self.ptr), "mpg_sync")

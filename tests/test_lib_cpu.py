@@ -125,6 +125,9 @@ def test_null_arguments_are_rejected():
     assert L.mpg_ctx_create(None, 0, 0, 0) == mpg.MPG_E_INVAL
     assert L.mpg_poll(None, None, 0, 0) == mpg.MPG_E_INVAL
     assert L.mpg_cancel(None, 1) == mpg.MPG_E_INVAL
+    p = mpg.params()
+    assert L.mpg_align_batch_dev_noalloc(None, ctypes.byref(p), None, None, None, 0, None, None,
+                                         0) == mpg.MPG_E_INVAL
 
 
 def test_chaining_defaults_are_the_papers():
