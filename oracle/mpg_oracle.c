@@ -49,7 +49,7 @@
  * op-string format, nor the default q/e/f/r and matrix, nor how the DP is
  * bounded at its start and end.  The optimal score of every mode is pinned
  * (brute force over the segment grammar, textbook Gotoh reduction, the worked
- * example of the "Spliced alignment" figure); which of several optimal paths
+ * alignment of "Residue alignment with dynamic programming"); which of several optimal paths
  * and end cells is reported, and how it is spelled, follows the choices above
  * and is checked only for validity (rescoring) and against itself.
  */

@@ -1,6 +1,7 @@
 // Lane-packed int16 variant of the DP for LOCAL score-only pairs (Eq. (full)
 // of Li 2022, "DP for protein-to-genome alignment"; the paper's own CPU
-// kernel also scores in 16-bit lanes, "Implementation details").
+// kernel also scores in 16-bit lanes, as the closing paragraph of that
+// subsection states).
 //
 // Two pairs share one wavefront: every 32-bit lane register holds pair A's
 // value in its low half and pair B's in its high half, and one packed
@@ -11,8 +12,9 @@
 // eligible pairs of similar size.  Saturation keeps -infinity fixed at
 // -32768; the host admits a pair only when every reachable value provably
 // fits: in LOCAL mode H >= 0, so the smallest value is bounded by the largest
-// penalty sum, and the largest by the sum over the protein of each residue's
-// best substitution score.
+// penalty sum (at most 8,192 is admitted), and the largest by the protein
+// length times the largest matrix entry (m * max(mat) <= 32,511 is
+// admitted): each residue adds at most one substitution score to a path.
 #include "mpg_dp.h"
 
 namespace mpg {

@@ -334,18 +334,18 @@ def long_tail(n_long: int = 200, n_short: int = 2000, seed: int = 4) -> list:
     return out
 
 
-def serving_jobs(n_jobs: int = 200000, rate_per_s: float = 1000.0, seed: int = 5,
-                 p_long_mix: float = 0.1, p_tb: float = 0.5, progress=None):
-    """Poisson job stream: each job is a batch-distribution pair w.p. 0.9, else
-    a long-tail-mixture pair (long w.p. 200/2200); traceback w.p. 0.5.
-    Returns (pairs, arrival_times_s).  The arrival times scale exactly as
-    1/rate_per_s (the same draws for every rate).  ``progress(k)`` is called
-    every 10,000 jobs if given."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    jobs = []
-    for k in range(n_jobs):
-        if progress is not None and k and k % 10000 == 0:
-            progress(k)
+SERVING_CHUNK = 1000  # jobs per independently seeded chunk of the serving stream
+
+
+def _serving_chunk(args) -> list:
+    """Jobs [c * SERVING_CHUNK, ...) of the serving stream: chunk c draws from
+    its own generator PCG64(SeedSequence([seed, 1, c])), so the stream is the
+    same whichever process draws which chunk.  The serving jobs keep no
+    ground truth (only the letters and the traceback flag are used)."""
+    seed, c, count, p_long_mix, p_tb = args
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1, c])))
+    out = []
+    for _ in range(count):
         if rng.random() >= p_long_mix:
             p = None
             while p is None:
@@ -358,8 +358,44 @@ def serving_jobs(n_jobs: int = 200000, rate_per_s: float = 1000.0, seed: int = 5
             while p is None:
                 p = _short_pair(rng, int(rng.integers(100, 301)))
         p.want_tb = bool(rng.random() < p_tb)
-        jobs.append(p)
-    gaps = rng.exponential(1.0 / rate_per_s, size=n_jobs)
+        p.truth = {}
+        out.append(p)
+    return out
+
+
+def serving_jobs(n_jobs: int = 200000, rate_per_s: float = 1000.0, seed: int = 5,
+                 p_long_mix: float = 0.1, p_tb: float = 0.5, progress=None, workers: int = 1):
+    """Poisson job stream: each job is a batch-distribution pair w.p. 0.9, else
+    a long-tail-mixture pair (long w.p. 200/2200); traceback w.p. 0.5.
+    Returns (pairs, arrival_times_s).  Jobs come in chunks of SERVING_CHUNK,
+    each drawn from its own seeded generator (so the first k jobs of a longer
+    stream are the stream of k jobs, and `workers` processes draw the chunks
+    in parallel with the same result); the exponential inter-arrival gaps
+    come from PCG64(SeedSequence([seed, 2])) and scale exactly as 1/rate_per_s.
+    ``progress(k)`` is called every 10,000 jobs if given."""
+    tasks = [(seed, c, min(SERVING_CHUNK, n_jobs - c * SERVING_CHUNK), p_long_mix, p_tb)
+             for c in range((n_jobs + SERVING_CHUNK - 1) // SERVING_CHUNK)]
+    jobs = []
+
+    def take(part):
+        before = len(jobs)
+        jobs.extend(part)
+        if progress is not None and len(jobs) // 10000 > before // 10000:
+            progress(len(jobs) // 10000 * 10000)
+
+    if workers > 1 and len(tasks) > 1:
+        import multiprocessing
+        from concurrent.futures import ProcessPoolExecutor
+        # fresh interpreters: the parent may already hold a GPU runtime
+        ctx = multiprocessing.get_context("spawn")
+        with ProcessPoolExecutor(max_workers=min(workers, len(tasks)), mp_context=ctx) as ex:
+            for part in ex.map(_serving_chunk, tasks):
+                take(part)
+    else:
+        for t in tasks:
+            take(_serving_chunk(t))
+    grng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 2])))
+    gaps = grng.exponential(1.0 / rate_per_s, size=n_jobs)
     return jobs, np.cumsum(gaps)
 
 
