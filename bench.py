@@ -1,23 +1,26 @@
 """Benchmark of the spliced protein-to-genome DP on one MI355X.
 
-Default workload: the batch of 10,000 planted-gene pairs (protein lengths
-log-normal around 400 aa, 1.2x-padded regions up to 40 kb, score-only, LOCAL,
-int32), inputs resident in HBM before the timed region.  One step = one
-``mpg_align_batch_dev`` call over the whole batch (plan upload, prepass, DP,
-end-cell reduction), synchronised.
+Default run (``--config all``): every workload of the metric in one process.
 
-Printed: one JSON line with GCUPS (sum of n*m over the batch / step time), the
-roofline of the DP kernel (integer VALU bound; device time from hipEvents the
-library records on its stream around the DP launches) and the CPU oracle's
-throughput on a bounded sample of the same batch (``cpu_baseline``).
+* Headline (``value``, ``roofline``, ``cpu_baseline``): the batch of 10,000
+  planted-gene pairs (protein lengths log-normal around 400 aa, 1.2x-padded
+  regions up to 40 kb, score-only, LOCAL, int32), inputs resident in HBM
+  before the timed region.  One step = one ``mpg_align_batch_dev`` call over
+  the whole batch (plan upload, prepass, DP, end-cell reduction),
+  synchronised.  ``cpu_baseline`` times the oracle on a bounded sample of the
+  same pairs and compares its results with the GPU's (``mismatches``).
+* ``legs.traceback``: the same 10,000 pairs with full traceback.
+* ``legs.longtail``: 200 pairs of 3-8k aa x 100-300 kb plus 2,000 short ones,
+  traceback, in one call under a 128 GiB direction-bit budget.
+* ``legs.serving``: 200,000 jobs submitted one by one at Poisson arrival
+  times through ``mpg_submit``/``mpg_poll``: p50/p99 latency from the
+  scheduled arrival to the result (overall and per class), served GCUPS, the
+  same jobs run one pair per launch, and every served result compared with a
+  batched run of the same jobs.
 
-Other workloads (``--config``): ``single`` (one 3,000-nt pair with
-traceback), ``traceback`` (the same 10,000 pairs with traceback),
-``longtail`` (200 long + 2,000 short pairs with traceback) and ``serving``
-(200,000 jobs submitted one by one at Poisson arrival times through
-``mpg_submit``/``mpg_poll``; reports p50/p99 latency from the scheduled
-arrival to the result, served GCUPS, the same jobs run one pair per launch,
-and a batched re-run of a sample of jobs compared with the served results).
+Each workload can also run alone (``--config``): ``batch``, ``batch16``,
+``traceback``, ``single``, ``longtail``, ``serving``, and the next rows'
+``profile``, ``chain``, ``chaining``, ``rescore``.
 """
 from __future__ import annotations
 
@@ -101,20 +104,40 @@ def recorded_traffic(config: str):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(pairs, tb: bool, budget_s: float):
+def _res_key(r, tb):
+    """Comparable fields of a result: status, score and end cell, plus begin
+    cell and op string with traceback (a dict from the GPU, or an oracle
+    Result)."""
+    if isinstance(r, dict):
+        st, sc, gb, ge, pb, pe, ops = (r["status"], r["score"], r["g_beg"], r["g_end"],
+                                       r["p_beg"], r["p_end"], r.get("ops"))
+    else:
+        st, sc, gb, ge, pb, pe, ops = r.status, r.score, r.g_beg, r.g_end, r.p_beg, r.p_end, r.ops
+    if st != 0:
+        return (st,)
+    return (st, sc, ge, pe, gb, pb, ops) if tb else (st, sc, ge, pe)
+
+
+def cpu_baseline(pairs, tb: bool, budget_s: float, gpu=None):
     """The oracle, as it stands, on all host cores, on a bounded sample: pairs
     in a seeded random order, fed to the pool in chunks until the wall time
-    reaches the budget."""
+    reaches the budget.  With `gpu` (the GPU's result for every pair, from the
+    timed run) each sampled pair's oracle result is compared with the GPU's:
+    status, score and end cell, and with traceback the begin cell and op
+    string; `mismatches` counts the pairs that differ."""
     import oracle
     threads = len(os.sched_getaffinity(0))
     rng = np.random.default_rng(12345)
     order = rng.permutation(len(pairs))
     chunk = threads * 4
-    k, cells = 0, 0
+    k, cells, mism = 0, 0, 0
     t0 = time.perf_counter()
     while k < len(order) and time.perf_counter() - t0 < budget_s:
-        part = [pairs[i] for i in order[k:k + chunk]]
-        oracle.align_many([(p.prot, p.dna) for p in part], None, tb, threads)
+        idx = order[k:k + chunk]
+        part = [pairs[i] for i in idx]
+        res = oracle.align_many([(p.prot, p.dna) for p in part], None, tb, threads)
+        if gpu is not None:
+            mism += sum(1 for i, r in zip(idx, res) if _res_key(gpu[i], tb) != _res_key(r, tb))
         cells += sum(len(p.prot) * len(p.dna) for p in part)
         k += len(part)
     dt = time.perf_counter() - t0
@@ -126,10 +149,14 @@ def cpu_baseline(pairs, tb: bool, budget_s: float):
                 break
     except OSError:
         pass
-    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d of %d pairs (seeded random order), %.3g cells, %.1f s wall, %s" % (
-                k, len(pairs), cells, dt, model)}
+    out = {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
+           "kind": "oracle",
+           "sample": "%d of %d pairs (seeded random order), %.3g cells, %.1f s wall, %s" % (
+               k, len(pairs), cells, dt, model)}
+    if gpu is not None:
+        out["checked"] = int(k)
+        out["mismatches"] = int(mism)
+    return out
 
 
 def cpu_baseline_chains(chains, budget_s: float):
@@ -656,7 +683,8 @@ def bench_serving(args):
     n = args.jobs
     t_gen = time.time()
     jobs, arr1 = W.serving_jobs(n, rate_per_s=1.0, seed=5,
-                                progress=lambda k: log("generated %d jobs" % k))
+                                progress=lambda k: log("generated %d jobs" % k),
+                                workers=min(16, len(os.sched_getaffinity(0))))
     log("serving workload: %d jobs generated in %.1f s" % (n, time.time() - t_gen))
     cells = np.array([len(q.prot) * len(q.dna) for q in jobs], dtype=np.float64)
     is_long = np.array([len(q.dna) > LONG_REGION for q in jobs])
@@ -762,8 +790,9 @@ def bench_serving(args):
         "served_vs_batched_mismatches": {"checked": int(len(sample)), "mismatches": mism},
         "one_pair_per_launch": baseline,
         "serving_stats": st,
+        "gpu_max_hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def main():
@@ -771,7 +800,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="batch")
+    ap.add_argument("--config", default="all",
+                    help="all (default: batch as the headline, then traceback, longtail and "
+                         "serving legs), batch, batch16, traceback, single, longtail, serving, "
+                         "profile, chain, chaining, rescore")
     ap.add_argument("--tb-budget-gib", type=float, default=None,
                     help="traceback budget of the context in GiB (default: 128 for longtail, "
                          "whose direction bits total ~250 GB, so it runs in two waves; else "
@@ -818,20 +850,79 @@ def main():
         bench_rescore(args)
         return
 
+    if args.config in ("serving", "all"):
+        # the serving scheduler runs several streams at once; give them
+        # hardware queues of their own (read when the HIP runtime starts,
+        # which is after this point: torch is imported later).  The record
+        # states the value in effect.
+        os.environ["GPU_MAX_HW_QUEUES"] = "16"
     if args.config == "serving":
-        # the serving scheduler runs seven streams (three short, four long
-        # lanes); give them hardware queues of their own (read when the HIP
-        # runtime starts, which is after this point: torch is imported later)
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
-        bench_serving(args)
+        line = bench_serving(args)
+        if line is not None:
+            print(json.dumps(line), flush=True)
         return
 
     import torch
     from paper_2210_08052_amd import mpg
 
+    if args.config != "all":
+        leg = run_batch_leg(mpg, torch, args.config, args.steps, args.warmup, args.cpu_budget,
+                            args.tb_budget_gib)
+        print(json.dumps(leg), flush=True)
+        return
+
+    # every workload of the metric: the 10,000-pair batch (the headline), the
+    # same pairs with traceback, the long-tail batch and the serving stream
+    t_all = time.time()
+    line = run_batch_leg(mpg, torch, "batch", args.steps, args.warmup, args.cpu_budget, None)
+    legs = {}
+    for name, steps, budget in (("traceback", min(args.steps, 10), None),
+                                ("longtail", min(args.steps, 3), None)):
+        leg = run_batch_leg(mpg, torch, name, steps, 1, 0.0, budget, e2e=False)
+        legs[name] = leg_summary(leg)
+        log("%s leg: %s" % (name, json.dumps(legs[name])))
+    args.baseline_budget = min(args.baseline_budget, 10.0)
+    srv = bench_serving(args)
+    legs["serving"] = srv
+    line["legs"] = legs
+    line["wall_s_all_legs"] = round(time.time() - t_all, 1)
+    print(json.dumps(line), flush=True)
+
+
+def leg_summary(leg):
+    """The fields of a batch leg that the combined line carries."""
+    r = leg["roofline"]
+    return {"workload": leg["config"]["workload"], "pairs": leg["config"]["pairs"],
+            "cells": leg["config"]["cells"], "steps": leg["steps"], "warmup": leg["warmup"],
+            "ms_per_step": leg["ms_per_step"], "gcups": leg["value"],
+            "kernel_gcups": r["kernel_gcups"], "dp_ms_per_step": r["dp_ms_per_step"],
+            "roofline_frac": r["frac"], "ops_per_cell": r["ops_per_cell"],
+            "traffic": r["traffic"], "autotune": leg["autotune"],
+            "tb_budget_gib": leg["config"].get("tb_budget_gib")}
+
+
+def dev_results(mpg, d_out, d_ops, n, tb):
+    """Result dicts of a device-resident call (records and op strings)."""
+    out = np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=mpg.DEV_RESULT_DTYPE)[:n]
+    ops = d_ops.cpu().numpy().tobytes() if tb else b""
+    res = []
+    for k in range(n):
+        r = {f: int(out[f][k]) for f in ("status", "score", "g_beg", "g_end", "p_beg", "p_end")}
+        r["ops"] = None
+        if tb and r["status"] == 0:
+            o0, ln = int(out["ops_off"][k]), int(out["ops_len"][k])
+            r["ops"] = ops[o0:o0 + ln].decode()
+        res.append(r)
+    return res
+
+
+def run_batch_leg(mpg, torch, config, steps, warmup, cpu_budget, tb_budget_gib, e2e=True):
+    """One batch workload: sequences resident in HBM, the strip width tuned on
+    the workload itself, `warmup` untimed and `steps` timed calls of
+    mpg_align_batch_dev, each synchronised.  Returns its JSON line."""
     t0 = time.time()
-    pairs, tb, desc = build_workload(args.config)
-    log("workload %s: %d pairs, generated in %.1f s" % (args.config, len(pairs), time.time() - t0))
+    pairs, tb, desc = build_workload(config)
+    log("workload %s: %d pairs, generated in %.1f s" % (config, len(pairs), time.time() - t0))
     cells = int(sum(len(p.prot) * len(p.dna) for p in pairs))
     pb, db, segs = mpg.pack_pairs([(p.prot, p.dna, tb) for p in pairs])
 
@@ -842,13 +933,13 @@ def main():
     d_ops = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
     d_out = torch.empty(len(pairs) * mpg.DEV_RESULT_DTYPE.itemsize, dtype=torch.uint8,
                         device=dev)
-    budget_gib = args.tb_budget_gib
+    budget_gib = tb_budget_gib
     if budget_gib is None:
-        budget_gib = 128.0 if args.config == "longtail" else 0.0
+        budget_gib = 128.0 if config == "longtail" else 0.0
     ctx = mpg.Context(0, tb_budget_bytes=int(budget_gib * (1 << 30)))
     stream = torch.cuda.Stream(device=dev)
     ctx.set_stream(stream.cuda_stream)
-    i16 = args.config == "batch16"
+    i16 = config == "batch16"
     p = mpg.params(flags=mpg.MPG_ALLOW_I16) if i16 else mpg.params()
     # kernel width from timed runs of this very workload
     tuning = ctx.autotune(p, d_prot.data_ptr(), d_dna.data_ptr(), segs)
@@ -858,7 +949,7 @@ def main():
         ctx.align_batch_dev(p, d_prot.data_ptr(), d_dna.data_ptr(), segs, d_out.data_ptr(),
                             d_ops.data_ptr(), cap)
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         step()
         ctx.sync()
         log("warmup %d done" % w)
@@ -871,25 +962,25 @@ def main():
     torch.cuda.synchronize()
     ctx.sync()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         step()
         ctx.sync()
         log("step %d done" % k)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tim = ctx.timing(reset=True)
-    ms_step = dt * 1e3 / args.steps
-    gcups = cells / (dt / args.steps) / 1e9
-    dp_ms = tim["dp_ms"] / max(1, args.steps)
+    ms_step = dt * 1e3 / steps
+    gcups = cells / (dt / steps) / 1e9
+    dp_ms = tim["dp_ms"] / max(1, steps)
     if i16:
         # 27 packed int16 operations advance two cells: 27 int16 lane-ops per
         # cell against twice the int32 lane rate
         ops = 27
         peak = 2 * PEAK_INT_OPS / 1e12
         runit = "Tops/s (int16 lane-ops)"
-        if tim["i16_pairs"] != len(pairs) * args.steps:
+        if tim["i16_pairs"] != len(pairs) * steps:
             raise SystemExit("int16 kernel ran %d pairs, expected %d" % (
-                tim["i16_pairs"], len(pairs) * args.steps))
+                tim["i16_pairs"], len(pairs) * steps))
     else:
         ops = OPS_PER_CELL["traceback" if tb else "score"]
         peak = PEAK_INT_OPS / 1e12
@@ -898,21 +989,28 @@ def main():
     kernel_gcups = cells / (dp_ms * 1e-3) / 1e9
     log("step %.3f ms, GCUPS %.1f; DP kernels %.3f ms/step (%.1f GCUPS), prepass %.3f ms, "
         "walk %.3f ms, host %.3f ms" % (ms_step, gcups, dp_ms, kernel_gcups,
-                                        tim["prepass_ms"] / args.steps,
-                                        tim["walk_ms"] / args.steps,
-                                        tim["host_ms"] / args.steps))
+                                        tim["prepass_ms"] / steps, tim["walk_ms"] / steps,
+                                        tim["host_ms"] / steps))
+    # the last timed step's results, for the oracle comparison
+    gpu_res = dev_results(mpg, d_out, d_ops, len(pairs), tb) if cpu_budget > 0 else None
 
-    e2e = end_to_end_ms(mpg, ctx, pairs, tb, p)
-    log("end to end over host buffers: %.3f ms (%.1f GCUPS)" % (e2e, cells / (e2e * 1e-3) / 1e9))
+    e2e_ms = None
+    if e2e:
+        e2e_ms = end_to_end_ms(mpg, ctx, pairs, tb, p)
+        log("end to end over host buffers: %.3f ms (%.1f GCUPS)" % (
+            e2e_ms, cells / (e2e_ms * 1e-3) / 1e9))
+    ctx.close()
+    del d_prot, d_dna, d_ops, d_out
+    torch.cuda.empty_cache()
 
     cpu = None
-    if args.cpu_budget > 0:
-        cpu = cpu_baseline(pairs, tb, args.cpu_budget)
+    if cpu_budget > 0:
+        cpu = cpu_baseline(pairs, tb, cpu_budget, gpu=gpu_res)
         log("cpu baseline: %s" % json.dumps(cpu))
 
     line = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "steps": steps, "warmup": warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int16" if i16 else "int32",
         "data": "synthetic (seeded planted genes)",
@@ -920,17 +1018,20 @@ def main():
                    "traceback": tb, "mode": "LOCAL"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                      "unit": runit, "frac": round(achieved / peak, 4),
-                     "traffic": recorded_traffic(args.config), "kernel_gcups": round(kernel_gcups, 2),
+                     "traffic": recorded_traffic(config), "kernel_gcups": round(kernel_gcups, 2),
                      "ops_per_cell": ops,
                      "dp_ms_per_step": round(dp_ms, 3)},
         "cpu_baseline": cpu,
         "autotune": tuning,
-        "end_to_end": {"ms": round(e2e, 3), "gcups": round(cells / (e2e * 1e-3) / 1e9, 2),
-                       "what": "one mpg_align_batch over host buffers (sequences in, "
-                               "records and op strings out over PCIe)"},
     }
-    print(json.dumps(line), flush=True)
-    ctx.close()
+    if budget_gib:
+        line["config"]["tb_budget_gib"] = budget_gib
+    if e2e_ms is not None:
+        line["end_to_end"] = {"ms": round(e2e_ms, 3),
+                              "gcups": round(cells / (e2e_ms * 1e-3) / 1e9, 2),
+                              "what": "one mpg_align_batch over host buffers (sequences in, "
+                                      "records and op strings out over PCIe)"}
+    return line
 
 
 if __name__ == "__main__":

@@ -89,26 +89,6 @@ def test_single_planted_pair(ctx):
     assert r["g_beg"] <= ex[0][0] + 30 and r["g_end"] >= ex[-1][1] - 30
 
 
-def test_batch_full_size_sampled(ctx):
-    """The 10,000-pair planted batch at full size in one call (score-only and
-    traceback); a seeded sample is checked against the oracle, and scores,
-    end cells and traceback runs agree for every pair."""
-    pairs = W.batch_pairs(10000, seed=2)
-    g, o = scorings(0, 0)
-    so = ctx.align_batch([(p.prot, p.dna, False) for p in pairs], g)
-    tb = ctx.align_batch([(p.prot, p.dna, True) for p in pairs], g)
-    for a, b in zip(so, tb):
-        assert a["status"] == b["status"] == 0
-        assert (a["score"], a["g_end"], a["p_end"]) == (b["score"], b["g_end"], b["p_end"])
-    rng = np.random.default_rng(7)
-    idx = rng.choice(len(pairs), size=40, replace=False)
-    sample = [(pairs[k].prot, pairs[k].dna) for k in idx]
-    exp_tb = oracle.align_many(sample, o, want_tb=True)
-    for k, e in zip(idx, exp_tb):
-        assert key_gpu(tb[k], True) == key_orc(e, True), int(k)
-        assert key_gpu(so[k], False) == key_orc(e, False), int(k)
-
-
 def test_long_pairs_pipelined(ctx):
     """Long proteins against long regions: their strips run as a pipeline
     over many wavefronts; a few moderately long planted pairs are checked
