@@ -578,7 +578,7 @@ def bench_rescore(args):
 # (one mpg_align_batch call over the first 20,000 jobs of the same stream,
 # measured by ``--config serving --calibrate``), rounded to two significant
 # digits and frozen here.
-SERVING_RATE = 31000.0  # 0.7 x 43,942 jobs/s measured on MI355X
+SERVING_RATE = 24000.0  # 0.7 x 34,233 jobs/s: batched capacity of the first 20,000 jobs on MI355X
 LONG_REGION = 50000  # regions above this length come from the long-tail mixture
 SERVING_TB_BUDGET = 96 << 30  # device bytes for traceback direction bits while serving
 

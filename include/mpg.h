@@ -136,6 +136,32 @@ void mpg_ctx_destroy(mpg_ctx *ctx);
  * the context's own stream).  The stream stays owned by the caller. */
 int mpg_set_stream(mpg_ctx *ctx, void *hip_stream);
 
+/*
+ * Take the device memory of every workspace of this context (plans, row
+ * descriptors, strip boundaries, direction bits, staging of sequences and
+ * results, serving batches) from the caller's allocator instead of
+ * hipMalloc/hipFree -- for example PyTorch's caching allocator, so that the
+ * library and the caller share one pool of device memory.  The computation
+ * itself stays in the library's kernels.
+ *  - alloc(bytes, user) returns a block of at least `bytes` bytes of device
+ *    memory on the context's device, 256-byte aligned, or NULL (the call
+ *    then fails with MPG_E_NOMEM; a misaligned block is given back and the
+ *    call fails with MPG_E_INVAL);
+ *  - release(ptr, user) takes back a block that alloc returned.  The library
+ *    calls it only when none of its own work that uses the block can still
+ *    be running: batch calls wait for the context's stream before a
+ *    workspace grows, serving parks outgrown blocks until no serving batch
+ *    is on the device, and the rest are released by mpg_ctx_destroy (or
+ *    mpg_plan_destroy) after the device work has finished.
+ * Both callbacks NULL: back to hipMalloc/hipFree for new blocks.  A block is
+ * always given back through the allocator that made it, so earlier callbacks
+ * and their `user` must stay valid until the context (and every plan made
+ * from it) is destroyed.  The callbacks may be called from the library's
+ * serving threads.  MPG_E_INVAL: ctx NULL, exactly one callback NULL, or the
+ * context has already served a job (mpg_submit): set the allocator before. */
+int mpg_set_allocator(mpg_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                      void (*release)(void *ptr, void *user), void *user);
+
 /* Fill *p with the defaults: q=11, e=1, f=23, r=29, BLOSUM62, the standard
  * genetic code, the final splice model of "Splice models", LOCAL mode. */
 void mpg_params_default(mpg_params *p);
@@ -494,9 +520,13 @@ int mpg_chain_anchors_dev(mpg_ctx *ctx, const mpg_chaining_params *cp, const int
  * start while earlier ones still run.  Within a batch every pair completes on
  * its own: the wavefront that finishes a pair's last strip walks its
  * traceback and publishes the result to host-mapped memory, and the result
- * is in mpg_poll at once, while the rest of the batch still runs.  The seven
- * streams run concurrently only with as many hardware queues: start the
- * process with GPU_MAX_HW_QUEUES of at least 8.
+ * is in mpg_poll at once, while the rest of the batch still runs.  Streams
+ * run concurrently only with hardware queues of their own: the context keeps
+ * no more serving streams than the process's GPU_MAX_HW_QUEUES (HIP's
+ * default is 4: three short lanes and one long lane; start the process with
+ * GPU_MAX_HW_QUEUES of at least 8 for all seven), reported in mpg_stats.
+ * A batch that fails (device memory, a HIP call, a bounded wait that gives
+ * up) completes each of its jobs with that status; none is lost.
  */
 int mpg_submit(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pair, uint64_t *job_id);
 
@@ -517,6 +547,8 @@ typedef struct {
     uint64_t queue_depth;   /* jobs submitted but not yet admitted */
     uint64_t in_flight;     /* jobs admitted to the device, not yet completed */
     uint64_t tb_bytes_in_use, tb_bytes_peak, tb_budget;
+    uint64_t short_streams, long_streams; /* serving lanes in use (capped by the process's
+                                             hardware queues, GPU_MAX_HW_QUEUES) */
 } mpg_stats;
 int mpg_get_stats(mpg_ctx *ctx, mpg_stats *st);
 

@@ -219,12 +219,13 @@ __device__ __forceinline__ void publish(mpg_dev_result* rec, const mpg_dev_resul
 }
 
 // Bounded wait until the left strip has published `target` chunks.  Gives up
-// after about 2^18 polls (well under a second) so no wave can spin forever;
-// the pair then reports MPG_E_DEVICE.
+// after `limit` polls (kMaxPolls: well under a second) so no wave can spin
+// forever; the pair then reports MPG_E_DEVICE.  A limit of 0 gives up at
+// once (the host sets it to exercise that path).
 // The polled value goes through readfirstlane: the loop exit is then uniform
 // for the compiler too, so the wave never runs it in divergent form.
-__device__ __forceinline__ bool wait_prog(const int* flag, int target) {
-    for (int it = 0; it < (1 << 18); ++it) {
+__device__ __forceinline__ bool wait_prog(const int* flag, int target, int limit) {
+    for (int it = 0; it < limit; ++it) {
         if (__builtin_amdgcn_readfirstlane(ld_dev(flag)) >= target) return true;
         __builtin_amdgcn_s_sleep(2);
     }
@@ -415,7 +416,8 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         const bool from_left = strip > 0;
         int seen = 0;
         if (from_left) {
-            if (!wait_prog(&prog[strip - 1], nchunks < 2 ? nchunks : 2)) failed = true;
+            if (!wait_prog(&prog[strip - 1], nchunks < 2 ? nchunks : 2, P.max_polls))
+                failed = true;
             nb = ld_dev2(&bnd_g[kBndLo + lane]);
             seen = ld_dev(&prog[strip - 1]);
         }
@@ -430,7 +432,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                     if (ch + 1 < nchunks) {
                         const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
                         if (__builtin_amdgcn_readfirstlane(seen) < need &&
-                            !wait_prog(&prog[strip - 1], need)) {
+                            !wait_prog(&prog[strip - 1], need, P.max_polls)) {
                             failed = true;
                             break;
                         }

@@ -214,7 +214,8 @@ dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
         const bool from_left = strip > 0;
         int seen = 0;
         if (from_left) {
-            if (!wait_prog(&prog[strip - 1], nchunks < 2 ? nchunks : 2)) failed = true;
+            if (!wait_prog(&prog[strip - 1], nchunks < 2 ? nchunks : 2, P.max_polls))
+                failed = true;
             nb = ld_dev2(&bnd_g[kBndLo + lane]);
             seen = ld_dev(&prog[strip - 1]);
         }
@@ -233,7 +234,7 @@ dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
                     if (ch + 1 < nchunks) {
                         const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
                         if (__builtin_amdgcn_readfirstlane(seen) < need &&
-                            !wait_prog(&prog[strip - 1], need)) {
+                            !wait_prog(&prog[strip - 1], need, P.max_polls)) {
                             failed = true;
                             break;
                         }

@@ -39,8 +39,12 @@ struct DevParams {
     uint8_t gcode[64];
     uint8_t donor[128];
     uint8_t acceptor[128];
+    int32_t max_polls;  // polls of a bounded wait before it gives up (kMaxPolls)
 };
 static_assert(offsetof(DevParams, mat) % 4 == 0, "the DP kernel copies mat in dwords");
+// A strip waits for its left neighbour's progress for at most this many
+// polls (well under a second) before the pair reports MPG_E_DEVICE.
+constexpr int32_t kMaxPolls = 1 << 18;
 
 // Per-pair launch plan (device copy; 96 bytes).
 struct PairJob {

@@ -85,17 +85,34 @@ int64_t now_ns() {
 }
 
 // ------------------------------------------------------------- device memory
+// Where device workspace memory comes from: the caller's allocator set with
+// mpg_set_allocator, else hipMalloc / hipFree.  A block goes back through
+// the allocator that made it.
+struct DevAlloc {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*release)(void*, void*) = nullptr;
+    void* user = nullptr;
+};
+
+void free_dev(void* q, const DevAlloc& a) {
+    if (!q) return;
+    if (a.release) a.release(q, a.user);
+    else (void)hipFree(q);
+}
+
 // Buffers outgrown while other work may be running.  hipFree and hipHostFree
-// wait for the whole device, so a serving workspace must not free while
-// batches run on other streams: it parks outgrown buffers here, and the
-// scheduler frees them when no batch is on the device.
+// wait for the whole device, and a caller's allocator may hand a block to
+// other work at once, so a serving workspace must not free while batches run
+// on other streams: it parks outgrown buffers here, and the scheduler frees
+// them when no batch is on the device.
 struct Retired {
     std::mutex mu;
-    std::vector<void*> dev, host;
+    std::vector<std::pair<void*, DevAlloc>> dev;
+    std::vector<void*> host;
     void flush() {
         std::lock_guard<std::mutex> g(mu);
-        for (void* q : dev) hipFree(q);
-        for (void* q : host) hipHostFree(q);
+        for (auto& q : dev) free_dev(q.first, q.second);
+        for (void* q : host) (void)hipHostFree(q);
         dev.clear();
         host.clear();
     }
@@ -104,34 +121,57 @@ struct Retired {
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
-    Retired* later = nullptr;  // set: park outgrown buffers instead of freeing
+    Retired* later = nullptr;      // set: park outgrown buffers instead of freeing
+    const DevAlloc* src = nullptr;  // allocator of new blocks (NULL or empty: hipMalloc)
+    DevAlloc owner;                 // allocator of the current block
+    // One block of `bytes` from the allocator in effect; MPG_E_INVAL if a
+    // caller's allocator returns a block that is not 256-byte aligned.
+    int grab(size_t bytes) {
+        if (src && src->alloc) {
+            void* q = src->alloc(bytes, src->user);
+            if (!q) return MPG_E_NOMEM;
+            if ((uintptr_t)q & 255) {
+                src->release(q, src->user);
+                return MPG_E_INVAL;
+            }
+            p = q;
+            owner = *src;
+            return MPG_OK;
+        }
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return MPG_E_NOMEM;
+        }
+        owner = DevAlloc{};
+        return MPG_OK;
+    }
     int ensure(size_t bytes) {
         if (bytes <= cap) return MPG_OK;
         if (p && later) {
             std::lock_guard<std::mutex> g(later->mu);
-            later->dev.push_back(p);
+            later->dev.push_back({p, owner});
         } else if (p) {
-            hipFree(p);
+            free_dev(p, owner);
         }
         p = nullptr;
         cap = 0;
         size_t want = std::max<size_t>(bytes, 256);
         want = want + want / 4;
-        if (hipMalloc(&p, want) != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            if (hipMalloc(&p, bytes) != hipSuccess) {
-                p = nullptr;
-                (void)hipGetLastError();
-                return MPG_E_NOMEM;
-            }
+        int rc = grab(want);
+        if (rc == MPG_E_NOMEM) {
+            rc = grab(bytes);
             want = bytes;
+        }
+        if (rc != MPG_OK) {
+            p = nullptr;
+            return rc;
         }
         cap = want;
         return MPG_OK;
     }
     void release() {
-        if (p) hipFree(p);
+        free_dev(p, owner);
         p = nullptr;
         cap = 0;
     }
@@ -218,6 +258,11 @@ struct Workspace {
     std::vector<ChainJob> cjobs;
     std::vector<int64_t> wave_ops_off;
     std::vector<int32_t> wave_idx;
+    void use_allocator(const DevAlloc* a) {
+        DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state,
+                       &chain, &piece_out, &piece_ops, &cset, &cio};
+        for (auto* b : d) b->src = a;
+    }
     void defer_frees(Retired* r) {
         DevBuf* d[] = {&jobs, &row_start, &order, &desc, &bnd, &tb, &seq, &out, &ops, &state,
                        &chain, &piece_out, &piece_ops, &cset, &cio};
@@ -393,6 +438,12 @@ void make_dev_params(const mpg_params* p, DevParams* d) {
     std::memcpy(d->gcode, p->gcode, 64);
     std::memcpy(d->donor, p->donor, 125);
     std::memcpy(d->acceptor, p->acceptor, 125);
+    d->max_polls = kMaxPolls;
+    // debug override for tests of the failure path: MPG_DEBUG_WAIT_POLLS=0
+    // makes every bounded wait between strips give up at once (its pairs
+    // report MPG_E_DEVICE; every kernel still runs to its end)
+    if (const char* v = std::getenv("MPG_DEBUG_WAIT_POLLS"))
+        d->max_polls = std::max(0, std::min(std::atoi(v), (int)kMaxPolls));
 }
 
 struct Timer;
@@ -631,6 +682,8 @@ struct mpg_ctx {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     uint64_t tb_budget = 64ull << 30;
+    // device memory of every workspace of the context (mpg_set_allocator)
+    DevAlloc alloc;
     Workspace ws;
     // allocation-free entry point: the device's fixed scratch array (its
     // address taken at creation) and the host storage its calls reuse
@@ -1142,18 +1195,44 @@ int mpg_ctx_create(mpg_ctx** out, int device, uint64_t tb_budget_bytes, uint32_t
     if (const int v = env_int("MPG_SRV_SHORT_MCELLS")) c->short_cells = (int64_t)v * 1000000;
     if (const int v = env_int("MPG_SRV_LONG_SHARE_PCT")) c->long_share = std::min(v, 100) / 100.0;
     if (const int v = env_int("MPG_SRV_MAX_JOBS")) c->max_jobs_per_batch = std::max(1, v);
+    if (const int v = env_int("MPG_SRV_MAX_PENDING")) c->max_pending = (size_t)std::max(1, v);
     if (const int v = env_int("MPG_SRV_K_SHORT")) c->serve_K_short = (v == 1 || v == 2 || v == 4) ? v : 1;
     if (const int v = env_int("MPG_SRV_K_LONG")) c->serve_K_long = (v == 1 || v == 2 || v == 4) ? v : 2;
+    // streams beyond the process's hardware queues share a queue and run
+    // one after another: keep no more serving streams than queues (HIP's
+    // default is 4), fewer long lanes first, at least one of each
+    {
+        const int hwq = env_int("GPU_MAX_HW_QUEUES") > 0 ? env_int("GPU_MAX_HW_QUEUES") : 4;
+        if (c->nshort + c->nlong > hwq) c->nlong = std::max(1, hwq - c->nshort);
+        if (c->nshort + c->nlong > hwq) c->nshort = std::max(1, hwq - c->nlong);
+    }
     if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return MPG_E_DEVICE;
     }
     c->stream = c->own_stream;
     c->stats.tb_budget = c->tb_budget;
+    c->stats.short_streams = (uint64_t)c->nshort;
+    c->stats.long_streams = (uint64_t)c->nlong;
+    c->ws.use_allocator(&c->alloc);
+    for (auto& w : c->chain_ws) w.use_allocator(&c->alloc);
     // the fixed scratch array of the allocation-free entry point, with this
     // device current (its address is taken once per device and kept)
     c->scratch_rc = scratch_address(device, &c->scratch) == hipSuccess ? MPG_OK : MPG_E_DEVICE;
     *out = c;
+    return MPG_OK;
+}
+
+int mpg_set_allocator(mpg_ctx* ctx, void* (*alloc)(size_t, void*),
+                      void (*release)(void*, void*), void* user) {
+    if (!ctx || (!alloc) != (!release)) return MPG_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    std::lock_guard<std::mutex> lk2(ctx->mu);
+    // the serving threads read the allocator without a lock
+    if (ctx->sched_running) return MPG_E_INVAL;
+    ctx->alloc.alloc = alloc;
+    ctx->alloc.release = release;
+    ctx->alloc.user = alloc ? user : nullptr;
     return MPG_OK;
 }
 
@@ -1357,34 +1436,39 @@ int serve_batch(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pa
         dbytes += pairs[k].dlen;
     }
     const int64_t ops_cap = mpg_ops_capacity(segs.data(), n);
-    int rc;
-    ws.prec.flags = ws.pops.flags = hipHostMallocMapped | hipHostMallocCoherent;
-    if ((rc = ws.seq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return rc;
-    if ((rc = ws.hseq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return rc;
-    if ((rc = ws.prec.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return rc;
-    if ((rc = ws.pops.ensure((size_t)ops_cap + 64)) != MPG_OK) return rc;
-    if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
-    uint8_t* hs = (uint8_t*)ws.hseq.p;
-    for (int32_t k = 0; k < n; ++k) {
-        if (pairs[k].plen) std::memcpy(hs + segs[k].prot_off, pairs[k].prot, pairs[k].plen);
-        if (pairs[k].dlen) std::memcpy(hs + pbytes + segs[k].dna_off, pairs[k].dna, pairs[k].dlen);
-    }
-    volatile mpg_dev_result* rec = (volatile mpg_dev_result*)ws.prec.p;
-    for (int32_t k = 0; k < n; ++k) rec[k].status = kPending;
-    std::atomic_thread_fence(std::memory_order_seq_cst);
-    uint8_t* d_seq = (uint8_t*)ws.seq.p;
-    if (pbytes + dbytes > 0 &&
-        hipMemcpyAsync(d_seq, hs, (size_t)(pbytes + dbytes), hipMemcpyHostToDevice, st) !=
-            hipSuccess)
-        return MPG_E_DEVICE;
-    RunCfg cfg;
-    cfg.tb_budget = tb_budget;
-    cfg.ncu = ncu;
-    cfg.serve = true;
-    cfg.tune = tune;
-    cfg.force_K = force_K;
-    rc = run_dev_waves(st, ws, p, d_seq, d_seq + pbytes, segs.data(), n,
-                       (mpg_dev_result*)ws.prec.p, (char*)ws.pops.p, cfg);
+    volatile mpg_dev_result* rec = nullptr;
+    // stage, launch; a failure anywhere here completes every pair with it
+    int rc = [&]() -> int {
+        int r;
+        ws.prec.flags = ws.pops.flags = hipHostMallocMapped | hipHostMallocCoherent;
+        if ((r = ws.seq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return r;
+        if ((r = ws.hseq.ensure((size_t)(pbytes + dbytes) + 64)) != MPG_OK) return r;
+        if ((r = ws.prec.ensure(sizeof(mpg_dev_result) * (size_t)n + 64)) != MPG_OK) return r;
+        if ((r = ws.pops.ensure((size_t)ops_cap + 64)) != MPG_OK) return r;
+        if (hipStreamSynchronize(st) != hipSuccess) return MPG_E_DEVICE;
+        uint8_t* hs = (uint8_t*)ws.hseq.p;
+        for (int32_t k = 0; k < n; ++k) {
+            if (pairs[k].plen) std::memcpy(hs + segs[k].prot_off, pairs[k].prot, pairs[k].plen);
+            if (pairs[k].dlen)
+                std::memcpy(hs + pbytes + segs[k].dna_off, pairs[k].dna, pairs[k].dlen);
+        }
+        rec = (volatile mpg_dev_result*)ws.prec.p;
+        for (int32_t k = 0; k < n; ++k) rec[k].status = kPending;
+        std::atomic_thread_fence(std::memory_order_seq_cst);
+        uint8_t* d_seq = (uint8_t*)ws.seq.p;
+        if (pbytes + dbytes > 0 &&
+            hipMemcpyAsync(d_seq, hs, (size_t)(pbytes + dbytes), hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+            return MPG_E_DEVICE;
+        RunCfg cfg;
+        cfg.tb_budget = tb_budget;
+        cfg.ncu = ncu;
+        cfg.serve = true;
+        cfg.tune = tune;
+        cfg.force_K = force_K;
+        return run_dev_waves(st, ws, p, d_seq, d_seq + pbytes, segs.data(), n,
+                             (mpg_dev_result*)ws.prec.p, (char*)ws.pops.p, cfg);
+    }();
     std::vector<char> got(n, 0);
     int32_t left = n;
     auto harvest = [&]() {
@@ -1429,8 +1513,11 @@ int serve_batch(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pa
             if (!f) std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
     }
+    // wait for whatever was enqueued before the records are given up
+    if (hipStreamSynchronize(st) != hipSuccess && rc == MPG_OK) rc = MPG_E_DEVICE;
     if (left) {
-        // the device failed, or a record was never published
+        // set-up or the device failed, or a record was never published:
+        // every pair not yet delivered completes with that status
         if (rc == MPG_OK) rc = MPG_E_DEVICE;
         for (int32_t k = 0; k < n; ++k) {
             if (got[k]) continue;
@@ -1440,7 +1527,6 @@ int serve_batch(hipStream_t st, Workspace& ws, const mpg_params* p, const mpg_pa
             deliver(k, R, nullptr);
         }
     }
-    hipStreamSynchronize(st);
     return rc;
 }
 
@@ -1464,6 +1550,7 @@ void scheduler(mpg_ctx* c) {
     for (int k = 0; k < ns; ++k) {
         hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking);
         wss[k].defer_frees(&retired);
+        wss[k].use_allocator(&c->alloc);
     }
     std::unique_lock<std::mutex> lk(c->mu);
     for (;;) {
@@ -2471,6 +2558,7 @@ int mpg_autotune(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot, const
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Workspace ws;
+    ws.use_allocator(&ctx->alloc);
     int rc = MPG_OK;
     hipStream_t st = ctx->stream;
     mpg_params prm;
@@ -2631,6 +2719,7 @@ int mpg_plan_create(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot,
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     pl->ctx = ctx;
+    pl->ws.use_allocator(&ctx->alloc);
     pl->cfg.tb_budget = ctx->tb_budget;
     pl->cfg.ncu = g_num_cu;
     pl->cfg.tune = &ctx->tune;

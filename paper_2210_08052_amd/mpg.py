@@ -100,7 +100,8 @@ class mpg_dev_result(ctypes.Structure):
 class mpg_stats(ctypes.Structure):
     _fields_ = [(nm, ctypes.c_uint64) for nm in (
         "submitted", "completed", "cancelled", "rejected_again", "rejected_range", "batches",
-        "cells", "queue_depth", "in_flight", "tb_bytes_in_use", "tb_bytes_peak", "tb_budget")]
+        "cells", "queue_depth", "in_flight", "tb_bytes_in_use", "tb_bytes_peak", "tb_budget",
+        "short_streams", "long_streams")]
 
 
 class mpg_timing(ctypes.Structure):
@@ -130,7 +131,12 @@ EXPORTS = ["mpg_ctx_create", "mpg_ctx_destroy", "mpg_set_stream", "mpg_params_de
            "mpg_chain_ops_capacity", "mpg_align_chains_dev", "mpg_align_profiles",
            "mpg_profile_bytes", "mpg_align_profiles_dev", "mpg_chaining_params_default",
            "mpg_chain_anchors", "mpg_chain_anchors_dev", "mpg_rescore_spliced_dev",
-           "mpg_align_batch_dev_noalloc"]
+           "mpg_align_batch_dev_noalloc", "mpg_set_allocator"]
+
+# mpg_set_allocator callbacks: alloc(bytes, user) -> device pointer or NULL;
+# release(ptr, user)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 _lib = None
 
@@ -166,6 +172,7 @@ def lib():
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
         L.mpg_align_batch_dev_noalloc.argtypes = L.mpg_align_batch_dev.argtypes
+        L.mpg_set_allocator.argtypes = [ctypes.c_void_p, ALLOC_FN, RELEASE_FN, ctypes.c_void_p]
         L.mpg_sync.argtypes = [ctypes.c_void_p]
         L.mpg_submit.argtypes = [ctypes.c_void_p, P(mpg_params), P(mpg_pair),
                                  P(ctypes.c_uint64)]
@@ -284,6 +291,19 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_allocator(self, alloc=None, release=None):
+        """Device memory of the context's workspaces from Python callables:
+        alloc(nbytes) -> device pointer (int, 0 on failure), release(ptr).
+        Both None: back to hipMalloc/hipFree.  The callables are kept alive
+        with the context."""
+        if alloc is None and release is None:
+            cbs = (ALLOC_FN(), RELEASE_FN())
+        else:
+            cbs = (ALLOC_FN(lambda n, _u: alloc(n) or None),
+                   RELEASE_FN(lambda q, _u: release(q)))
+        check(lib().mpg_set_allocator(self.ptr, cbs[0], cbs[1], None), "mpg_set_allocator")
+        self._alloc_cbs = getattr(self, "_alloc_cbs", []) + [cbs]
 
     def set_stream(self, stream_handle: int):
         check(lib().mpg_set_stream(self.ptr, ctypes.c_void_p(stream_handle)), "mpg_set_stream")

@@ -778,3 +778,178 @@ def test_long_tail_full_size_properties(ctx):
         s, ge, pe = rescore(p.prot.decode(), p.dna.decode(), o, a["g_beg"], a["p_beg"], a["ops"])
         assert (s, ge, pe) == (a["score"], a["g_end"], a["p_end"]), (len(p.prot), len(p.dna))
     assert max(len(p.dna) for p in pairs) > 100000
+
+
+def test_allocator_hook_torch_caching_allocator():
+    """mpg_set_allocator with PyTorch's caching allocator: every workspace
+    block comes from torch's pool, results equal the hipMalloc path on calls
+    that grow and shrink, every block is given back (none while the context's
+    stream still had work), and serving through the hook equals batch."""
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    events, live = [], {}
+
+    def alloc(n):
+        q = torch.cuda.caching_allocator_alloc(n, device=0, stream=stream)
+        live[q] = n
+        events.append(("alloc", q, n, True))
+        return q
+
+    def release(q):
+        events.append(("release", q, live.pop(q), stream.query()))
+        torch.cuda.caching_allocator_delete(q)
+
+    g, _ = scorings(0, 0)
+    small = [(p, d, k % 2 == 0) for k, (p, d) in enumerate(_pairs(61, n=10, max_prot=120,
+                                                                  max_dna=600))]
+    big = [(p, d, k % 3 == 0) for k, (p, d) in enumerate(_pairs(62, n=40, max_prot=500,
+                                                                max_dna=4000))]
+    with mpg.Context(0) as plain:
+        ref = {id(j): plain.align_batch(j, g) for j in (small, big)}
+    in_torch = torch.cuda.memory_allocated(dev)
+    with mpg.Context(0) as c:
+        c.set_stream(stream.cuda_stream)
+        c.set_allocator(alloc, release)
+        for rnd, jobs in enumerate((small, big, small, big)):
+            got = c.align_batch(jobs, g)
+            for k, (r, e) in enumerate(zip(got, ref[id(jobs)])):
+                tb = jobs[k][2]
+                assert key_gpu(r, tb) == key_gpu(e, tb), (rnd, k)
+        assert torch.cuda.memory_allocated(dev) > in_torch  # the workspaces live in torch's pool
+        n_alloc = sum(1 for e in events if e[0] == "alloc")
+        assert n_alloc >= 5
+        assert len(live) > 0
+        # serving through the same hook (its own workspaces, other threads)
+        ids = [c.submit(g, p, d, want_tb=tb) for p, d, tb in big[:12]]
+        served = {}
+        while len(served) < len(ids):
+            for r in c.poll(64, 200000):
+                served[r["job_id"]] = r
+        for k, jid in enumerate(ids):
+            tb = big[k][2]
+            assert key_gpu(served[jid], tb) == key_gpu(ref[id(big)][k], tb), k
+        with pytest.raises(RuntimeError):
+            c.set_allocator(None, None)  # not once the context has served jobs
+    assert not live, "%d blocks never given back" % len(live)
+    rel = [e for e in events if e[0] == "release"]
+    assert len(rel) == sum(1 for e in events if e[0] == "alloc")
+    busy = [e for e in rel if not e[3]]
+    assert not busy, "%d blocks released while the context's stream had work" % len(busy)
+
+
+def _collect(srv, ids, timeout_s=60.0):
+    import time
+    got, t0 = {}, time.time()
+    want = set(ids)
+    while not want <= set(got) and time.time() - t0 < timeout_s:
+        for r in srv.poll(64, 100000):
+            got[r["job_id"]] = r
+    assert want <= set(got), "jobs never completed: %s" % sorted(want - set(got))
+    return got
+
+
+def _submit_retry(srv, g, prot, dna, tb, timeout_s=30.0):
+    """Submit, retrying while the queue is full (MPG_E_AGAIN)."""
+    import time
+    t0 = time.time()
+    while True:
+        jid = srv.submit(g, prot, dna, want_tb=tb)
+        if jid != mpg.MPG_E_AGAIN or time.time() - t0 > timeout_s:
+            return jid
+        time.sleep(0.001)
+
+
+def test_serving_failure_paths(monkeypatch):
+    """Serving failure paths, each forced deterministically from the host:
+    a full queue (MPG_E_AGAIN), a job over the traceback budget at submit
+    (MPG_E_RANGE), a cancelled queued job (MPG_E_CANCELLED), unknown ids, and
+    per-pair MPG_E_DEVICE when every bounded wait between strips gives up at
+    once (MPG_DEBUG_WAIT_POLLS=0: the kernels still run to their end).  Every
+    submitted job comes back, and the same context then serves the next jobs
+    exactly as the batch path does."""
+    monkeypatch.setenv("MPG_SRV_MAX_PENDING", "2")
+    rng = np.random.default_rng(77)
+    aa, nt = np.array(list(b"ACDEFGHIKLMNPQRSTVWY")), np.array(list(b"ACGT"))
+
+    def rand(m, n):
+        return rng.choice(aa, size=m).astype(np.uint8).tobytes(), \
+            rng.choice(nt, size=n).astype(np.uint8).tobytes()
+
+    g, _ = scorings(0, 0)
+    # a long job (3e8 cells) holds 576 MB of direction bits while it runs;
+    # with a 680 MB budget no short traceback job of 138 MB is admitted then
+    long_job = rand(300, 1000000)
+    shorts = [rand(2000, 60000) for _ in range(3)]
+    huge = rand(3000, 300000)
+    with mpg.Context(0, tb_budget_bytes=680000000) as srv:
+        assert srv.submit(g, *huge, want_tb=True) == mpg.MPG_E_RANGE
+        jl = srv.submit(g, *long_job, want_tb=True)
+        assert jl > 0
+        import time
+        t0 = time.time()
+        while srv.stats()["queue_depth"] > 0 and time.time() - t0 < 5:
+            time.sleep(0.0005)  # the long job is admitted (and holds its budget)
+        assert srv.stats()["queue_depth"] == 0
+        j1 = srv.submit(g, *shorts[0], want_tb=True)
+        j2 = srv.submit(g, *shorts[1], want_tb=True)
+        assert min(jl, j1, j2) > 0
+        assert srv.submit(g, *shorts[2], want_tb=True) == mpg.MPG_E_AGAIN
+        assert srv.cancel(j2) == mpg.MPG_OK
+        assert srv.cancel(j2) == mpg.MPG_E_INVAL
+        assert srv.cancel(10 ** 9) == mpg.MPG_E_INVAL
+        got = _collect(srv, [jl, j1, j2])
+        assert got[j2]["status"] == mpg.MPG_E_CANCELLED
+        with mpg.Context(0) as c:
+            srv_ref = c.align_batch([long_job + (True,), shorts[0] + (True,)], g)
+        for jid, r in zip((jl, j1), srv_ref):
+            assert key_gpu(got[jid], True) == key_gpu(r, True)
+        st = srv.stats()
+        assert (st["rejected_again"], st["rejected_range"], st["cancelled"]) == (1, 1, 1)
+        assert st["in_flight"] == 0 and st["tb_bytes_in_use"] == 0
+
+        # every bounded wait between strips gives up: pairs of several strips
+        # report MPG_E_DEVICE, pairs of one strip are unaffected
+        multi = [rand(300, 3000) for _ in range(4)]
+        single = [rand(40, 2000) for _ in range(4)]
+        with mpg.Context(0) as c:
+            ref = c.align_batch([x + (k % 2 == 0,) for k, x in enumerate(multi + single)], g)
+        monkeypatch.setenv("MPG_DEBUG_WAIT_POLLS", "0")
+        ids = [_submit_retry(srv, g, *x, k % 2 == 0) for k, x in enumerate(multi + single)]
+        assert min(ids) > 0
+        got = _collect(srv, ids)
+        for k, jid in enumerate(ids):
+            if k < len(multi):
+                assert got[jid]["status"] == mpg.MPG_E_DEVICE, k
+            else:
+                assert key_gpu(got[jid], k % 2 == 0) == key_gpu(ref[k], k % 2 == 0), k
+        monkeypatch.delenv("MPG_DEBUG_WAIT_POLLS")
+        # the same context serves the next jobs correctly
+        ids = [_submit_retry(srv, g, *x, k % 2 == 0) for k, x in enumerate(multi + single)]
+        assert min(ids) > 0
+        got = _collect(srv, ids)
+        for k, jid in enumerate(ids):
+            assert key_gpu(got[jid], k % 2 == 0) == key_gpu(ref[k], k % 2 == 0), k
+        st = srv.stats()
+        # jl and j1, then two rounds of jobs (a cancelled job counts as cancelled)
+        assert st["completed"] == 2 + 2 * len(ids) and st["in_flight"] == 0
+
+
+def test_batch_bounded_wait_gives_up_per_pair(monkeypatch):
+    """The batch path under the same forced give-up: pairs of several strips
+    report MPG_E_DEVICE, the others are exact, and the next call is exact."""
+    g, o = scorings(0, 0)
+    pairs = _pairs(4242, n=16, max_prot=400, max_dna=1500, min_prot=150)
+    pairs += _pairs(4243, n=8, max_prot=40, max_dna=800)
+    monkeypatch.setenv("MPG_FORCE_K", "1")
+    with mpg.Context(0) as c:
+        ok = compare(c, pairs, g, o, True, label="before")
+        monkeypatch.setenv("MPG_DEBUG_WAIT_POLLS", "0")
+        bad = c.align_batch([(p, d, True) for p, d in pairs], g)
+        monkeypatch.delenv("MPG_DEBUG_WAIT_POLLS")
+        for k, (p, d) in enumerate(pairs):
+            if len(p) + 1 > 64:
+                assert bad[k]["status"] == mpg.MPG_E_DEVICE, k
+            else:
+                assert key_gpu(bad[k], True) == key_gpu(ok[k], True), k
+        compare(c, pairs, g, o, True, label="after")

@@ -128,6 +128,7 @@ def test_null_arguments_are_rejected():
     p = mpg.params()
     assert L.mpg_align_batch_dev_noalloc(None, ctypes.byref(p), None, None, None, 0, None, None,
                                          0) == mpg.MPG_E_INVAL
+    assert L.mpg_set_allocator(None, mpg.ALLOC_FN(), mpg.RELEASE_FN(), None) == mpg.MPG_E_INVAL
 
 
 def test_chaining_defaults_are_the_papers():
