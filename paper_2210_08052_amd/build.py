@@ -15,8 +15,11 @@ SOURCES = ["mpg_dp_k1.hip", "mpg_dp_k2.hip", "mpg_dp_k4.hip", "mpg_dp_p1.hip", "
            "mpg_dp16.hip", "mpg_chain.hip", "mpg_kernels.hip", "mpg_lib.cpp"]
 ARCH = os.environ.get("MPG_OFFLOAD_ARCH", "gfx950")
 
-# Packed-FP32 instructions are disabled for all device code.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed-FP32 instructions are disabled for all device code.  The DP kernels
+# unroll their 64-step chunks completely (#pragma unroll); the default size
+# limit on pragma-requested unrolling would leave the wider variants rolled.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-pragma-unroll-threshold=1000000"]
 
 
 def _hipcc() -> str:

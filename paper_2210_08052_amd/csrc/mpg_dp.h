@@ -17,9 +17,22 @@
 #ifndef MPG_SCORE_WAVES
 #define MPG_SCORE_WAVES 4
 #endif
+#ifndef MPG_TB_WAVES
+#define MPG_TB_WAVES 3
+#endif
+// A scheduling barrier between the steps of a chunk keeps each step's
+// instructions together (bounding the registers the unrolled chunk needs):
+// kept in the score-only kernels, left out of the traceback ones, which run
+// 2% faster with neighbouring steps interleaved (timed on the 10k batch).
+#ifndef MPG_STEP_BARRIER
+#define MPG_STEP_BARRIER 1
+#endif
+#ifndef MPG_TB_STEP_BARRIER
+#define MPG_TB_STEP_BARRIER 0
+#endif
 template <int K, bool TB>
 struct WavesPerEu {
-    static constexpr int value = K > 2 ? 1 : (TB ? (K == 2 ? 3 : 1) : MPG_SCORE_WAVES);
+    static constexpr int value = K > 2 ? 1 : (TB ? (K == 2 ? MPG_TB_WAVES : 1) : MPG_SCORE_WAVES);
 };
 
 namespace mpg {
@@ -151,16 +164,13 @@ struct Sentinel {
     static constexpr int UNREACH = floor_mode(MODE) ? NEG / 2 : -(1 << 29);
 };
 
-// acc = 2*acc + (ext >= open) in every lane: the compare is a wave ballot
-// (one v_cmp into a scalar mask, placed by the compiler), the shift-in one
-// add-with-carry that reads the mask.  Collects a lane's extension decisions,
-// one bit per step, most recent step in bit 0.
-__device__ __forceinline__ uint32_t push_ge(uint32_t acc, int ext, int open) {
-    const unsigned long long m = __builtin_amdgcn_ballot_w64(ext >= open);
-    uint32_t r;
-    unsigned long long co;
-    asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=&s"(co) : "v"(acc), "s"(m));
-    return r;
+// acc = 2*acc + (diff < 0) in every lane, one funnel shift: the choice of a
+// gap or intron state, one bit per step, most recent step in bit 0.  diff =
+// extension - opening, so the bit is 1 where the state opened (opening
+// strictly better: extension wins ties).  All values lie within 2^31 of each
+// other (planner's score bound), so the difference never overflows.
+__device__ __forceinline__ uint32_t push_open(uint32_t acc, int diff) {
+    return __builtin_amdgcn_alignbit(acc, (uint32_t)diff, 31);
 }
 
 // Per-pair state shared by the waves that work on the pair's strips.
@@ -280,6 +290,11 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
     const int cqD = TB ? 16 * (P.q + P.e) - 12 : P.q;  // D open  (TB: nibble 12)
     const int ce = TB ? 16 * P.e : P.e;
     const int cf = TB ? 16 * P.f : P.f;
+    // traceback: the F1 and G1 candidates' offsets (16f less their nibbles),
+    // kept opaque so that the compiler does not share H - 16f between them
+    // and add each nibble with a separate instruction
+    int cf11 = cf - 11, cf9 = cf - 9;
+    asm volatile("" : "+s"(cf11), "+s"(cf9));
 
     // Items are taken when the previous one is done (claiming ahead would
     // hold a strip that the next strip of its pair then waits for).
@@ -326,11 +341,13 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 for (int tr = 0; tr < 25; ++tr) {
                     const bool poison = pc < 0 || tr == 24;
                     const int v = tr < 24 ? sv[tr < 24 ? tr : 0] : 0;
+                    // column c of every lane in a row of its own, so that each
+                    // step reads one sign-extended entry per column
                     if (TB)
-                        ((int16_t*)prof)[tr * LY::SW + lane * K + c] =
+                        ((int16_t*)prof)[(c * 25 + tr) * 64 + lane] =
                             (int16_t)(poison ? -32768 : 16 * v + 14);
                     else
-                        ((int8_t*)prof)[tr * LY::SW + lane * K + c] = (int8_t)(poison ? -128 : v);
+                        ((int8_t*)prof)[(c * 25 + tr) * 64 + lane] = (int8_t)(poison ? -128 : v);
                 }
             }
             inb[lane] = make_int2(NEG, NEG);
@@ -357,6 +374,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         }
         int h1[K], h2[K], h3[K], d1[K], d2[K], d3[K], a1[K], b1[K], c1[K];
         int zl[K], best[K], bstep[K], bk[K], bkt[K], hn[K];
+        int fp[K];  // previous row's frameshift term (F1/G1 maximum)
         uint32_t nacc[K];
         uint32_t xacc[5][K];  // extension decisions of the last steps, per lane
         // The fixed-end kernel also runs EXTEND_LEFT pairs: their start term
@@ -376,6 +394,9 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
             bk[c] = INT_MIN;
             bkt[c] = 0;
             hn[c] = NEG;
+            // the frameshift term of the row above the strip's first (every
+            // H there is -infinity)
+            fp[c] = TB ? NEG - cf11 : NEG - cf;
             nacc[c] = 0;
 #pragma unroll
             for (int x = 0; x < 5; ++x) xacc[x][c] = 0;
@@ -469,13 +490,13 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                 };
                 auto ld_prof = [&](const int4& x0, int* scv) {
                     if (TB) {
-                        const int16_t* pr = (const int16_t*)prof + x0.x * LY::SW + lane * K;
+                        const int16_t* pr = (const int16_t*)prof + x0.x * 64 + lane;
 #pragma unroll
-                        for (int c = 0; c < K; ++c) scv[c] = pr[c];
+                        for (int c = 0; c < K; ++c) scv[c] = pr[c * 25 * 64];
                     } else {
-                        const int8_t* pr = (const int8_t*)prof + x0.x * LY::SW + lane * K;
+                        const int8_t* pr = (const int8_t*)prof + x0.x * 64 + lane;
 #pragma unroll
-                        for (int c = 0; c < K; ++c) scv[c] = pr[c];
+                        for (int c = 0; c < K; ++c) scv[c] = pr[c * 25 * 64];
                     }
                 };
                 int4 cd0, cd1 = make_int4(0, 0, 0, 0), nd0, nd1 = make_int4(0, 0, 0, 0);
@@ -511,50 +532,77 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         const int z = floor_mode(SM) ? zr : imin(zr, zl[c]);
                         if (!TB) {
                             const int D = imax(h3[c] - cqDv[c], d3[c]) - ceDv[c];
-                            int H = D;
+                            const int I = imax(L0 - cqv[c], IL) - cev[c];
+                            const int M = L3 + csc[c];
+                            // frameshifts: F1 and G1 of this row cost f each, and F2,
+                            // G2 are the previous row's F1, G1 (H two rows up is the
+                            // history one row up), so one max per cell covers all four
+                            int pf = 0;
+                            if (!NOF) {
+                                pf = imax(L1, h1[c]) - cf;
+                                // opaque to the next row: the compiler would otherwise
+                                // expand fp - ... back into four candidates there
+                                asm("" : "+v"(pf));
+                            }
+                            int H;
                             if (!NOI) {
                                 const int A = imax(h1[c] - ddm1, a1[c]);
                                 const int B = imax(L1 - dd0, b1[c]);
                                 const int C = imax(L1 - ds0.z, c1[c]);
-                                H = imax3(H, A - ds0.w, imax(B - aam2, C - aam1));
                                 An[c] = A; Bn[c] = B; Cn[c] = C;
+                                const int x = imax3(D, A - ds0.w, B - aam2);
+                                if (!NOF) H = imax3(x, imax3(C - aam1, pf, fp[c]), imax3(M, I, z));
+                                else H = imax3(x, imax3(C - aam1, M, I), z);
+                            } else {
+                                if (!NOF) H = imax(imax3(D, pf, fp[c]), imax3(M, I, z));
+                                else H = imax(imax3(D, M, I), z);
                             }
-                            if (!NOF) {
-                                const int fg = imax(imax3(L1, L2, h1[c]), h2[c]) - cf;
-                                H = imax(H, fg);
-                            }
-                            const int I = imax(L0 - cqv[c], IL) - cev[c];
-                            H = imax3(H, L3 + csc[c], I);
-                            H = imax(H, z);
+                            if (!NOF) fp[c] = pf;
                             Hn[c] = H; In[c] = I; Dn[c] = D;
                         } else {
                             const int oD = h3[c] - cqDv[c], xD = d3[c] - ceDv[c];
-                            xacc[1][c] = push_ge(xacc[1][c], xD, oD);
-                            const int D = imax(oD, xD);
-                            int Hk = D;
+                            xacc[1][c] = push_open(xacc[1][c], xD - oD);
+                            int D = imax(oD, xD);
+                            const int oI = L0 - cqv[c], xI = IL - cev[c];
+                            xacc[0][c] = push_open(xacc[0][c], xI - oI);
+                            int I = imax(oI, xI);
+                            const int M = L3 + csc[c];
+                            // F1 (nibble 11) and G1 (9) of this row; F2 (10) and G2
+                            // (8) are the previous row's F1 and G1 less one, so their
+                            // maximum is the previous row's maximum less one
+                            int p1 = 0, p2 = 0;
+                            if (!NOF) {
+                                p1 = imax(L1 - cf11, h1[c] - cf9);
+                                // opaque to the next row: the compiler would otherwise
+                                // expand fp - 1 back into four candidates there
+                                asm("" : "+v"(p1));
+                                p2 = fp[c] - 1;
+                                fp[c] = p1;
+                            }
+                            // the states enter H's maximum as they are: left visible,
+                            // the compiler may also build H from their two halves in a
+                            // second tree (seen at one column per lane)
+                            asm("" : "+v"(D), "+v"(I));
+                            int Hk;
                             if (!NOI) {
                                 const int oA = h1[c] - ds0.z;
-                                xacc[2][c] = push_ge(xacc[2][c], a1[c], oA);
-                                const int A = imax(oA, a1[c]);
+                                xacc[2][c] = push_open(xacc[2][c], a1[c] - oA);
+                                int A = imax(oA, a1[c]);
                                 const int oB = L1 - ds0.w;
-                                xacc[3][c] = push_ge(xacc[3][c], b1[c], oB);
-                                const int B = imax(oB, b1[c]);
+                                xacc[3][c] = push_open(xacc[3][c], b1[c] - oB);
+                                int B = imax(oB, b1[c]);
                                 const int oC = L1 - ds1.x;
-                                xacc[4][c] = push_ge(xacc[4][c], c1[c], oC);
-                                const int C = imax(oC, c1[c]);
-                                Hk = imax3(Hk, A - ds1.y, B - ds1.z);
-                                Hk = imax(Hk, C - ds1.w);
+                                xacc[4][c] = push_open(xacc[4][c], c1[c] - oC);
+                                int C = imax(oC, c1[c]);
+                                asm("" : "+v"(A), "+v"(B), "+v"(C));
                                 An[c] = A; Bn[c] = B; Cn[c] = C;
+                                const int x = imax3(D, A - ds1.y, B - ds1.z);
+                                if (!NOF) Hk = imax3(x, imax3(C - ds1.w, p1, p2), imax3(M, I, z));
+                                else Hk = imax3(x, imax3(C - ds1.w, M, I), z);
+                            } else {
+                                if (!NOF) Hk = imax(imax3(D, p1, p2), imax3(M, I, z));
+                                else Hk = imax(imax3(D, M, I), z);
                             }
-                            if (!NOF) {
-                                Hk = imax3(Hk, L1 - (cf - 11), L2 - (cf - 10));
-                                Hk = imax3(Hk, h1[c] - (cf - 9), h2[c] - (cf - 8));
-                            }
-                            const int oI = L0 - cqv[c], xI = IL - cev[c];
-                            xacc[0][c] = push_ge(xacc[0][c], xI, oI);
-                            const int I = imax(oI, xI);
-                            Hk = imax3(Hk, z, L3 + csc[c]);
-                            Hk = imax(Hk, I);
                             nacc[c] = __builtin_amdgcn_alignbit(Hk, nacc[c], 4);
                             Hn[c] = Hk & ~15;
                             In[c] = I; Dn[c] = D;
@@ -601,8 +649,8 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                             *(uint32_t*)(tbblk + (((t >> 3) * K + c) * 64 + lane) * 4) = nacc[c];
                     }
                     if (TB && (t & 31) == 31) {
-                        // each lane's extension bits of the last 32 steps, bit
-                        // 31 - (t & 31) for step t
+                        // each lane's state choices of the last 32 steps, bit
+                        // 31 - (t & 31) for step t, 1 = opened
 #pragma unroll
                         for (int x = 0; x < 5; ++x) {
                             if (NOI && x >= 2) continue;
@@ -633,7 +681,8 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
 #pragma unroll
                     for (int c = 0; c < K; ++c) csc[c] = nsc[c];
                     cin = nin;
-                    __builtin_amdgcn_sched_barrier(0);
+                    if (TB ? MPG_TB_STEP_BARRIER : MPG_STEP_BARRIER)
+                        __builtin_amdgcn_sched_barrier(0);
                 }  // steps
 
                 // merge the chunk's best into the strip's best (first maximum)

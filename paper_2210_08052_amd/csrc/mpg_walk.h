@@ -26,12 +26,14 @@ struct TbView {
         const uint32_t w = *(const uint32_t*)(b + (((t >> 3) * K + c) * 64 + k) * 4);
         return 15 - (int)((w >> ((t & 7) * 4)) & 15u);
     }
+    // 1 if state x (I, D, A, B, C) extended at (i, j); the stored bit is 1
+    // where the state opened
     __device__ __forceinline__ int ext(int x, int i, int j) const {
         int k, c, t;
         const uint8_t* b = blk(i, j, k, c, t);
         const uint32_t w =
             *(const uint32_t*)(b + 2048 * K + (((x * K + c) * 2 + (t >> 5)) * 64 + k) * 4);
-        return (int)((w >> (31 - (t & 31))) & 1u);
+        return (int)((~w >> (31 - (t & 31))) & 1u);
     }
 };
 
