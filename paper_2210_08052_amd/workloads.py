@@ -156,9 +156,10 @@ def _cuts(rng, cds_len: int, n_cuts: int, avoid: list) -> list | None:
 
 
 def planted_gene(rng, L: int, rho: float, n_fs: int, intron_lens: list,
-                 canonical: list):
-    """Steps 1-5: returns (query protein bytes, gene bytes, truth dict)."""
-    prot = rng.integers(0, 20, size=L)
+                 canonical: list, residues=None):
+    """Steps 1-5: returns (query protein bytes, gene bytes, truth dict).
+    ``residues`` (indices into STD20) replaces the draw of step 1."""
+    prot = rng.integers(0, 20, size=L) if residues is None else np.asarray(residues, np.int64)
     mut = prot.copy()
     k = int(round(rho * L))
     if k:
@@ -428,6 +429,85 @@ def random_scoring(seed: int, with_tables: bool = True) -> dict:
         out["mat"] = m.astype(np.int8)
         out["donor"] = rng.integers(0, 31, size=125).astype(np.uint8)
         out["acceptor"] = rng.integers(0, 31, size=125).astype(np.uint8)
+    return out
+
+
+def near_bound_pairs(seed: int = 9) -> list:
+    """Pairs whose best LOCAL score under BLOSUM62 lies just under the int16
+    lanes' admission bound (m * 11 <= 32,511 for a protein of m residues, W:W
+    = 11 being the matrix's largest entry): Trp-rich proteins of 2,940-2,956
+    residues against their own planted genes.
+
+    * pair 0: W^2955 against (TGG)^2955 in random flanks (best score exactly
+      11 * 2955 = 32,505);
+    * pair 1: W^2956 against (TGG)^2956 (bound 32,516: beyond it);
+    * pairs 2-9: 97-99.9 % W (the rest uniform over the 20 residues),
+      0-0.5 % substitutions, 0-1 frameshift, 1-2 canonical introns of 60-300 nt,
+      300-700 nt flanks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = STD20.index("W")
+    out = []
+    for L in (2955, 2956):
+        left, right = int(rng.integers(300, 701)), int(rng.integers(300, 701))
+        gene = np.frombuffer(b"TGG" * L, np.uint8)
+        dna = np.concatenate([_rand_dna(rng, left), gene, _rand_dna(rng, right)])
+        out.append(Pair(b"W" * L, dna.tobytes(), False, {"gene_start": left}))
+    for _ in range(8):
+        L = int(rng.integers(2940, 2956))
+        frac_w = float(rng.uniform(0.97, 0.999))
+        res = np.where(rng.random(L) < frac_w, w, rng.integers(0, 20, size=L))
+        n_in = int(rng.integers(1, 3))
+        ilens = [int(x) for x in rng.integers(60, 301, size=n_in)]
+        prot, gene, truth = planted_gene(rng, L, float(rng.uniform(0.0, 0.005)),
+                                         int(rng.integers(0, 2)), ilens, [True] * n_in,
+                                         residues=res)
+        left, right = int(rng.integers(300, 701)), int(rng.integers(300, 701))
+        out.append(_finish(rng, prot, gene, truth, len(gene) + left + right, left))
+    return out
+
+
+def near_bound_scoring(seed: int, maxpos: int = 120, big_penalties: bool = False) -> dict:
+    """Random scoring inputs with large entries for int16-bound tests: a
+    symmetric 24x24 matrix drawn in [-128, maxpos - 1] whose 20 standard
+    diagonal entries are maxpos (so a protein against its own reverse
+    translation scores maxpos per residue), and penalties either moderate
+    (gap open 0-40, extend 1-10, frameshift 0-60, intron 0-80, splice tables
+    0-30) or near the int16 lanes' penalty limit of 8,192 (gap open
+    1,000-5,000, extend 500-3,000, frameshift 4,000-8,000, intron
+    5,000-7,600, splice tables 0-255)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = rng.integers(-128, maxpos, size=(24, 24))
+    m = np.triu(m) + np.triu(m, 1).T
+    m[np.arange(20), np.arange(20)] = maxpos
+    if big_penalties:
+        q, e = int(rng.integers(1000, 5001)), int(rng.integers(500, 3001))
+        out = {"q": q, "e": min(e, 8192 - q), "f": int(rng.integers(4000, 8001)),
+               "r": int(rng.integers(5000, 7601))}
+        hi = 256
+    else:
+        out = {"q": int(rng.integers(0, 41)), "e": int(rng.integers(1, 11)),
+               "f": int(rng.integers(0, 61)), "r": int(rng.integers(0, 81))}
+        hi = 31
+    out["mat"] = m.astype(np.int8)
+    out["donor"] = rng.integers(0, hi, size=125).astype(np.uint8)
+    out["acceptor"] = rng.integers(0, hi, size=125).astype(np.uint8)
+    return out
+
+
+def self_pairs(seed: int, lengths, rho: float = 0.01) -> list:
+    """One planted gene per protein length (uniform residues, rho
+    substitutions, 0-1 frameshift, 0-2 canonical introns of 60-300 nt,
+    100-400 nt flanks): against a matrix whose diagonal is its largest entry
+    the best score is close to length * that entry."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for L in lengths:
+        n_in = int(rng.integers(0, 3))
+        ilens = [int(x) for x in rng.integers(60, 301, size=n_in)]
+        prot, gene, truth = planted_gene(rng, int(L), rho, int(rng.integers(0, 2)), ilens,
+                                         [True] * n_in)
+        left, right = int(rng.integers(100, 401)), int(rng.integers(100, 401))
+        out.append(_finish(rng, prot, gene, truth, len(gene) + left + right, left))
     return out
 
 

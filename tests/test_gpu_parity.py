@@ -282,6 +282,73 @@ def test_int16_batch_equals_int32(ctx):
         assert key_gpu(r16[k], False) == key_orc(e, False), k
 
 
+# int16 lanes next to their admission bound (m * max(mat) <= 32,511, largest
+# penalty <= 8,192): (pairs, scoring inputs or None for the defaults)
+def _near_bound_cases():
+    L = [270, 271, 269, 255, 200, 150, 90]
+    return [(W.near_bound_pairs(9), None, True),
+            (W.self_pairs(11, L), W.near_bound_scoring(1), True),
+            (W.self_pairs(12, L), W.near_bound_scoring(2, big_penalties=True), False),
+            (W.self_pairs(13, [258, 257, 256, 255, 254, 100]), W.near_bound_scoring(3, maxpos=127),
+             True)]
+
+
+_NB_ORACLE = {}
+
+
+def _nb_scoring(r, allow16):
+    fl = mpg.MPG_ALLOW_I16 if allow16 else 0
+    if r is None:
+        return mpg.params(flags=fl), oracle.default_scoring()
+    kw = dict(q=r["q"], e=r["e"], f=r["f"], r=r["r"], mat=r["mat"], donor=r["donor"],
+              acceptor=r["acceptor"])
+    return mpg.params(flags=fl, **kw), oracle.default_scoring(**kw)
+
+
+@pytest.mark.parametrize("K16", [1, 2])
+def test_int16_near_bound(ctx, K16, monkeypatch):
+    """Best scores within a few hundred of the int16 bound (Trp-rich
+    2,940-2,956-residue proteins against their genes under BLOSUM62, and
+    proteins against their genes under matrices whose diagonal is the
+    largest entry, 120 or 127, with moderate penalties; near-limit penalties
+    push the other side, the gap and intron states, towards -8,192): the
+    int16 lanes, the int32 kernel and the oracle agree on every pair, and
+    exactly the pairs inside the bound run in int16 lanes."""
+    monkeypatch.setenv("MPG_FORCE_K16", str(K16))
+    for ci, (pairs, r, near) in enumerate(_near_bound_cases()):
+        pp = [(q.prot, q.dna) for q in pairs]
+        g16, o = _nb_scoring(r, True)
+        g32, _ = _nb_scoring(r, False)
+        mat = np.ctypeslib.as_array(g16.mat)
+        maxpos = max(0, int(mat.max()))
+        pen = max(g16.q + g16.e, g16.f, g16.r + max(g16.donor) + max(g16.acceptor),
+                  -int(mat.min()))
+        assert pen <= 8192
+        expect = sum(1 for p, _ in pp if maxpos * len(p) <= 32767 - 256)
+        assert 0 < expect < len(pp)
+        print("case K16=%d set=%d pairs=%d int16=%d" % (K16, ci, len(pp), expect), flush=True)
+        if ci not in _NB_ORACLE:
+            _NB_ORACLE[ci] = oracle.align_many(pp, o, want_tb=False, threads=0)
+        exp = _NB_ORACLE[ci]
+        if r is None:
+            # the all-W pair: 11 per residue, the bound itself
+            assert exp[0].score == 11 * len(pp[0][0]) == 32505
+        ctx.enable_timing(True)
+        ctx.timing(reset=True)
+        r16 = ctx.align_batch([(p, d, False) for p, d in pp], g16)
+        n16 = ctx.timing(reset=True)["i16_pairs"]
+        ctx.enable_timing(False)
+        assert n16 == expect, (n16, expect)
+        r32 = ctx.align_batch([(p, d, False) for p, d in pp], g32)
+        if near:
+            best = max(e.score for p, e in zip(pp, exp) if maxpos * len(p) <= 32767 - 256)
+            assert best > 32767 - 256 - 700, best
+        for k, e in enumerate(exp):
+            assert key_gpu(r16[k], False) == key_gpu(r32[k], False) == key_orc(e, False), \
+                (ci, k, len(pp[k][0]), key_gpu(r16[k], False), key_gpu(r32[k], False),
+                 key_orc(e, False))
+
+
 def test_serving_results_arrive_per_pair():
     """A long job submitted first and short jobs after it: results are handed
     out pair by pair, so short results arrive while the long pair still runs,

@@ -279,6 +279,23 @@ def test_mode_nesting_and_monotonicity():
         assert oracle.align(prot, dna, base.replace(donor=d2), False).score <= sl
 
 
+def test_all_trp_reaches_the_score_bound():
+    """Each protein residue adds at most the matrix's largest entry (W:W = 11
+    under BLOSUM62) and every other term is a penalty, so a score is at most
+    11 m.  W^m against (TGG)^m in random flanks attains it on an ungapped path
+    of m codon:residue steps; at m = 2,955 and 2,956 the scores straddle the
+    int16 lanes' admission bound (32,511)."""
+    from paper_2210_08052_amd import workloads as W
+    sc = params.default_scoring()
+    for pr in W.near_bound_pairs(9)[:2]:
+        m = len(pr.prot)
+        r = oracle.align(pr.prot, pr.dna, sc, want_tb=True)
+        assert r.score == 11 * m
+        assert r.ops == "%dM" % m and (r.p_beg, r.p_end) == (0, m)
+        assert r.g_end - r.g_beg == 3 * m
+        assert pr.dna[r.g_beg:r.g_end] == b"TGG" * m
+
+
 def test_empty_inputs():
     sc = params.default_scoring()
     for mode in (0, 1):

@@ -94,7 +94,15 @@ DIGESTS = {
     "chain_1000": "15615f3cfd122d22659be7e7ba8f1236c2ece52bd64d76d8c7af3cd0d727dacc",
     "profile_1000": "162e04091b90ab8e075687cfe0f513635ee5b5e8f4babe7277c04ba337720ce5",
     "chaining_1000": "57adacdaf4de5080f70dce910a1801c692566457903da1264972a36d343ae88a",
+    "near_bound": "46d07401a56adec4ee83b457c64303f7c82e34505bf75b5a07385b4ea796dd22",
+    "self_pairs_11": "0ff4873f34b0be62e0b238f3cfee2fb39e2399b99377f604a5530d088608db07",
+    "near_bound_scoring": "1d7334d9c9cb67bafa3f1843c99299ff163fc4e7ab6fe4a2d209f258b0ff8444",
 }
+
+
+def _nb_scoring(seed, big, maxpos):
+    r = W.near_bound_scoring(seed, maxpos=maxpos, big_penalties=big)
+    return [r["q"], r["e"], r["f"], r["r"], r["mat"], r["donor"], r["acceptor"]]
 
 
 def test_dataset_digests_pinned():
@@ -106,6 +114,10 @@ def test_dataset_digests_pinned():
         "chain_1000": _sha(W.chain_jobs(1000, seed=6)),
         "profile_1000": _sha(W.profile_jobs(1000, seed=2, profile_seed=7)),
         "chaining_1000": _sha(W.chaining_sets(1000, seed=8)),
+        "near_bound": _sha(W.near_bound_pairs(9)),
+        "self_pairs_11": _sha(W.self_pairs(11, [270, 271, 269, 255, 200, 150, 90])),
+        "near_bound_scoring": _sha([_nb_scoring(1, False, 120), _nb_scoring(2, True, 120),
+                                    _nb_scoring(3, False, 127)]),
     }
     assert got == DIGESTS
 
