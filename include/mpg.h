@@ -564,6 +564,7 @@ typedef struct {
     double host_ms;    /* host wall time planning and enqueuing the device work */
     uint64_t i16_pairs; /* pairs that ran in the lane-packed int16 kernel */
     uint64_t cells;     /* DP cells (genome length x protein length) of the pairs run */
+    uint64_t seg_packs; /* wavefronts that ran two pairs' last strips side by side */
 } mpg_timing;
 
 /* Turn event timing of batch calls on (1) or off (0). */

@@ -162,7 +162,11 @@ __device__ __forceinline__ int wave_find_owner(const int64_t* __restrict__ start
 // H winner codes: 0 start, 1 M, 2 I, 3 D, 4 F1, 5 F2, 6 G1, 7 G2, 8 A, 9 B,
 // 10 C; nibble = 15 - code.
 
-template <int K, bool TB>
+// SEG: the kernel also runs two pairs' last strips on lane segments of one
+// wavefront; the second pair's descriptor ring follows the other areas, and
+// its incoming boundary takes the outgoing boundary's area (a last strip
+// publishes no boundary).
+template <int K, bool TB, bool SEG = false>
 struct LdsLayout {
     static constexpr int DS = TB ? 32 : 16;    // descriptor bytes per row
     static constexpr int PS = TB ? 2 : 1;      // profile entry bytes
@@ -172,7 +176,8 @@ struct LdsLayout {
     static constexpr int IN = 64 * 8;          // incoming boundary of the chunk
     static constexpr int OUT = 128 * 8;        // outgoing boundary, then a dummy slot per lane
     static constexpr int MAT = 640;            // substitution matrix, then the letter codes
-    static constexpr int WAVE = RING + PROF + IN + OUT + MAT;
+    static constexpr int RING2 = RING + PROF + IN + OUT + MAT;  // SEG: second ring
+    static constexpr int WAVE = RING2 + (SEG ? RING : 0);
 };
 
 // Sentinels per layout.  The floor modes keep -infinity small enough that a
@@ -261,6 +266,311 @@ __device__ __forceinline__ bool wait_prog(const int* flag, int target, int limit
     return false;
 }
 
+// Result record of a LOCAL score-only pair from its end key (score, -i, -j).
+__device__ __forceinline__ void local_record(mpg_dev_result& R, const PairJob& J,
+                                             unsigned long long ku, bool bad) {
+    R.g_beg = -1;
+    R.p_beg = -1;
+    R.ops_off = J.ops_off;
+    R.ops_len = 0;
+    R._pad = 0;
+    if (bad) {
+        R.status = MPG_E_DEVICE;
+        R.score = 0;
+        R.g_end = -1;
+        R.p_end = -1;
+    } else {
+        R.status = MPG_OK;
+        R.score = (int)(ku >> 36) - (1 << 27);
+        R.g_end = (1 << 21) - 1 - (int)((ku >> 15) & ((1u << 21) - 1));
+        R.p_end = (1 << 15) - 1 - (int)(ku & ((1u << 15) - 1));
+    }
+}
+
+// Two LOCAL score-only pairs' last strips on lane segments of one wavefront
+// (a strip that fills at most part of its lanes leaves the rest idle for all
+// its steps).  item = (pair A, -1 - (pair B << 6 | split)): pair A's last strip
+// in lanes [0, split), pair B's in [split, 64); both strips run the same
+// number of chunks.  Each lane works on its own pair's rows (the segment's
+// lane k at step s on row s - k), reads its pair's descriptors from that
+// pair's LDS ring and takes its left neighbour's H and I by the same DPP shift
+// as a whole-wave strip; the first lane of each segment takes them from its
+// pair's incoming boundary instead (one select per value and step).  A pair
+// of one strip starts from the -infinity column; otherwise its previous strip
+// streams the boundary through HBM as for any strip.
+template <int K, bool NOI, bool NOF>
+__device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restrict__ jobs,
+                                         PairState* __restrict__ pst, int* __restrict__ prog_g,
+                                         const uint8_t* __restrict__ prot,
+                                         const uint8_t* __restrict__ desc, int2* __restrict__ bnd,
+                                         const DpSink& sink, const DevParams& P, uint8_t* smem,
+                                         const int8_t* smat, const uint8_t* saa) {
+    using LY = LdsLayout<K, false, true>;
+    constexpr int NEG = Sentinel<MPG_LOCAL, false>::NEG;
+    constexpr int UNREACH = Sentinel<MPG_LOCAL, false>::UNREACH;
+    const int lane = threadIdx.x & 63;
+    const int code = -1 - item.y;
+    const int ja = item.x, jb = code >> 6, split = code & 63;
+    const PairJob JA = jobs[ja], JB = jobs[jb];
+    const bool sg = lane >= split;            // lane of pair B
+    const bool first = lane == 0 || lane == split;
+    const int kk = sg ? lane - split : lane;  // lane within its segment
+    const int nA = JA.n, nB = JB.n;
+    const int n_l = sg ? nB : nA, m_l = sg ? JB.m : JA.m;
+    const int nchunks = JA.nchunks;
+    const int stripA = JA.nstrips - 1, stripB = JB.nstrips - 1;
+    const int col0 = (sg ? stripB : stripA) * LY::SW + kk * K;
+    const uint8_t* dscA = desc + JA.desc_off;
+    const uint8_t* dscB = desc + JB.desc_off;
+    const uint8_t* dsc_l = sg ? dscB : dscA;
+    const uint8_t* Pa = prot + (sg ? JB.prot_off : JA.prot_off);
+    const int2* bndA = bnd + JA.bnd_off;
+    const int2* bndB = bnd + JB.bnd_off;
+    const int* progA = prog_g + JA.prog_off;
+    const int* progB = prog_g + JB.prog_off;
+    const bool leftA = stripA > 0, leftB = stripB > 0;
+    uint8_t* ringA = smem;
+    uint8_t* ringB = smem + LY::RING2;
+    uint8_t* prof = smem + LY::RING;
+    int2* inbA = (int2*)(smem + LY::RING + LY::PROF);
+    int2* inbB = (int2*)(smem + LY::RING + LY::PROF + LY::IN);
+    const int cq = P.q, ce = P.e, cf = P.f;
+    const int2 neg2 = make_int2(NEG, NEG);
+
+    // profile of this lane's columns (its own pair's residues)
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const int j = col0 + c;
+        int pc = -1;
+        if (j >= 1 && j <= m_l) {
+            const uint32_t ch = Pa[j - 1];
+            const uint32_t u = (ch | 0x20u) - 'a';
+            pc = ch == '*' ? 23 : (u < 26u ? saa[u] : 22);
+        }
+        int sv[24];
+#pragma unroll
+        for (int tr = 0; tr < 24; ++tr) sv[tr] = pc < 0 ? 0 : (int)smat[tr * 24 + pc];
+#pragma unroll
+        for (int tr = 0; tr < 25; ++tr) {
+            const bool poison = pc < 0 || tr == 24;
+            const int v = tr < 24 ? sv[tr < 24 ? tr : 0] : 0;
+            ((int8_t*)prof)[(c * 25 + tr) * 64 + lane] = (int8_t)(poison ? -128 : v);
+        }
+    }
+    int h1[K], h2[K], h3[K], d1[K], d2[K], d3[K], a1[K], b1[K], c1[K];
+    int best[K], bstep[K], bk[K], fp[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        h1[c] = h2[c] = h3[c] = NEG;
+        d1[c] = d2[c] = d3[c] = NEG;
+        a1[c] = b1[c] = c1[c] = NEG;
+        best[c] = NEG;
+        bstep[c] = 0;
+        bk[c] = INT_MIN;
+        fp[c] = NEG - cf;
+    }
+    int hl1 = NEG, hl2 = NEG, hl3 = NEG;
+    int Hout = NEG, Iout = NEG;
+    int dd0, ddm1, aam1, aam2;
+    {
+        const int4 u = *(const int4*)(dsc_l + (int64_t)(-kk - 1 + kDescLo) * LY::DS);
+        const int4 v = *(const int4*)(dsc_l + (int64_t)(-kk - 2 + kDescLo) * LY::DS);
+        dd0 = u.z; aam1 = u.w; ddm1 = v.z; aam2 = v.w;
+    }
+    // both rings: rows -64..-1 then 0..63 of each pair
+    {
+        const int4 a0 = *(const int4*)(dscA + (int64_t)(lane - 64 + kDescLo) * LY::DS);
+        const int4 a1v = *(const int4*)(dscA + (int64_t)(lane + kDescLo) * LY::DS);
+        const int4 b0 = *(const int4*)(dscB + (int64_t)(lane - 64 + kDescLo) * LY::DS);
+        const int4 b1v = *(const int4*)(dscB + (int64_t)(lane + kDescLo) * LY::DS);
+        *(int4*)(ringA + lane * LY::DS) = a0;
+        *(int4*)(ringA + (64 + lane) * LY::DS) = a1v;
+        *(int4*)(ringB + lane * LY::DS) = b0;
+        *(int4*)(ringB + (64 + lane) * LY::DS) = b1v;
+    }
+    inbA[lane] = neg2;
+    inbB[lane] = neg2;
+    bool failed = false;
+    int2 nbA = neg2, nbB = neg2;
+    int seenA = 0, seenB = 0;
+    if (leftA) {
+        if (!wait_prog(&progA[stripA - 1], nchunks < 2 ? nchunks : 2, P.max_polls)) failed = true;
+        nbA = ld_dev2(&bndA[kBndLo + lane]);
+        seenA = ld_dev(&progA[stripA - 1]);
+    }
+    if (leftB) {
+        if (!wait_prog(&progB[stripB - 1], nchunks < 2 ? nchunks : 2, P.max_polls)) failed = true;
+        nbB = ld_dev2(&bndB[kBndLo + lane]);
+        seenB = ld_dev(&progB[stripB - 1]);
+    }
+    int4 pfA = make_int4(0, 0, 0, 0), pfB = make_int4(0, 0, 0, 0);
+    const uint8_t* ring_l = sg ? ringB : ringA;
+    const int2* inb_l = sg ? inbB : inbA;
+
+    for (int ch = 0; ch < nchunks && !failed; ++ch) {
+        // incoming boundary rows ch*64 .. ch*64+63 of each pair with a left strip
+        if (leftA) {
+            inbA[lane] = ch * 64 + lane > nA ? neg2 : nbA;
+            if (ch + 1 < nchunks) {
+                const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
+                if (__builtin_amdgcn_readfirstlane(seenA) < need &&
+                    !wait_prog(&progA[stripA - 1], need, P.max_polls)) {
+                    failed = true;
+                    break;
+                }
+                nbA = ld_dev2(&bndA[kBndLo + (ch + 1) * 64 + lane]);
+                seenA = ld_dev(&progA[stripA - 1]);
+            }
+        }
+        if (leftB) {
+            inbB[lane] = ch * 64 + lane > nB ? neg2 : nbB;
+            if (ch + 1 < nchunks) {
+                const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
+                if (__builtin_amdgcn_readfirstlane(seenB) < need &&
+                    !wait_prog(&progB[stripB - 1], need, P.max_polls)) {
+                    failed = true;
+                    break;
+                }
+                nbB = ld_dev2(&bndB[kBndLo + (ch + 1) * 64 + lane]);
+                seenB = ld_dev(&progB[stripB - 1]);
+            }
+        }
+        if (ch > 0) {
+            const int4 oA = *(const int4*)(ringA + (64 + lane) * LY::DS);
+            const int4 oB = *(const int4*)(ringB + (64 + lane) * LY::DS);
+            *(int4*)(ringA + lane * LY::DS) = oA;
+            *(int4*)(ringA + (64 + lane) * LY::DS) = pfA;
+            *(int4*)(ringB + lane * LY::DS) = oB;
+            *(int4*)(ringB + (64 + lane) * LY::DS) = pfB;
+        }
+        pfA = *(const int4*)(dscA + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS);
+        pfB = *(const int4*)(dscB + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS);
+        const uint8_t* rb = ring_l + (64 - kk) * LY::DS;
+        auto ld_prof = [&](const int4& x0, int* scv) {
+            const int8_t* pr = (const int8_t*)prof + x0.x * 64 + lane;
+#pragma unroll
+            for (int c = 0; c < K; ++c) scv[c] = pr[c * 25 * 64];
+        };
+        int4 cd0 = *(const int4*)(rb), nd0 = *(const int4*)(rb + LY::DS);
+        int csc[K];
+        ld_prof(cd0, csc);
+        int2 cin = inb_l[0];
+#pragma unroll
+        for (int t = 0; t < 64; ++t) {
+            int4 fd0 = make_int4(0, 0, 0, 0);
+            if (t + 2 < 64) fd0 = *(const int4*)(rb + (t + 2) * LY::DS);
+            int nsc[K];
+            int2 nin = make_int2(0, 0);
+            if (t + 1 < 64) {
+                ld_prof(nd0, nsc);
+                nin = inb_l[t + 1];
+            }
+            const int4 ds0 = cd0;
+            // a segment's first lane takes its own pair's boundary
+            int hl0 = shr1(cin.x, Hout), il0 = shr1(cin.y, Iout);
+            hl0 = first ? cin.x : hl0;
+            il0 = first ? cin.y : il0;
+            const int z = ds0.y;
+            int Hn[K], In[K], Dn[K], An[K], Bn[K], Cn[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const int L0 = c ? Hn[c - 1] : hl0;
+                const int IL = c ? In[c - 1] : il0;
+                const int L1 = c ? h1[c - 1] : hl1;
+                const int L3 = c ? h3[c - 1] : hl3;
+                const int D = imax(h3[c] - cq, d3[c]) - ce;
+                const int I = imax(L0 - cq, IL) - ce;
+                const int M = L3 + csc[c];
+                int pf = 0;
+                if (!NOF) {
+                    pf = imax(L1, h1[c]) - cf;
+                    asm("" : "+v"(pf));
+                }
+                int H;
+                if (!NOI) {
+                    const int A = imax(h1[c] - ddm1, a1[c]);
+                    const int B = imax(L1 - dd0, b1[c]);
+                    const int C = imax(L1 - ds0.z, c1[c]);
+                    An[c] = A; Bn[c] = B; Cn[c] = C;
+                    const int x = imax3(D, A - ds0.w, B - aam2);
+                    if (!NOF) H = imax3(x, imax3(C - aam1, pf, fp[c]), imax3(M, I, z));
+                    else H = imax3(x, imax3(C - aam1, M, I), z);
+                } else {
+                    if (!NOF) H = imax(imax3(D, pf, fp[c]), imax3(M, I, z));
+                    else H = imax(imax3(D, M, I), z);
+                }
+                if (!NOF) fp[c] = pf;
+                Hn[c] = H; In[c] = I; Dn[c] = D;
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c) bk[c] = imax(bk[c], (Hn[c] << 6) | (63 - t));
+            hl3 = hl2; hl2 = hl1; hl1 = hl0;
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                h3[c] = h2[c]; h2[c] = h1[c]; h1[c] = Hn[c];
+                d3[c] = d2[c]; d2[c] = d1[c]; d1[c] = Dn[c];
+                if (!NOI) { a1[c] = An[c]; b1[c] = Bn[c]; c1[c] = Cn[c]; }
+            }
+            ddm1 = dd0; dd0 = ds0.z; aam2 = aam1; aam1 = ds0.w;
+            Hout = Hn[K - 1];
+            Iout = In[K - 1];
+            cd0 = nd0; nd0 = fd0;
+#pragma unroll
+            for (int c = 0; c < K; ++c) csc[c] = nsc[c];
+            cin = nin;
+            if (MPG_STEP_BARRIER) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const int v = bk[c] >> 6, tt = 63 - (bk[c] & 63);
+            if (v > best[c]) { best[c] = v; bstep[c] = ch * 64 + tt; }
+            bk[c] = INT_MIN;
+        }
+    }
+
+    // each pair's best cell over its own lanes, folded into the pair
+    uint64_t key = 0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const int row = bstep[c] - kk, col = col0 + c;
+        if (col <= m_l && row >= 0 && row <= n_l && best[c] > UNREACH) {
+            const uint64_t k2 = end_key(best[c], row, col);
+            key = k2 > key ? k2 : key;
+        }
+    }
+    const uint64_t keyA = wave_max_u64(sg ? 0 : key), keyB = wave_max_u64(sg ? key : 0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const PairJob& J = q ? JB : JA;
+        PairState* ps = pst + (q ? jb : ja);
+        const unsigned long long k = q ? keyB : keyA;
+        const bool solo = J.nstrips == 1;
+        int done = 0;
+        if (!solo) {
+            if (lane == 0) {
+                if (failed) atomicMax(&ps->bad, 1);
+                else if (k) atomicMax(&ps->key, k);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            if (lane == 0)
+                done = __hip_atomic_fetch_add(&ps->done, 1, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+            done = __builtin_amdgcn_readfirstlane(done);
+        }
+        if (done == J.nstrips - 1) {
+            const unsigned long long kf =
+                solo ? k : __hip_atomic_load(&ps->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool bad =
+                solo ? failed : __builtin_amdgcn_readfirstlane(ld_dev(&ps->bad)) != 0;
+            const uint32_t khi = __builtin_amdgcn_readfirstlane((uint32_t)(kf >> 32));
+            const uint32_t klo = __builtin_amdgcn_readfirstlane((uint32_t)kf);
+            mpg_dev_result R;
+            local_record(R, J, ((unsigned long long)khi << 32) | klo, bad);
+            if (lane == 0) publish(sink.out + J.res, R, sink.system);
+        }
+    }
+}
+
 // The DP kernel.  Persistent single-wavefront workgroups take (pair, strip)
 // work items from one queue ordered longest pair first, strips in order.  A
 // strip streams its left boundary (H and I of the previous strip's last
@@ -277,7 +587,10 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
           int* __restrict__ qhead, PairState* __restrict__ pst, int* __restrict__ prog_g,
           const uint8_t* __restrict__ prot, const uint8_t* __restrict__ desc,
           int2* __restrict__ bnd, uint8_t* __restrict__ tbbuf, DpSink sink, DevParams P) {
-    using LY = LdsLayout<K, TB>;
+    // score-only LOCAL launches also run lane-segment items (two pairs' last
+    // strips in one wavefront)
+    constexpr bool SEGOK = !TB && MODE == MPG_LOCAL && !PRO;
+    using LY = LdsLayout<K, TB, SEGOK>;
     // the mixed variant runs EXTEND and fixed-end pairs (per-pair modes)
     constexpr bool MIXED = MODE == kModeMixed;
     constexpr int SM = MIXED ? (int)MPG_GLOBAL : MODE;  // mode of the sentinels and the floor
@@ -331,6 +644,13 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         const int it = __builtin_amdgcn_readfirstlane(atomicAdd(qhead, lane == 0 ? 1 : 0));
         if (it >= nitems) break;
         const int2 item = items[it];
+        if constexpr (SEGOK) {
+            if (item.y < 0) {
+                seg_item<K, NOI, NOF>(item, jobs, pst, prog_g, prot, desc, bnd, sink, P, smem,
+                                      smat, saa);
+                continue;
+            }
+        }
         const PairJob J = jobs[item.x];
         const int strip = item.y;
         const int n = J.n, m = J.m;
@@ -906,7 +1226,7 @@ hipError_t launch_dp_t(hipStream_t s, int ncu, const DevParams& P, const PairJob
                        const DpSink& sink) {
     const bool noi = (P.flags & MPG_NO_INTRON) != 0;
     const bool nof = (P.flags & MPG_NO_FRAMESHIFT) != 0;
-    const size_t lds = (size_t)LdsLayout<K, TB>::WAVE;
+    const size_t lds = (size_t)LdsLayout<K, TB, !TB && MODE == MPG_LOCAL && !PRO>::WAVE;
     dim3 b(64);
     // persistent grid: as many waves as ncu compute units hold at once for
     // this kernel, never more than there are items

@@ -224,6 +224,12 @@ struct Group {
 
 struct Plan {
     std::vector<int2> items;  // work items of every group, group after group
+    // lane-segment packs: per job, the partner whose last strip shares its
+    // wavefront (-1: none), and per job whether it carries the pack item
+    std::vector<int32_t> seg_mate;
+    std::vector<uint8_t> seg_emit;
+    std::vector<int32_t> seg_key;  // per job: pack class and lanes, or -1
+    std::vector<std::pair<int64_t, int32_t>> seg_cand;
     // planning scratch: per job group key, traceback and strips; the queue
     // orders and the sort's buffers
     std::vector<uint32_t> ginfo;
@@ -318,7 +324,10 @@ int env_int(const char* name) {
 // Debug overrides are read once per call (getenv per pair is too slow).
 struct Overrides {
     int K = 0, K16 = 0;
-    Overrides() : K(env_int("MPG_FORCE_K")), K16(env_int("MPG_FORCE_K16")) {}
+    bool no_seg = false;  // MPG_NO_SEG_PACK=1: every last strip in a wavefront of its own
+    Overrides()
+        : K(env_int("MPG_FORCE_K")), K16(env_int("MPG_FORCE_K16")),
+          no_seg(env_int("MPG_NO_SEG_PACK") != 0) {}
 };
 
 // Strip widths chosen by mpg_autotune from timed runs (0: not tuned).
@@ -492,12 +501,16 @@ void sort_by_key(std::vector<std::pair<int64_t, int32_t>>& v, bool descending,
     };
     const uint64_t span = (uint64_t)(hi - lo);
     tmp.resize(v.size());
-    cnt.resize(65537);
-    for (int sh = 0; sh < 64 && (span >> sh) != 0; sh += 16) {
+    // 16-bit digits for large inputs, 8-bit ones below 16k entries (where
+    // clearing and scanning 65,536 counters per pass would dominate)
+    const int bits = v.size() < 16384 ? 8 : 16;
+    const uint64_t mask = (1u << bits) - 1;
+    cnt.resize((size_t)mask + 2);
+    for (int sh = 0; sh < 64 && (span >> sh) != 0; sh += bits) {
         std::fill(cnt.begin(), cnt.end(), 0u);
-        for (const auto& e : v) ++cnt[((digit_key(e.first) >> sh) & 0xFFFF) + 1];
-        for (int d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
-        for (const auto& e : v) tmp[cnt[(digit_key(e.first) >> sh) & 0xFFFF]++] = e;
+        for (const auto& e : v) ++cnt[((digit_key(e.first) >> sh) & mask) + 1];
+        for (uint64_t d = 0; d <= mask; ++d) cnt[d + 1] += cnt[d];
+        for (const auto& e : v) tmp[cnt[(digit_key(e.first) >> sh) & mask]++] = e;
         v.swap(tmp);
     }
 }
@@ -544,6 +557,13 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     // per job: group key << 24 | traceback << 23 | strips (a compact copy for
     // the passes in queue order, which visit the jobs out of order)
     P.ginfo.resize(cnt);
+    P.seg_key.assign(cnt, -1);
+    // lanes the last strip of a pair needs
+    auto last_lanes = [](const PairJob& J) {
+        if (J.nstrips == 1) return J.m / J.K + 1;
+        return (J.m + 1 - (J.nstrips - 1) * 64 * J.K + J.K - 1) / J.K;
+    };
+    const bool seg_on = !ov.no_seg && !cfg.pro && cnt < (1 << 24);
     for (int32_t k = 0; k < cnt; ++k) {
         const mpg_seg& s = segs[idx[k]];
         PairJob& J = P.jobs[k];
@@ -598,6 +618,14 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         J.prog_off = (int32_t)P.nprog;
         P.nprog += J.nstrips;
         P.ginfo[k] = (uint32_t)gkey(J) << 24 | (uint32_t)(J.tb ? 1 : 0) << 23 | (uint32_t)J.nstrips;
+        // lane-segment class (width, chunks), then lanes descending; a pair
+        // has fewer than 2^15 chunks (genome rows are below 2^21)
+        P.seg_key[k] = -1;
+        if (seg_on && J.status == MPG_OK && !J.tb && gmode(J.mode) == MPG_LOCAL) {
+            const int u = last_lanes(J);
+            if (u >= 1 && u <= 63)
+                P.seg_key[k] = ((K == 1 ? 0 : K == 2 ? 1 : 2) << 21) | (J.nchunks << 6) | (63 - u);
+        }
         bysize.push_back({(int64_t)J.nstrips * J.nchunks, k});
     }
     // batches: longest pair first (the last pairs to finish are the short
@@ -618,6 +646,46 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         gcount[gidx[key]] += gi & 0x7FFFFF;
         nwalk += (gi >> 23) & 1;
     }
+    // Lane-segment packs.  A pair's last strip fills only the lanes its
+    // remaining columns need and idles the rest for all its steps.  Two
+    // LOCAL score-only pairs of one width whose strips run the same number of
+    // chunks and whose last strips need at most 64 lanes together share one
+    // wavefront: the pair with more lanes first, the other from lane `split`.
+    // Within each (width, chunks) class the widest remaining last strip is
+    // matched with the narrowest that fits.  The pack's item goes where the
+    // later pair's last strip would be, so it follows both pairs' other
+    // strips in the queue and its waits point to items taken earlier.
+    P.seg_mate.assign(cnt, -1);
+    P.seg_emit.assign(cnt, 0);
+    if (seg_on) {
+        std::vector<std::pair<int64_t, int32_t>>& cand = P.seg_cand;
+        cand.clear();
+        for (size_t q = 0; q < bysize.size(); ++q) {
+            const int32_t key = P.seg_key[bysize[q].second];
+            if (key >= 0) cand.push_back({key, (int32_t)q});
+        }
+        sort_by_key(cand, false, P.sort_tmp, P.sort_cnt);
+        for (size_t r0 = 0; r0 < cand.size();) {
+            size_t r1 = r0;
+            while (r1 < cand.size() && (cand[r1].first >> 6) == (cand[r0].first >> 6)) ++r1;
+            size_t lo = r0, hi = r1;  // [lo, hi): widest first
+            while (hi - lo >= 2) {
+                const int ua = 63 - (int)(cand[lo].first & 63);
+                const int ub = 63 - (int)(cand[hi - 1].first & 63);
+                if (ua + ub <= 64) {
+                    const int32_t qa = cand[lo].second, qb = cand[hi - 1].second;
+                    const int32_t a = bysize[qa].second, b = bysize[qb].second;
+                    P.seg_mate[a] = b;
+                    P.seg_mate[b] = a;
+                    P.seg_emit[qa > qb ? a : b] = 1;
+                    --gcount[gidx[P.ginfo[a] >> 24]];
+                    --hi;
+                }
+                ++lo;
+            }
+            r0 = r1;
+        }
+    }
     size_t total = 0;
     for (size_t g = 0; g < P.groups.size(); ++g) {
         P.groups[g].off = total;
@@ -629,7 +697,19 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         const uint32_t gi = P.ginfo[e.second];
         Group& g = P.groups[gidx[gi >> 24]];
         const int ns = (int)(gi & 0x7FFFFF);
-        for (int st = 0; st < ns; ++st) P.items[g.off + g.cnt++] = make_int2(e.second, st);
+        const int32_t mate = P.seg_mate[e.second];
+        for (int st = 0; st < ns; ++st) {
+            if (st == ns - 1 && mate >= 0) {
+                if (!P.seg_emit[e.second]) continue;
+                // the pair with more lanes in [0, split)
+                int32_t a = e.second, b = mate;
+                const int ua = 63 - (P.seg_key[a] & 63), ub = 63 - (P.seg_key[b] & 63);
+                if (ua < ub) std::swap(a, b);
+                P.items[g.off + g.cnt++] = make_int2(a, -1 - ((b << 6) | (ua < ub ? ub : ua)));
+                continue;
+            }
+            P.items[g.off + g.cnt++] = make_int2(e.second, st);
+        }
         if ((gi >> 23) & 1) P.walk.push_back(e.second);
     }
     // int16 pairs: neighbours in size order share a pack
@@ -705,7 +785,7 @@ struct mpg_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pre, ev_dp, ev_walk;
     std::vector<hipEvent_t> ev_pool;
     double t_pre = 0, t_dp = 0, t_walk = 0, t_host = 0;
-    uint64_t n_dp = 0, n_calls = 0, n_i16 = 0, n_cells = 0;
+    uint64_t n_dp = 0, n_calls = 0, n_i16 = 0, n_cells = 0, n_seg = 0;
 
     // ---- serving
     std::mutex mu;
@@ -757,6 +837,7 @@ struct Timer {
     double* host_ms;  // wall time spent planning and enqueuing on the host
     uint64_t* i16 = nullptr;  // pairs run in the int16 kernel
     uint64_t* cells = nullptr;  // DP cells (n*m) of the pairs run
+    uint64_t* segs = nullptr;   // lane-segment packs run
     hipEvent_t open[3] = {nullptr, nullptr, nullptr};
     hipEvent_t get() {
         hipEvent_t e = nullptr;
@@ -863,6 +944,8 @@ int prepare(hipStream_t st, Workspace& ws, const mpg_params* p, const uint8_t* d
     X.npacks = npacks;
     if (tm && tm->i16)
         for (const PackJob& Q : P.packs) *tm->i16 += Q.b >= 0 ? 2 : 1;
+    if (tm && tm->segs)
+        for (const int2& it : P.items) *tm->segs += it.y < 0 ? 1 : 0;
     if (tm && tm->cells)
         for (const PairJob& J : P.jobs)
             if (J.status == MPG_OK) *tm->cells += (uint64_t)J.n * (uint64_t)J.m;
@@ -1277,7 +1360,7 @@ int mpg_align_batch_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
-             &ctx->n_cells};
+             &ctx->n_cells, &ctx->n_seg};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -1995,7 +2078,7 @@ int mpg_align_batch(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs, in
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
-             &ctx->n_cells};
+             &ctx->n_cells, &ctx->n_seg};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -2025,7 +2108,7 @@ int mpg_align_chains_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_pro
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
-             &ctx->n_cells};
+             &ctx->n_cells, &ctx->n_seg};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -2093,7 +2176,7 @@ int mpg_align_chains(mpg_ctx* ctx, const mpg_params* p, const mpg_chain* chains,
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
-             &ctx->n_cells};
+             &ctx->n_cells, &ctx->n_seg};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -2188,7 +2271,7 @@ int mpg_align_profiles_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_p
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
-             &ctx->n_cells};
+             &ctx->n_cells, &ctx->n_seg};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -2229,7 +2312,7 @@ int mpg_align_profiles(mpg_ctx* ctx, const mpg_params* p, const mpg_profile_pair
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
-             &ctx->n_cells};
+             &ctx->n_cells, &ctx->n_seg};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -2350,7 +2433,7 @@ int mpg_rescore_spliced_dev(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
-             &ctx->n_cells};
+             &ctx->n_cells, &ctx->n_seg};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -2405,7 +2488,7 @@ int mpg_rescore_spliced(mpg_ctx* ctx, const mpg_params* p, const mpg_pair* pairs
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     hipSetDevice(ctx->device);
     Timer tm{{&ctx->ev_pre, &ctx->ev_dp, &ctx->ev_walk}, &ctx->ev_pool, &ctx->t_host, &ctx->n_i16,
-             &ctx->n_cells};
+             &ctx->n_cells, &ctx->n_seg};
     ctx->n_calls++;
     RunCfg cfg;
     cfg.tb_budget = ctx->tb_budget;
@@ -2810,9 +2893,10 @@ int mpg_get_timing(mpg_ctx* ctx, mpg_timing* t, int reset) {
     t->host_ms = ctx->t_host;
     t->i16_pairs = ctx->n_i16;
     t->cells = ctx->n_cells;
+    t->seg_packs = ctx->n_seg;
     if (reset) {
         ctx->t_pre = ctx->t_dp = ctx->t_walk = ctx->t_host = 0;
-        ctx->n_dp = ctx->n_calls = ctx->n_i16 = ctx->n_cells = 0;
+        ctx->n_dp = ctx->n_calls = ctx->n_i16 = ctx->n_cells = ctx->n_seg = 0;
     }
     return MPG_OK;
 }

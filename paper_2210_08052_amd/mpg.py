@@ -108,7 +108,8 @@ class mpg_timing(ctypes.Structure):
     _fields_ = [("prepass_ms", ctypes.c_double), ("dp_ms", ctypes.c_double),
                 ("walk_ms", ctypes.c_double), ("dp_spans", ctypes.c_uint64),
                 ("calls", ctypes.c_uint64), ("host_ms", ctypes.c_double),
-                ("i16_pairs", ctypes.c_uint64), ("cells", ctypes.c_uint64)]
+                ("i16_pairs", ctypes.c_uint64), ("cells", ctypes.c_uint64),
+                ("seg_packs", ctypes.c_uint64)]
 
 
 class mpg_tuning(ctypes.Structure):

@@ -197,6 +197,55 @@ def test_serving_matches_batch(ctx):
         assert got[k]["t_done_ns"] >= got[k]["t_arrive_ns"] > 0
 
 
+# ---- lane-segment packs: two pairs' last strips in one wavefront
+
+def _seg_pairs(K, seed, n_dna=3000, count=48):
+    """Planted genes whose last strips need at most half a wavefront's lanes
+    (1, 2 or 3 strips of 64*K columns), every region padded to one length so
+    that the strips run the same number of chunks."""
+    SW = 64 * K
+    rng = np.random.default_rng(seed)
+    lengths = []
+    for i in range(count):
+        last = int(rng.integers(1, 32 * K + 1))  # columns 0..m of the last strip
+        lengths.append((i % 3) * SW + last - 1 if (i % 3) else max(1, last - 1))
+    out = []
+    for q in W.self_pairs(seed, lengths):
+        pad = n_dna - len(q.dna)
+        assert pad >= 0
+        tail = "".join(rng.choice(list("ACGT"), size=pad)).encode()
+        out.append((q.prot, q.dna + tail))
+    return out
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_lane_segment_packs(ctx, K, monkeypatch):
+    """Pairs of one region length whose last strips need few lanes: two
+    pairs' last strips share a wavefront (pairs of one strip, and pairs whose
+    last strip streams its boundary from the previous strip); the results
+    equal those of the same call without packs and the oracle's, with and
+    without the intron and frameshift terms."""
+    monkeypatch.setenv("MPG_FORCE_K", str(K))
+    pairs = _seg_pairs(K, 900 + K)
+    for flags in (0, 3):
+        print("case K=%d flags=%d" % (K, flags), flush=True)
+        g, o = scorings(0, flags)
+        ctx.enable_timing(True)
+        ctx.timing(reset=True)
+        got = compare(ctx, pairs, g, o, False, label="seg K=%d" % K)
+        packs = ctx.timing(reset=True)["seg_packs"]
+        ctx.enable_timing(False)
+        assert packs >= len(pairs) // 4, packs
+        monkeypatch.setenv("MPG_NO_SEG_PACK", "1")
+        ctx.enable_timing(True)
+        ref = ctx.align_batch([(p, d, False) for p, d in pairs], g)
+        assert ctx.timing(reset=True)["seg_packs"] == 0
+        ctx.enable_timing(False)
+        monkeypatch.delenv("MPG_NO_SEG_PACK")
+        for k in range(len(pairs)):
+            assert key_gpu(got[k], False) == key_gpu(ref[k], False), k
+
+
 # ---- lane-packed int16 kernel (LOCAL, score-only, two pairs per wavefront)
 
 def _i16_run(ctx, pairs, g, o, expect_i16):
