@@ -478,7 +478,7 @@ typedef struct {
     int32_t len;
 } mpg_chain_out;
 
-#define MPG_MAX_ANCHORS 6144 /* anchors of one set */
+#define MPG_MAX_ANCHORS 65536 /* anchors of one set */
 
 /*
  * Chain nsets anchor sets on the GPU.  anchors: 2 int32 per anchor (x, y), all

@@ -203,16 +203,24 @@ struct ChainSetJob {
     int32_t id;      // the set's index in the call (its ntop and top slots)
     int32_t _pad;
 };
-// LDS bytes per anchor of the chaining kernel: f (8) and the used flag (1),
-// plus, when they fit in 64 KB, the anchor (8) and its predecessor (4).
-constexpr int kChainBaseBytes = 9;
-constexpr int kChainStageBytes = 21;
+// LDS of the chaining kernel (at most 64 KB): the reduction slots, then per
+// anchor the used flag (1 byte), f (8) when it fits, and the anchor (8) and
+// its predecessor (4) when those fit too.
+constexpr int kChainRedBytes = 64;
+constexpr int kChainLdsBytes = 65536;
 struct ChainCfg {
     int32_t k, G, binned, max_chains;
     int32_t max_n;   // largest set of the launch (sizes the LDS)
     int32_t stage;   // 1: anchors and predecessors also staged in LDS
+    int32_t f_lds;   // 1: f in LDS; 0: f read and written in the f output
+    int32_t waves;   // wavefronts per set: 1 or 4
     double beta;
 };
+inline size_t chain_lds_bytes(const ChainCfg& c) {
+    const size_t n = (size_t)c.max_n;
+    return (kChainRedBytes + (c.f_lds ? 8 * n : 0) + (c.stage ? 12 * n : 0) + n + 15) &
+           ~(size_t)15;
+}
 struct ChainRec {    // one extracted chain (scratch)
     double score;
     int32_t first, len;

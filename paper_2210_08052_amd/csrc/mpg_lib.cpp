@@ -1970,7 +1970,12 @@ int chain_sets_dev(hipStream_t st, Workspace& ws, const mpg_chaining_params* cp,
     cfg.binned = cp->binned;
     cfg.max_chains = cp->max_chains;
     cfg.max_n = max_n;
-    cfg.stage = kChainStageBytes * (int64_t)max_n + 16 <= 65536 ? 1 : 0;
+    // f in LDS when it fits beside the used flags; anchors and predecessors
+    // too when they also fit; four wavefronts per set once the largest set's
+    // candidate loops are long enough to share
+    cfg.f_lds = kChainRedBytes + 9 * (int64_t)max_n + 16 <= kChainLdsBytes ? 1 : 0;
+    cfg.stage = cfg.f_lds && kChainRedBytes + 21 * (int64_t)max_n + 16 <= kChainLdsBytes ? 1 : 0;
+    cfg.waves = max_n >= 512 ? 4 : 1;
     cfg.beta = cp->beta;
     ChainRec* recs = (ChainRec*)((uint8_t*)ws.cset.p + ((jb + 15) & ~(size_t)15));
     if (launch_chain(st, (const ChainSetJob*)ws.cset.p, nsets, (const int2*)d_anchors, cfg, d_f,

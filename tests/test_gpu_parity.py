@@ -833,15 +833,20 @@ def test_chaining_sets(ctx, binned):
 
 
 def test_chaining_limits(ctx):
+    """A set too large for f in LDS (9,000 anchors: f in HBM, four
+    wavefronts per set) beside a small one; a set beyond MPG_MAX_ANCHORS
+    reports MPG_E_RANGE; unsorted sets and bad parameters fail the call."""
     rng = np.random.default_rng(3)
-    big = rng.integers(0, 50000, size=(6144, 2))
+    big = rng.integers(0, 80000, size=(9000, 2))
     big = big[np.lexsort((big[:, 1], big[:, 0]))]
-    over = np.zeros((6145, 2), np.int32)
-    over[:, 0] = np.arange(6145)
+    small = np.array([[3, 1], [3, 2], [40, 9], [41, 10]], np.int32)
+    over = np.zeros((65537, 2), np.int32)
+    over[:, 0] = np.arange(65537)
     cp = mpg.chaining_params(binned=0)
-    got = ctx.chain_anchors([big.astype(np.int32), over], cp)
+    got = ctx.chain_anchors([big.astype(np.int32), small, over], cp)
     _check_chaining(got[0], big, cp.k, cp.beta, cp.G, False, cp.max_chains)
-    assert got[1]["status"] == mpg.MPG_E_RANGE
+    _check_chaining(got[1], small, cp.k, cp.beta, cp.G, False, cp.max_chains)
+    assert got[2]["status"] == mpg.MPG_E_RANGE
     with pytest.raises(RuntimeError):
         ctx.chain_anchors([np.array([[5, 1], [4, 2]], np.int32)], cp)
     with pytest.raises(RuntimeError):
