@@ -607,24 +607,31 @@ void mpg_plan_destroy(mpg_plan *plan);
 
 /* ---- autotuning ----------------------------------------------------------- */
 
-/* DP rates (GCUPS) of a sample batch at each kernel width, and the widths
- * chosen. */
+/* DP rates (GCUPS) of a sample batch under each planning choice tried, and
+ * the choices kept. */
 typedef struct {
-    double gcups[3];     /* int32 kernels at 1, 2, 4 columns per lane */
+    double gcups[3];     /* int32 kernels at 1, 2, 4 columns per lane (every pair) */
     double i16_gcups[2]; /* int16 lanes at 1, 2 columns per lane (0 if not tried) */
     int32_t K, K16;      /* the widths this context uses from now on */
-    int32_t _pad[2];
+    int32_t narrow_cols; /* pairs of at most this many columns (residues + 1) run one
+                            column per lane */
+    int32_t seg_packs;   /* 1: two pairs' ragged last strips may share a wavefront */
+    double narrow_gcups[3]; /* at width K with the cutover at 64, 128, 192 columns
+                               (0 if not tried: at K = 1 it changes nothing) */
+    double seg_gcups[2];    /* at width K and the kept cutover, packs off and on */
 } mpg_tuning;
 
 /*
- * Run a sample of the caller's workload at every kernel width and keep the
- * fastest for the batch calls of this context.  The sample is given like
+ * Run a sample of the caller's workload at every kernel width, then, at the
+ * fastest width, with the narrow-pair cutover at 64, 128 and 192 columns and
+ * with lane-segment packs off and on, and keep the fastest choices for the
+ * batch calls of this context.  The sample is given like
  * mpg_align_batch_dev's input (letters in device memory, n segments, params
  * p; MPG_ALLOW_I16 in p also tunes the int16 width); with n = 0 a built-in
  * sample is used (1,024 pairs of 511 residues x 4,096 nucleotides, half with
- * traceback; p, d_prot, d_dna and segs may then be NULL).  Each width runs
- * twice and the second run's DP time counts.  Results never depend on the
- * width.  Serving uses its own width (the narrowest, for the shortest per-pair
+ * traceback; p, d_prot, d_dna and segs may then be NULL).  Each choice runs
+ * twice and the second run's DP time counts.  Results never depend on these
+ * choices.  Serving uses its own width (the narrowest, for the shortest per-pair
  * critical path).  Call it while no other work of the context is in flight.
  * out may be NULL.
  */

@@ -330,10 +330,12 @@ struct Overrides {
           no_seg(env_int("MPG_NO_SEG_PACK") != 0) {}
 };
 
-// Strip widths chosen by mpg_autotune from timed runs (0: not tuned).
+// Planning choices made by mpg_autotune from timed runs (0: not tuned).
 struct Tuning {
-    int K = 0;    // int32 kernels
-    int K16 = 0;  // int16 kernel
+    int K = 0;       // int32 kernels
+    int K16 = 0;     // int16 kernel
+    int narrow = 0;  // pairs of at most this many columns run one column per lane (64)
+    int seg = -1;    // lane-segment packs: 1 on, 0 off, -1 not tuned (on)
 };
 
 // Columns per lane: one width for the pairs of a call wider than 64 columns
@@ -563,7 +565,11 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         if (J.nstrips == 1) return J.m / J.K + 1;
         return (J.m + 1 - (J.nstrips - 1) * 64 * J.K + J.K - 1) / J.K;
     };
-    const bool seg_on = !ov.no_seg && !cfg.pro && cnt < (1 << 24);
+    const bool seg_pref = !(cfg.tune && cfg.tune->seg == 0);
+    const bool seg_on = seg_pref && !ov.no_seg && !cfg.pro && cnt < (1 << 24);
+    // pairs this narrow run one column per lane: a single strip of at most 64
+    // lanes by default; the autotuner may move the cutover
+    const int narrow = cfg.tune && cfg.tune->narrow > 0 ? cfg.tune->narrow : 64;
     for (int32_t k = 0; k < cnt; ++k) {
         const mpg_seg& s = segs[idx[k]];
         PairJob& J = P.jobs[k];
@@ -586,7 +592,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         const int nn = std::max(0, J.n), mm = std::max(0, J.m);
         // a pair whose columns fit one strip of 64 takes one column per lane:
         // wider lanes would only add idle columns to every step
-        int K = (mm + 1 <= 64 && !ov.K && !cfg.force_K) ? 1 : kc.K[want_tb ? 1 : 0];
+        int K = (mm + 1 <= narrow && !ov.K && !cfg.force_K) ? 1 : kc.K[want_tb ? 1 : 0];
         if (cfg.pro && K > 2) K = 2;  // profile kernels come in widths 1 and 2
         J.K = K;
         const int nsteps = pair_nsteps(nn, mm, K);
@@ -2699,7 +2705,9 @@ int mpg_autotune(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot, const
         return rc;
     }
     // DP time of the sample at one width (the second of two runs)
-    auto run = [&](int K, int K16, double& ms_out) -> int {
+    // DP time of the sample (the second of two runs) at one width (K > 0, all
+    // pairs), or with the planning choices of t (K = 0)
+    auto run = [&](int K, int K16, double& ms_out, const Tuning* t = nullptr) -> int {
         std::vector<std::pair<hipEvent_t, hipEvent_t>> e3[3];
         std::vector<hipEvent_t> pool;
         double host = 0;
@@ -2710,6 +2718,7 @@ int mpg_autotune(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot, const
         cfg.ncu = g_num_cu;
         cfg.force_K = K;
         cfg.force_K16 = K16;
+        cfg.tune = t;
         for (int rep = 0; rep < 2; ++rep) {
             cfg.tm = rep ? &tm : nullptr;
             const int r = run_dev_waves(st, ws, &prm, d_prot, d_dna, sg.data(), n,
@@ -2746,11 +2755,42 @@ int mpg_autotune(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot, const
             tu.K = Ks[q];
         }
     }
+    // at that width: the narrow-pair cutover (pairs of at most 64, 128 or 192
+    // columns in strips of one column per lane: the one-wavefront strip of a
+    // narrow pair against more, cheaper strips), then lane-segment packs on
+    // and off
+    tu.narrow = 64;
+    tu.seg = 1;
+    double best_c = 0;
+    const int cuts[3] = {64, 128, 192};
+    for (int q = 0; q < 3 && rc == MPG_OK && (q == 0 || tu.K > 1); ++q) {
+        Tuning t = tu;
+        t.narrow = cuts[q];
+        double ms = 0;
+        rc = run(0, 2, ms, &t);
+        if (rc != MPG_OK || ms <= 0) break;
+        res.narrow_gcups[q] = cells / (ms * 1e-3) / 1e9;
+        if (best_c == 0 || ms < best_c) {
+            best_c = ms;
+            tu.narrow = cuts[q];
+        }
+    }
+    if (rc == MPG_OK && best_c > 0) {
+        Tuning t = tu;
+        t.seg = 0;
+        double ms = 0;
+        rc = run(0, 2, ms, &t);
+        if (rc == MPG_OK && ms > 0) {
+            res.seg_gcups[0] = cells / (ms * 1e-3) / 1e9;
+            res.seg_gcups[1] = cells / (best_c * 1e-3) / 1e9;
+            if (ms < best_c) tu.seg = 0;
+        }
+    }
     if (rc == MPG_OK && (prm.flags & MPG_ALLOW_I16)) {
         double b16 = 0;
         for (int q = 0; q < 2 && rc == MPG_OK; ++q) {
             double ms = 0;
-            rc = run(tu.K, q + 1, ms);
+            rc = run(0, q + 1, ms, &tu);
             if (rc != MPG_OK || ms <= 0) break;
             res.i16_gcups[q] = cells / (ms * 1e-3) / 1e9;
             if (b16 == 0 || ms < b16) {
@@ -2765,6 +2805,8 @@ int mpg_autotune(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot, const
     ctx->tune = tu;
     res.K = tu.K;
     res.K16 = tu.K16;
+    res.narrow_cols = tu.narrow;
+    res.seg_packs = tu.seg;
     if (out) *out = res;
     return MPG_OK;
 }

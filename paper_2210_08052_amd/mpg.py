@@ -114,7 +114,9 @@ class mpg_timing(ctypes.Structure):
 
 class mpg_tuning(ctypes.Structure):
     _fields_ = [("gcups", ctypes.c_double * 3), ("i16_gcups", ctypes.c_double * 2),
-                ("K", ctypes.c_int32), ("K16", ctypes.c_int32), ("_pad", ctypes.c_int32 * 2)]
+                ("K", ctypes.c_int32), ("K16", ctypes.c_int32), ("narrow_cols", ctypes.c_int32),
+                ("seg_packs", ctypes.c_int32), ("narrow_gcups", ctypes.c_double * 3),
+                ("seg_gcups", ctypes.c_double * 2)]
 
 
 SEG_DTYPE = np.dtype([("prot_off", "<i8"), ("dna_off", "<i8"), ("plen", "<i4"),
@@ -547,7 +549,9 @@ class Context:
                                     ctypes.c_void_p(d_dna), segs.ctypes.data_as(ctypes.c_void_p),
                                     len(segs), ctypes.byref(t))
         check(st, "mpg_autotune")
-        return {"gcups": list(t.gcups), "i16_gcups": list(t.i16_gcups), "K": t.K, "K16": t.K16}
+        return {"gcups": list(t.gcups), "i16_gcups": list(t.i16_gcups), "K": t.K, "K16": t.K16,
+                "narrow_cols": t.narrow_cols, "seg_packs": t.seg_packs,
+                "narrow_gcups": list(t.narrow_gcups), "seg_gcups": list(t.seg_gcups)}
 
     def plan(self, p: mpg_params, d_prot, d_dna, segs: np.ndarray, d_out, d_ops, ops_cap: int):
         """mpg_plan_create: a Plan bound to these device buffers."""

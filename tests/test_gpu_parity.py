@@ -427,15 +427,18 @@ def test_serving_results_arrive_per_pair():
 
 
 def test_autotune_keeps_results():
-    """mpg_autotune times every kernel width (built-in sample, then a sample of
-    the caller's pairs); the width it keeps changes only speed: results still
-    equal the oracle's."""
+    """mpg_autotune times every kernel width, then the narrow-pair cutover and
+    lane-segment packs at the fastest width (built-in sample, then a sample of
+    the caller's pairs); what it keeps changes only speed: results still equal
+    the oracle's."""
     import torch
     pairs = _pairs(4321, n=30, max_prot=600, max_dna=1500)
     with mpg.Context(0) as c:
         rates = c.autotune()
         print("autotune built-in", rates, flush=True)
         assert all(v > 0 for v in rates["gcups"]) and rates["K"] in (1, 2, 4)
+        assert rates["narrow_cols"] in (64, 128, 192) and rates["seg_packs"] in (0, 1)
+        assert rates["narrow_gcups"][0] > 0 and all(v > 0 for v in rates["seg_gcups"])
         g, o = scorings(0, 0)
         g.flags |= mpg.MPG_ALLOW_I16
         pb, db, segs = mpg.pack_pairs([(p, d, k % 2 == 0) for k, (p, d) in enumerate(pairs)])
