@@ -177,7 +177,11 @@ int mpg_params_check(const mpg_params *p, int32_t max_plen, int32_t max_dlen);
  * are borrowed for the call only.  out[k] receives pair k; its ops string is
  * owned by the library until mpg_result_release(ctx, out, n).  Per-pair
  * failures (MPG_E_RANGE, MPG_E_NOALN) are reported in out[k].status; the
- * call itself fails only for MPG_E_INVAL / MPG_E_NOMEM / MPG_E_DEVICE.
+ * call itself fails only for MPG_E_INVAL / MPG_E_NOMEM / MPG_E_DEVICE.  A
+ * strip whose wait for its left neighbour gives up (bounded, so that no
+ * kernel can hang) reports MPG_E_DEVICE for its pair, and for the pair whose
+ * last strip shares its wavefront, if any (two LOCAL pairs' ragged last
+ * strips may share one).
  */
 int mpg_align_batch(mpg_ctx *ctx, const mpg_params *p, const mpg_pair *pairs, int32_t n,
                     mpg_result *out);

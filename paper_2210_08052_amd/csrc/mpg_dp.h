@@ -157,8 +157,11 @@ __device__ __forceinline__ int wave_find_owner(const int64_t* __restrict__ start
 // Score-only layout (TB = false): plain values, descriptor {tr, z, r+d(i+1),
 // a(i)}; r+d(i), r+d(i-1), a(i-1), a(i-2) are carried in registers.
 // Traceback layout (TB = true): H is 16*H; I, D, A, B, C are 16*v + their
-// fixed nibble (13, 12, 7, 6, 5); descriptor {tr, 16z+15, 16(r+d(i-1))-7,
-// 16(r+d(i))-6, 16(r+d(i+1))-5, 16a(i), 16a(i-2), 16a(i-1)}.
+// fixed nibble (13, 12, 7, 6, 5); descriptor {tr, z+15, 5-16(r+d(i+1)),
+// 16a(i)}, the same rows carried: C opens at H - 16(r+d(i+1)) + 5, B at
+// H - 16(r+d(i)) + 6 (the previous row's field plus one), A at
+// H - 16(r+d(i-1)) + 7 (the field of two rows up plus two), one three-input
+// add each.
 // H winner codes: 0 start, 1 M, 2 I, 3 D, 4 F1, 5 F2, 6 G1, 7 G2, 8 A, 9 B,
 // 10 C; nibble = 15 - code.
 
@@ -168,7 +171,7 @@ __device__ __forceinline__ int wave_find_owner(const int64_t* __restrict__ start
 // publishes no boundary).
 template <int K, bool TB, bool SEG = false>
 struct LdsLayout {
-    static constexpr int DS = TB ? 32 : 16;    // descriptor bytes per row
+    static constexpr int DS = 16;              // descriptor bytes per row
     static constexpr int PS = TB ? 2 : 1;      // profile entry bytes
     static constexpr int SW = 64 * K;          // strip width
     static constexpr int RING = 128 * DS;      // two chunks of descriptors
@@ -187,6 +190,15 @@ struct Sentinel {
     static constexpr int NEG = floor_mode(MODE) ? (TB ? -(1 << 29) : -(1 << 25)) : -(1 << 30);
     static constexpr int UNREACH = floor_mode(MODE) ? NEG / 2 : -(1 << 29);
 };
+
+// a + b + k in one instruction (left to itself, the compiler shares b + k
+// between a lane's columns and spends two)
+template <int k>
+__device__ __forceinline__ int add3k(int a, int b) {
+    int r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "i"(k));
+    return r;
+}
 
 // acc = 2*acc + (diff < 0) in every lane, one funnel shift: the choice of a
 // gap or intron state, one bit per step, most recent step in bit 0.  diff =
@@ -287,27 +299,31 @@ __device__ __forceinline__ void local_record(mpg_dev_result& R, const PairJob& J
     }
 }
 
-// Two LOCAL score-only pairs' last strips on lane segments of one wavefront
-// (a strip that fills at most part of its lanes leaves the rest idle for all
-// its steps).  item = (pair A, -1 - (pair B << 6 | split)): pair A's last strip
-// in lanes [0, split), pair B's in [split, 64); both strips run the same
-// number of chunks.  Each lane works on its own pair's rows (the segment's
-// lane k at step s on row s - k), reads its pair's descriptors from that
-// pair's LDS ring and takes its left neighbour's H and I by the same DPP shift
-// as a whole-wave strip; the first lane of each segment takes them from its
-// pair's incoming boundary instead (one select per value and step).  A pair
-// of one strip starts from the -infinity column; otherwise its previous strip
-// streams the boundary through HBM as for any strip.
-template <int K, bool NOI, bool NOF>
+// Two LOCAL pairs' last strips on lane segments of one wavefront (a strip
+// that fills only part of its lanes leaves the rest idle for all its steps).
+// item = (pair A, -1 - (pair B << 6 | split)): pair A's last strip in lanes
+// [0, split), pair B's in [split, 64); both strips run the same number of
+// chunks.  Each lane works on its own pair's rows (the segment's lane k at
+// step s on row s - k), reads its pair's descriptors from that pair's LDS
+// ring and takes its left neighbour's H and I by the same DPP shift as a
+// whole-wave strip; the first lane of each segment takes them from its pair's
+// incoming boundary instead (one select per value and step).  A pair of one
+// strip starts from the -infinity column; otherwise its previous strip
+// streams the boundary through HBM as for any strip.  With traceback (batch
+// calls, walked afterwards by the walk kernel) each lane stores its direction
+// bits into its own pair's block of the strip at its lane within the
+// segment: the layout of a whole-wave strip.
+template <int K, bool TB, bool NOI, bool NOF>
 __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restrict__ jobs,
                                          PairState* __restrict__ pst, int* __restrict__ prog_g,
                                          const uint8_t* __restrict__ prot,
                                          const uint8_t* __restrict__ desc, int2* __restrict__ bnd,
-                                         const DpSink& sink, const DevParams& P, uint8_t* smem,
-                                         const int8_t* smat, const uint8_t* saa) {
-    using LY = LdsLayout<K, false, true>;
-    constexpr int NEG = Sentinel<MPG_LOCAL, false>::NEG;
-    constexpr int UNREACH = Sentinel<MPG_LOCAL, false>::UNREACH;
+                                         uint8_t* __restrict__ tbbuf, const DpSink& sink,
+                                         const DevParams& P, uint8_t* smem, const int8_t* smat,
+                                         const uint8_t* saa) {
+    using LY = LdsLayout<K, TB, true>;
+    constexpr int NEG = Sentinel<MPG_LOCAL, TB>::NEG;
+    constexpr int UNREACH = Sentinel<MPG_LOCAL, TB>::UNREACH;
     const int lane = threadIdx.x & 63;
     const int code = -1 - item.y;
     const int ja = item.x, jb = code >> 6, split = code & 63;
@@ -329,12 +345,22 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
     const int* progA = prog_g + JA.prog_off;
     const int* progB = prog_g + JB.prog_off;
     const bool leftA = stripA > 0, leftB = stripB > 0;
+    // traceback: this lane's direction-bit blocks (its pair's last strip)
+    uint8_t* tb_l = TB ? tbbuf + (sg ? JB.tb_off : JA.tb_off) +
+                             (int64_t)(sg ? stripB : stripA) * nchunks * (kTbBlockBytes * K)
+                       : nullptr;
     uint8_t* ringA = smem;
     uint8_t* ringB = smem + LY::RING2;
     uint8_t* prof = smem + LY::RING;
     int2* inbA = (int2*)(smem + LY::RING + LY::PROF);
     int2* inbB = (int2*)(smem + LY::RING + LY::PROF + LY::IN);
-    const int cq = P.q, ce = P.e, cf = P.f;
+    // penalties in the layout of the variant (as in the whole-wave strips)
+    const int cq = TB ? 16 * (P.q + P.e) - 13 : P.q;
+    const int cqD = TB ? 16 * (P.q + P.e) - 12 : P.q;
+    const int ce = TB ? 16 * P.e : P.e;
+    const int cf = TB ? 16 * P.f : P.f;
+    int cf11 = cf - 11, cf9 = cf - 9;
+    asm volatile("" : "+s"(cf11), "+s"(cf9));
     const int2 neg2 = make_int2(NEG, NEG);
 
     // profile of this lane's columns (its own pair's residues)
@@ -354,11 +380,16 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
         for (int tr = 0; tr < 25; ++tr) {
             const bool poison = pc < 0 || tr == 24;
             const int v = tr < 24 ? sv[tr < 24 ? tr : 0] : 0;
-            ((int8_t*)prof)[(c * 25 + tr) * 64 + lane] = (int8_t)(poison ? -128 : v);
+            if (TB)
+                ((int16_t*)prof)[(c * 25 + tr) * 64 + lane] =
+                    (int16_t)(poison ? -32768 : 16 * v + 14);
+            else
+                ((int8_t*)prof)[(c * 25 + tr) * 64 + lane] = (int8_t)(poison ? -128 : v);
         }
     }
     int h1[K], h2[K], h3[K], d1[K], d2[K], d3[K], a1[K], b1[K], c1[K];
     int best[K], bstep[K], bk[K], fp[K];
+    uint32_t nacc[K], xacc[5][K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         h1[c] = h2[c] = h3[c] = NEG;
@@ -367,7 +398,10 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
         best[c] = NEG;
         bstep[c] = 0;
         bk[c] = INT_MIN;
-        fp[c] = NEG - cf;
+        fp[c] = TB ? NEG - cf11 : NEG - cf;
+        nacc[c] = 0;
+#pragma unroll
+        for (int x = 0; x < 5; ++x) xacc[x][c] = 0;
     }
     int hl1 = NEG, hl2 = NEG, hl3 = NEG;
     int Hout = NEG, Iout = NEG;
@@ -447,10 +481,17 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
         pfB = *(const int4*)(dscB + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS);
         const uint8_t* rb = ring_l + (64 - kk) * LY::DS;
         auto ld_prof = [&](const int4& x0, int* scv) {
-            const int8_t* pr = (const int8_t*)prof + x0.x * 64 + lane;
+            if (TB) {
+                const int16_t* pr = (const int16_t*)prof + x0.x * 64 + lane;
 #pragma unroll
-            for (int c = 0; c < K; ++c) scv[c] = pr[c * 25 * 64];
+                for (int c = 0; c < K; ++c) scv[c] = pr[c * 25 * 64];
+            } else {
+                const int8_t* pr = (const int8_t*)prof + x0.x * 64 + lane;
+#pragma unroll
+                for (int c = 0; c < K; ++c) scv[c] = pr[c * 25 * 64];
+            }
         };
+        uint8_t* tbblk = TB ? tb_l + (int64_t)ch * (kTbBlockBytes * K) : nullptr;
         int4 cd0 = *(const int4*)(rb), nd0 = *(const int4*)(rb + LY::DS);
         int csc[K];
         ld_prof(cd0, csc);
@@ -478,32 +519,89 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
                 const int IL = c ? In[c - 1] : il0;
                 const int L1 = c ? h1[c - 1] : hl1;
                 const int L3 = c ? h3[c - 1] : hl3;
-                const int D = imax(h3[c] - cq, d3[c]) - ce;
-                const int I = imax(L0 - cq, IL) - ce;
-                const int M = L3 + csc[c];
-                int pf = 0;
-                if (!NOF) {
-                    pf = imax(L1, h1[c]) - cf;
-                    asm("" : "+v"(pf));
-                }
-                int H;
-                if (!NOI) {
-                    const int A = imax(h1[c] - ddm1, a1[c]);
-                    const int B = imax(L1 - dd0, b1[c]);
-                    const int C = imax(L1 - ds0.z, c1[c]);
-                    An[c] = A; Bn[c] = B; Cn[c] = C;
-                    const int x = imax3(D, A - ds0.w, B - aam2);
-                    if (!NOF) H = imax3(x, imax3(C - aam1, pf, fp[c]), imax3(M, I, z));
-                    else H = imax3(x, imax3(C - aam1, M, I), z);
+                if (!TB) {
+                    const int D = imax(h3[c] - cq, d3[c]) - ce;
+                    const int I = imax(L0 - cq, IL) - ce;
+                    const int M = L3 + csc[c];
+                    int pf = 0;
+                    if (!NOF) {
+                        pf = imax(L1, h1[c]) - cf;
+                        asm("" : "+v"(pf));
+                    }
+                    int H;
+                    if (!NOI) {
+                        const int A = imax(h1[c] - ddm1, a1[c]);
+                        const int B = imax(L1 - dd0, b1[c]);
+                        const int C = imax(L1 - ds0.z, c1[c]);
+                        An[c] = A; Bn[c] = B; Cn[c] = C;
+                        const int x = imax3(D, A - ds0.w, B - aam2);
+                        if (!NOF) H = imax3(x, imax3(C - aam1, pf, fp[c]), imax3(M, I, z));
+                        else H = imax3(x, imax3(C - aam1, M, I), z);
+                    } else {
+                        if (!NOF) H = imax(imax3(D, pf, fp[c]), imax3(M, I, z));
+                        else H = imax(imax3(D, M, I), z);
+                    }
+                    if (!NOF) fp[c] = pf;
+                    Hn[c] = H; In[c] = I; Dn[c] = D;
                 } else {
-                    if (!NOF) H = imax(imax3(D, pf, fp[c]), imax3(M, I, z));
-                    else H = imax(imax3(D, M, I), z);
+                    const int oD = h3[c] - cqD, xD = d3[c] - ce;
+                    xacc[1][c] = push_open(xacc[1][c], xD - oD);
+                    int D = imax(oD, xD);
+                    const int oI = L0 - cq, xI = IL - ce;
+                    xacc[0][c] = push_open(xacc[0][c], xI - oI);
+                    int I = imax(oI, xI);
+                    const int M = L3 + csc[c];
+                    int p1 = 0, p2 = 0;
+                    if (!NOF) {
+                        p1 = imax(L1 - cf11, h1[c] - cf9);
+                        asm("" : "+v"(p1));
+                        p2 = fp[c] - 1;
+                        fp[c] = p1;
+                    }
+                    asm("" : "+v"(D), "+v"(I));
+                    int Hk;
+                    if (!NOI) {
+                        const int oA = add3k<2>(h1[c], ddm1);
+                        xacc[2][c] = push_open(xacc[2][c], a1[c] - oA);
+                        int A = imax(oA, a1[c]);
+                        const int oB = add3k<1>(L1, dd0);
+                        xacc[3][c] = push_open(xacc[3][c], b1[c] - oB);
+                        int B = imax(oB, b1[c]);
+                        const int oC = L1 + ds0.z;
+                        xacc[4][c] = push_open(xacc[4][c], c1[c] - oC);
+                        int C = imax(oC, c1[c]);
+                        asm("" : "+v"(A), "+v"(B), "+v"(C));
+                        An[c] = A; Bn[c] = B; Cn[c] = C;
+                        const int x = imax3(D, A - ds0.w, B - aam2);
+                        if (!NOF) Hk = imax3(x, imax3(C - aam1, p1, p2), imax3(M, I, z));
+                        else Hk = imax3(x, imax3(C - aam1, M, I), z);
+                    } else {
+                        if (!NOF) Hk = imax(imax3(D, p1, p2), imax3(M, I, z));
+                        else Hk = imax(imax3(D, M, I), z);
+                    }
+                    nacc[c] = __builtin_amdgcn_alignbit(Hk, nacc[c], 4);
+                    Hn[c] = Hk & ~15;
+                    In[c] = I; Dn[c] = D;
                 }
-                if (!NOF) fp[c] = pf;
-                Hn[c] = H; In[c] = I; Dn[c] = D;
             }
 #pragma unroll
-            for (int c = 0; c < K; ++c) bk[c] = imax(bk[c], (Hn[c] << 6) | (63 - t));
+            for (int c = 0; c < K; ++c)
+                bk[c] = imax(bk[c], (Hn[c] << (TB ? 2 : 6)) | (63 - t));
+            if (TB && (t & 7) == 7) {
+#pragma unroll
+                for (int c = 0; c < K; ++c)
+                    *(uint32_t*)(tbblk + (((t >> 3) * K + c) * 64 + kk) * 4) = nacc[c];
+            }
+            if (TB && (t & 31) == 31) {
+#pragma unroll
+                for (int x = 0; x < 5; ++x) {
+                    if (NOI && x >= 2) continue;
+#pragma unroll
+                    for (int c = 0; c < K; ++c)
+                        *(uint32_t*)(tbblk + 2048 * K +
+                                     (((x * K + c) * 2 + (t >> 5)) * 64 + kk) * 4) = xacc[x][c];
+                }
+            }
             hl3 = hl2; hl2 = hl1; hl1 = hl0;
 #pragma unroll
             for (int c = 0; c < K; ++c) {
@@ -518,11 +616,13 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
 #pragma unroll
             for (int c = 0; c < K; ++c) csc[c] = nsc[c];
             cin = nin;
-            if (MPG_STEP_BARRIER) __builtin_amdgcn_sched_barrier(0);
+            if (TB ? MPG_TB_STEP_BARRIER : MPG_STEP_BARRIER) __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int c = 0; c < K; ++c) {
-            const int v = bk[c] >> 6, tt = 63 - (bk[c] & 63);
+            int v = bk[c] >> 6;
+            const int tt = 63 - (bk[c] & 63);
+            if (TB) v <<= 4;  // back to 16*H units
             if (v > best[c]) { best[c] = v; bstep[c] = ch * 64 + tt; }
             bk[c] = INT_MIN;
         }
@@ -534,7 +634,7 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
     for (int c = 0; c < K; ++c) {
         const int row = bstep[c] - kk, col = col0 + c;
         if (col <= m_l && row >= 0 && row <= n_l && best[c] > UNREACH) {
-            const uint64_t k2 = end_key(best[c], row, col);
+            const uint64_t k2 = end_key(TB ? (best[c] >> 4) : best[c], row, col);
             key = k2 > key ? k2 : key;
         }
     }
@@ -587,9 +687,9 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
           int* __restrict__ qhead, PairState* __restrict__ pst, int* __restrict__ prog_g,
           const uint8_t* __restrict__ prot, const uint8_t* __restrict__ desc,
           int2* __restrict__ bnd, uint8_t* __restrict__ tbbuf, DpSink sink, DevParams P) {
-    // score-only LOCAL launches also run lane-segment items (two pairs' last
-    // strips in one wavefront)
-    constexpr bool SEGOK = !TB && MODE == MPG_LOCAL && !PRO;
+    // LOCAL launches also run lane-segment items (two pairs' last strips in
+    // one wavefront)
+    constexpr bool SEGOK = MODE == MPG_LOCAL && !PRO;
     using LY = LdsLayout<K, TB, SEGOK>;
     // the mixed variant runs EXTEND and fixed-end pairs (per-pair modes)
     constexpr bool MIXED = MODE == kModeMixed;
@@ -646,8 +746,8 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         const int2 item = items[it];
         if constexpr (SEGOK) {
             if (item.y < 0) {
-                seg_item<K, NOI, NOF>(item, jobs, pst, prog_g, prot, desc, bnd, sink, P, smem,
-                                      smat, saa);
+                seg_item<K, TB, NOI, NOF>(item, jobs, pst, prog_g, prot, desc, bnd, tbbuf, sink,
+                                          P, smem, smat, saa);
                 continue;
             }
         }
@@ -758,31 +858,23 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
         }
         int hl1 = NEG, hl2 = NEG, hl3 = NEG;
         int Hout = NEG, Iout = NEG;
-        // registers carrying r+d(i), r+d(i-1), a(i-1), a(i-2) (score-only layout)
+        // registers carrying the previous two rows' donor and acceptor fields
+        // (score-only: r+d(i), r+d(i-1), a(i-1), a(i-2))
         int dd0 = 0, ddm1 = 0, aam1 = 0, aam2 = 0;
-        if (!TB && act) {
+        if (act) {
             const int4 u = *(const int4*)(dsc_g + (int64_t)(-lane - 1 + kDescLo) * LY::DS);
             const int4 v = *(const int4*)(dsc_g + (int64_t)(-lane - 2 + kDescLo) * LY::DS);
             dd0 = u.z; aam1 = u.w; ddm1 = v.z; aam2 = v.w;
         }
         // descriptor ring: rows -64..-1 then 0..63
-        int4 pf0 = make_int4(0, 0, 0, 0), pf1 = make_int4(0, 0, 0, 0);
+        int4 pf0 = make_int4(0, 0, 0, 0);
         if (act) {
             // all loads first, then the stores
             const uint8_t* src = dsc_g + (int64_t)(lane - 64 + kDescLo) * LY::DS;
             const uint8_t* src2 = dsc_g + (int64_t)(lane + kDescLo) * LY::DS;
             const int4 r0 = *(const int4*)src, r2 = *(const int4*)src2;
-            int4 r1 = make_int4(0, 0, 0, 0), r3 = make_int4(0, 0, 0, 0);
-            if (TB) {
-                r1 = *(const int4*)(src + 16);
-                r3 = *(const int4*)(src2 + 16);
-            }
             *(int4*)(ring + lane * LY::DS) = r0;
             *(int4*)(ring + (64 + lane) * LY::DS) = r2;
-            if (TB) {
-                *(int4*)(ring + lane * LY::DS + 16) = r1;
-                *(int4*)(ring + (64 + lane) * LY::DS + 16) = r3;
-            }
         }
         int2 nb = make_int2(NEG, NEG);
         // the left strip's last column arrives from HBM as that strip
@@ -821,28 +913,15 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                     const int4 o0 = *(const int4*)(ring + (64 + lane) * LY::DS);
                     *(int4*)(ring + lane * LY::DS) = o0;
                     *(int4*)(ring + (64 + lane) * LY::DS) = pf0;
-                    if (TB) {
-                        const int4 o1 = *(const int4*)(ring + (64 + lane) * LY::DS + 16);
-                        *(int4*)(ring + lane * LY::DS + 16) = o1;
-                        *(int4*)(ring + (64 + lane) * LY::DS + 16) = pf1;
-                    }
                 }
-                {
-                    const uint8_t* src =
-                        dsc_g + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS;
-                    pf0 = *(const int4*)src;
-                    if (TB) pf1 = *(const int4*)(src + 16);
-                }
+                pf0 = *(const int4*)(dsc_g + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS);
                 const uint8_t* rb = ring + (64 - lane) * LY::DS;
                 uint8_t* tbblk = tbp + ((int64_t)strip * nchunks + ch) * (kTbBlockBytes * K);
                 const int srow_n = ch * 64 - n;  // GLOBAL: lane == t + srow_n  <=>  row == n
 
                 // Software pipeline: descriptors are read two steps ahead, the
                 // profile entries and the incoming boundary value one step ahead.
-                auto ld_desc = [&](int tt, int4& x0, int4& x1) {
-                    x0 = *(const int4*)(rb + tt * LY::DS);
-                    if (TB) x1 = *(const int4*)(rb + tt * LY::DS + 16);
-                };
+                auto ld_desc = [&](int tt, int4& x0) { x0 = *(const int4*)(rb + tt * LY::DS); };
                 auto ld_prof = [&](const int4& x0, int* scv) {
                     if (TB) {
                         const int16_t* pr = (const int16_t*)prof + x0.x * 64 + lane;
@@ -854,9 +933,9 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         for (int c = 0; c < K; ++c) scv[c] = pr[c * 25 * 64];
                     }
                 };
-                int4 cd0, cd1 = make_int4(0, 0, 0, 0), nd0, nd1 = make_int4(0, 0, 0, 0);
-                ld_desc(0, cd0, cd1);
-                ld_desc(1, nd0, nd1);
+                int4 cd0, nd0;
+                ld_desc(0, cd0);
+                ld_desc(1, nd0);
                 int csc[K];
                 ld_prof(cd0, csc);
                 int2 cin = inb[0];
@@ -864,15 +943,15 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
 #pragma unroll
                 for (int t = 0; t < 64; ++t) {
                     // ---- prefetch for steps t+1 and t+2
-                    int4 fd0 = make_int4(0, 0, 0, 0), fd1 = make_int4(0, 0, 0, 0);
-                    if (t + 2 < 64) ld_desc(t + 2, fd0, fd1);
+                    int4 fd0 = make_int4(0, 0, 0, 0);
+                    if (t + 2 < 64) ld_desc(t + 2, fd0);
                     int nsc[K];
                     int2 nin = make_int2(0, 0);
                     if (t + 1 < 64) {
                         ld_prof(nd0, nsc);
                         nin = inb[t + 1];
                     }
-                    const int4 ds0 = cd0, ds1 = cd1;
+                    const int4 ds0 = cd0;
                     const int hl0 = shr1(cin.x, Hout);
                     const int il0 = FUSE_I ? 0 : shr1(cin.y, Iout);
                     const int zr = ds0.y;
@@ -946,20 +1025,20 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                             asm("" : "+v"(D), "+v"(I));
                             int Hk;
                             if (!NOI) {
-                                const int oA = h1[c] - ds0.z;
+                                const int oA = add3k<2>(h1[c], ddm1);
                                 xacc[2][c] = push_open(xacc[2][c], a1[c] - oA);
                                 int A = imax(oA, a1[c]);
-                                const int oB = L1 - ds0.w;
+                                const int oB = add3k<1>(L1, dd0);
                                 xacc[3][c] = push_open(xacc[3][c], b1[c] - oB);
                                 int B = imax(oB, b1[c]);
-                                const int oC = L1 - ds1.x;
+                                const int oC = L1 + ds0.z;
                                 xacc[4][c] = push_open(xacc[4][c], c1[c] - oC);
                                 int C = imax(oC, c1[c]);
                                 asm("" : "+v"(A), "+v"(B), "+v"(C));
                                 An[c] = A; Bn[c] = B; Cn[c] = C;
-                                const int x = imax3(D, A - ds1.y, B - ds1.z);
-                                if (!NOF) Hk = imax3(x, imax3(C - ds1.w, p1, p2), imax3(M, I, z));
-                                else Hk = imax3(x, imax3(C - ds1.w, M, I), z);
+                                const int x = imax3(D, A - ds0.w, B - aam2);
+                                if (!NOF) Hk = imax3(x, imax3(C - aam1, p1, p2), imax3(M, I, z));
+                                else Hk = imax3(x, imax3(C - aam1, M, I), z);
                             } else {
                                 if (!NOF) Hk = imax(imax3(D, p1, p2), imax3(M, I, z));
                                 else Hk = imax(imax3(D, M, I), z);
@@ -1030,7 +1109,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                         d3[c] = d2[c]; d2[c] = d1[c]; d1[c] = Dn[c];
                         if (!NOI) { a1[c] = An[c]; b1[c] = Bn[c]; c1[c] = Cn[c]; }
                     }
-                    if (!TB) { ddm1 = dd0; dd0 = ds0.z; aam2 = aam1; aam1 = ds0.w; }
+                    ddm1 = dd0; dd0 = ds0.z; aam2 = aam1; aam1 = ds0.w;
                     Hout = Hn[K - 1];
                     Iout = In[K - 1];
                     // lane 63 records the row; the other lanes write to slots
@@ -1038,7 +1117,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                     // splits the step's scheduling region and costs spills)
                     outb[lane == 63 ? t : 64 + lane] = make_int2(Hout, Iout);
                     // rotate the pipeline
-                    cd0 = nd0; cd1 = nd1; nd0 = fd0; nd1 = fd1;
+                    cd0 = nd0; nd0 = fd0;
 #pragma unroll
                     for (int c = 0; c < K; ++c) csc[c] = nsc[c];
                     cin = nin;
@@ -1226,7 +1305,7 @@ hipError_t launch_dp_t(hipStream_t s, int ncu, const DevParams& P, const PairJob
                        const DpSink& sink) {
     const bool noi = (P.flags & MPG_NO_INTRON) != 0;
     const bool nof = (P.flags & MPG_NO_FRAMESHIFT) != 0;
-    const size_t lds = (size_t)LdsLayout<K, TB, !TB && MODE == MPG_LOCAL && !PRO>::WAVE;
+    const size_t lds = (size_t)LdsLayout<K, TB, MODE == MPG_LOCAL && !PRO>::WAVE;
     dim3 b(64);
     // persistent grid: as many waves as ncu compute units hold at once for
     // this kernel, never more than there are items

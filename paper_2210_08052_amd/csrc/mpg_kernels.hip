@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
     // (pairs are laid out in row order).  Each thread writes its rows here,
     // then the block copies the range out in consecutive 16-byte pieces, so
     // the stores coalesce although a thread owns several consecutive rows.
-    __shared__ __align__(16) uint8_t s_out[256 * kPrepassRows * 32];
+    __shared__ __align__(16) uint8_t s_out[256 * kPrepassRows * 16];
     __shared__ int64_t s_base;  // byte offset in desc of the block's first row
     __shared__ int s_len;       // bytes of the block's rows
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x * kPrepassRows;
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
         if (threadIdx.x == 0) {
             first_owner = o;
             const PairJob& J0 = jobs[o];
-            s_base = J0.desc_off + (g0 - row_start[o]) * (J0.tb ? 32 : 16);
+            s_base = J0.desc_off + (g0 - row_start[o]) * 16;
             s_len = 0;
         }
     }
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
         }
         const int neg = neg_for(J.mode, J.tb != 0);
         const bool floor = floor_mode(J.mode);
-        const int64_t at = J.desc_off + (int64_t)(i0 + kDescLo) * (J.tb ? 32 : 16) - s_base;
+        const int64_t at = J.desc_off + (int64_t)(i0 + kDescLo) * 16 - s_base;
         uint8_t* rowp = s_out + at;
 #pragma unroll
         for (int rr = 0; rr < kPrepassRows; ++rr) {
@@ -115,17 +115,17 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
             };
             const bool valid = (i >= 0 && i <= n);
             const int z = floor ? (valid ? 0 : neg) : (i == 0 ? 0 : neg);
-            if (!J.tb) {
+            // traceback layout: the start candidate's nibble, and the donor
+            // term negated and offset by C's nibble (the kernel adds B's and
+            // A's nibble differences when it reads the row again one and two
+            // rows later)
+            if (!J.tb)
                 ((int4*)rowp)[rr] = make_int4(tr, z, P.r + dpen(i + 1), apen(i));
-            } else {
-                int4* out = (int4*)rowp + 2 * rr;
-                out[0] = make_int4(tr, z + 15, 16 * (P.r + dpen(i - 1)) - 7,
-                                   16 * (P.r + dpen(i)) - 6);
-                out[1] = make_int4(16 * (P.r + dpen(i + 1)) - 5, 16 * apen(i), 16 * apen(i - 2),
-                                   16 * apen(i - 1));
-            }
+            else
+                ((int4*)rowp)[rr] = make_int4(tr, z + 15, 5 - 16 * (P.r + dpen(i + 1)),
+                                              16 * apen(i));
         }
-        atomicMax(&s_len, (int)at + kPrepassRows * (J.tb ? 32 : 16));
+        atomicMax(&s_len, (int)at + kPrepassRows * 16);
     }
     __syncthreads();
     const int len = s_len;

@@ -616,7 +616,7 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         const int64_t rows = (int64_t)nsteps + kDescLo + kDescHi;
         P.row_start[k] = P.total_rows;
         P.total_rows += rows;
-        P.desc_bytes += rows * (J.tb ? 32 : 16);
+        P.desc_bytes += rows * 16;
         J.bnd_off = P.bnd_elems;
         P.bnd_elems += (int64_t)nsteps + kBndLo + kBndHi;
         J.tb_off = P.tb_bytes;
@@ -624,13 +624,17 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
         J.prog_off = (int32_t)P.nprog;
         P.nprog += J.nstrips;
         P.ginfo[k] = (uint32_t)gkey(J) << 24 | (uint32_t)(J.tb ? 1 : 0) << 23 | (uint32_t)J.nstrips;
-        // lane-segment class (width, chunks), then lanes descending; a pair
-        // has fewer than 2^15 chunks (genome rows are below 2^21)
+        // lane-segment class (traceback, width, chunks), then lanes
+        // descending; a pair has fewer than 2^15 chunks (genome rows are
+        // below 2^21).  Traced pairs only in batch calls (serving walks each
+        // pair in the wavefront that finishes it).
         P.seg_key[k] = -1;
-        if (seg_on && J.status == MPG_OK && !J.tb && gmode(J.mode) == MPG_LOCAL) {
+        if (seg_on && J.status == MPG_OK && (!J.tb || !cfg.serve) &&
+            gmode(J.mode) == MPG_LOCAL) {
             const int u = last_lanes(J);
             if (u >= 1 && u <= 63)
-                P.seg_key[k] = ((K == 1 ? 0 : K == 2 ? 1 : 2) << 21) | (J.nchunks << 6) | (63 - u);
+                P.seg_key[k] = (J.tb << 23) | ((K == 1 ? 0 : K == 2 ? 1 : 2) << 21) |
+                               (J.nchunks << 6) | (63 - u);
         }
         bysize.push_back({(int64_t)J.nstrips * J.nchunks, k});
     }
@@ -654,9 +658,9 @@ void plan_pairs(const mpg_params* p, const mpg_seg* segs, const int32_t* idx, in
     }
     // Lane-segment packs.  A pair's last strip fills only the lanes its
     // remaining columns need and idles the rest for all its steps.  Two
-    // LOCAL score-only pairs of one width whose strips run the same number of
-    // chunks and whose last strips need at most 64 lanes together share one
-    // wavefront: the pair with more lanes first, the other from lane `split`.
+    // LOCAL pairs of one width and kind (score-only or traced) whose strips
+    // run the same number of chunks and whose last strips need at most 64
+    // lanes together share one wavefront: the pair with more lanes first, the other from lane `split`.
     // Within each (width, chunks) class the widest remaining last strip is
     // matched with the narrowest that fits.  The pack's item goes where the
     // later pair's last strip would be, so it follows both pairs' other

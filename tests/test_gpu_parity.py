@@ -218,32 +218,34 @@ def _seg_pairs(K, seed, n_dna=3000, count=48):
     return out
 
 
+@pytest.mark.parametrize("tb", [False, True])
 @pytest.mark.parametrize("K", [1, 2, 4])
-def test_lane_segment_packs(ctx, K, monkeypatch):
+def test_lane_segment_packs(ctx, K, tb, monkeypatch):
     """Pairs of one region length whose last strips need few lanes: two
     pairs' last strips share a wavefront (pairs of one strip, and pairs whose
     last strip streams its boundary from the previous strip); the results
-    equal those of the same call without packs and the oracle's, with and
-    without the intron and frameshift terms."""
+    (with traceback: begin cell and op string too) equal those of the same
+    call without packs and the oracle's, with and without the intron and
+    frameshift terms."""
     monkeypatch.setenv("MPG_FORCE_K", str(K))
     pairs = _seg_pairs(K, 900 + K)
     for flags in (0, 3):
-        print("case K=%d flags=%d" % (K, flags), flush=True)
+        print("case K=%d tb=%d flags=%d" % (K, tb, flags), flush=True)
         g, o = scorings(0, flags)
         ctx.enable_timing(True)
         ctx.timing(reset=True)
-        got = compare(ctx, pairs, g, o, False, label="seg K=%d" % K)
+        got = compare(ctx, pairs, g, o, tb, label="seg K=%d tb=%d" % (K, tb))
         packs = ctx.timing(reset=True)["seg_packs"]
         ctx.enable_timing(False)
         assert packs >= len(pairs) // 4, packs
         monkeypatch.setenv("MPG_NO_SEG_PACK", "1")
         ctx.enable_timing(True)
-        ref = ctx.align_batch([(p, d, False) for p, d in pairs], g)
+        ref = ctx.align_batch([(p, d, tb) for p, d in pairs], g)
         assert ctx.timing(reset=True)["seg_packs"] == 0
         ctx.enable_timing(False)
         monkeypatch.delenv("MPG_NO_SEG_PACK")
         for k in range(len(pairs)):
-            assert key_gpu(got[k], False) == key_gpu(ref[k], False), k
+            assert key_gpu(got[k], tb) == key_gpu(ref[k], tb), k
 
 
 # ---- lane-packed int16 kernel (LOCAL, score-only, two pairs per wavefront)
@@ -1059,13 +1061,19 @@ def test_serving_failure_paths(monkeypatch):
         assert st["completed"] == 2 + 2 * len(ids) and st["in_flight"] == 0
 
 
-def test_batch_bounded_wait_gives_up_per_pair(monkeypatch):
+@pytest.mark.parametrize("packs", [False, True])
+def test_batch_bounded_wait_gives_up_per_pair(monkeypatch, packs):
     """The batch path under the same forced give-up: pairs of several strips
-    report MPG_E_DEVICE, the others are exact, and the next call is exact."""
+    report MPG_E_DEVICE and the next call is exact.  Without lane-segment
+    packs every pair of one strip is exact; with them, a pair of one strip
+    that shares a wavefront with a failing pair's last strip reports
+    MPG_E_DEVICE too, and every other pair is exact."""
     g, o = scorings(0, 0)
     pairs = _pairs(4242, n=16, max_prot=400, max_dna=1500, min_prot=150)
     pairs += _pairs(4243, n=8, max_prot=40, max_dna=800)
     monkeypatch.setenv("MPG_FORCE_K", "1")
+    if not packs:
+        monkeypatch.setenv("MPG_NO_SEG_PACK", "1")
     with mpg.Context(0) as c:
         ok = compare(c, pairs, g, o, True, label="before")
         monkeypatch.setenv("MPG_DEBUG_WAIT_POLLS", "0")
@@ -1074,6 +1082,6 @@ def test_batch_bounded_wait_gives_up_per_pair(monkeypatch):
         for k, (p, d) in enumerate(pairs):
             if len(p) + 1 > 64:
                 assert bad[k]["status"] == mpg.MPG_E_DEVICE, k
-            else:
+            elif not packs or bad[k]["status"] != mpg.MPG_E_DEVICE:
                 assert key_gpu(bad[k], True) == key_gpu(ok[k], True), k
         compare(c, pairs, g, o, True, label="after")
