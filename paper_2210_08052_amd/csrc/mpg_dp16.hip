@@ -130,8 +130,13 @@ __global__ void __launch_bounds__(256) prepass16_kernel(const PairJob* __restric
     }
 }
 
+// Waves per SIMD the register allocation of the int16 kernel aims at.
+#ifndef MPG_I16_WAVES
+#define MPG_I16_WAVES 3
+#endif
+
 template <int K, bool NOI, bool NOF>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MPG_I16_WAVES)))
 dp16_kernel(const PairJob* __restrict__ jobs, const PackJob* __restrict__ packs,
             const int2* __restrict__ items, int nitems, int* __restrict__ qhead,
             PairState* __restrict__ pst, int* __restrict__ prog_g,
