@@ -11,7 +11,8 @@ Default run (``--config all``): every workload of the metric in one process.
   same pairs and compares its results with the GPU's (``mismatches``).
 * ``legs.traceback``: the same 10,000 pairs with full traceback.
 * ``legs.longtail``: 200 pairs of 3-8k aa x 100-300 kb plus 2,000 short ones,
-  traceback, in one call under a 128 GiB direction-bit budget.
+  traceback, in one call under a 240 GiB direction-bit budget (its ~250 GB
+  of direction bits then fit one wave).
 * ``legs.serving``: 200,000 jobs submitted one by one at Poisson arrival
   times through ``mpg_submit``/``mpg_poll``: p50/p99 latency from the
   scheduled arrival to the result (overall and per class), served GCUPS, the
@@ -807,8 +808,8 @@ def main():
                          "serving legs), batch, batch16, traceback, single, longtail, serving, "
                          "profile, chain, chaining, rescore")
     ap.add_argument("--tb-budget-gib", type=float, default=None,
-                    help="traceback budget of the context in GiB (default: 128 for longtail, "
-                         "whose direction bits total ~250 GB, so it runs in two waves; else "
+                    help="traceback budget of the context in GiB (default: 240 for longtail, "
+                         "whose direction bits total ~250 GB, so they fit one wave; else "
                          "the library's 64)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
@@ -937,7 +938,7 @@ def run_batch_leg(mpg, torch, config, steps, warmup, cpu_budget, tb_budget_gib, 
                         device=dev)
     budget_gib = tb_budget_gib
     if budget_gib is None:
-        budget_gib = 128.0 if config == "longtail" else 0.0
+        budget_gib = 240.0 if config == "longtail" else 0.0
     ctx = mpg.Context(0, tb_budget_bytes=int(budget_gib * (1 << 30)))
     stream = torch.cuda.Stream(device=dev)
     ctx.set_stream(stream.cuda_stream)

@@ -6,7 +6,8 @@ the op string for traced pairs.
 
 * The 10,000-pair planted batch: every pair, score-only and with traceback.
 * The long-tail batch: 200 pairs of 3,000-8,000 residues x 100-300 kb plus
-  2,000 short ones in one call under a 128 GiB direction-bit budget.  The
+  2,000 short ones in one call under a 240 GiB direction-bit budget (one
+  wave, as bench.py runs it).  The
   oracle traces every short pair and a seeded sample of 20 long pairs (it
   stores two bytes per cell, so its concurrency is capped by host memory);
   every long pair's traced path is rescored by the oracle's rescorer, and the
@@ -107,7 +108,7 @@ def test_batch_10k_every_pair():
 def test_long_tail_full_size_against_oracle():
     pairs = W.long_tail(200, 2000, seed=4)
     p = mpg.params()
-    with mpg.Context(0, tb_budget_bytes=128 << 30) as ctx:
+    with mpg.Context(0, tb_budget_bytes=240 << 30) as ctx:
         tb = _run_dev(ctx, pairs, True, p)
         so = _run_dev(ctx, pairs, False, p, tune=False)
     is_long = np.array([len(q.prot) >= 3000 for q in pairs])
