@@ -618,16 +618,16 @@ typedef struct {
     double i16_gcups[2]; /* int16 lanes at 1, 2 columns per lane (0 if not tried) */
     int32_t K, K16;      /* the widths this context uses from now on */
     int32_t narrow_cols; /* pairs of at most this many columns (residues + 1) run one
-                            column per lane */
+                            column per lane (1: none but the empty protein) */
     int32_t seg_packs;   /* 1: two pairs' ragged last strips may share a wavefront */
-    double narrow_gcups[3]; /* at width K with the cutover at 64, 128, 192 columns
+    double narrow_gcups[4]; /* at width K with the cutover at 64, 128, 192 and 1 columns
                                (0 if not tried: at K = 1 it changes nothing) */
     double seg_gcups[2];    /* at width K and the kept cutover, packs off and on */
 } mpg_tuning;
 
 /*
  * Run a sample of the caller's workload at every kernel width, then, at the
- * fastest width, with the narrow-pair cutover at 64, 128 and 192 columns and
+ * fastest width, with the narrow-pair cutover at 64, 128, 192 and 1 columns and
  * with lane-segment packs off and on, and keep the fastest choices for the
  * batch calls of this context.  The sample is given like
  * mpg_align_batch_dev's input (letters in device memory, n segments, params

@@ -2761,13 +2761,14 @@ int mpg_autotune(mpg_ctx* ctx, const mpg_params* p, const uint8_t* d_prot, const
     }
     // at that width: the narrow-pair cutover (pairs of at most 64, 128 or 192
     // columns in strips of one column per lane: the one-wavefront strip of a
-    // narrow pair against more, cheaper strips), then lane-segment packs on
-    // and off
+    // narrow pair against more, cheaper strips; or none, 1: narrow pairs at
+    // the width too, two of them sharing a wavefront), then lane-segment packs
+    // on and off
     tu.narrow = 64;
     tu.seg = 1;
     double best_c = 0;
-    const int cuts[3] = {64, 128, 192};
-    for (int q = 0; q < 3 && rc == MPG_OK && (q == 0 || tu.K > 1); ++q) {
+    const int cuts[4] = {64, 128, 192, 1};
+    for (int q = 0; q < 4 && rc == MPG_OK && (q == 0 || tu.K > 1); ++q) {
         Tuning t = tu;
         t.narrow = cuts[q];
         double ms = 0;

@@ -115,7 +115,7 @@ class mpg_timing(ctypes.Structure):
 class mpg_tuning(ctypes.Structure):
     _fields_ = [("gcups", ctypes.c_double * 3), ("i16_gcups", ctypes.c_double * 2),
                 ("K", ctypes.c_int32), ("K16", ctypes.c_int32), ("narrow_cols", ctypes.c_int32),
-                ("seg_packs", ctypes.c_int32), ("narrow_gcups", ctypes.c_double * 3),
+                ("seg_packs", ctypes.c_int32), ("narrow_gcups", ctypes.c_double * 4),
                 ("seg_gcups", ctypes.c_double * 2)]
 
 

@@ -439,7 +439,7 @@ def test_autotune_keeps_results():
         rates = c.autotune()
         print("autotune built-in", rates, flush=True)
         assert all(v > 0 for v in rates["gcups"]) and rates["K"] in (1, 2, 4)
-        assert rates["narrow_cols"] in (64, 128, 192) and rates["seg_packs"] in (0, 1)
+        assert rates["narrow_cols"] in (64, 128, 192, 1) and rates["seg_packs"] in (0, 1)
         assert rates["narrow_gcups"][0] > 0 and all(v > 0 for v in rates["seg_gcups"])
         g, o = scorings(0, 0)
         g.flags |= mpg.MPG_ALLOW_I16
