@@ -13,7 +13,10 @@
 // on the 10k batch); the width-2 traceback kernels run three (a few spilled
 // registers outside the step loop, which the third wave repays: 4.9% on the
 // traceback batch).  Width 1 with traceback (about 190 VGPRs, two waves) and
-// width 4 keep the registers they need.
+// width 4 keep the registers they need (width 4 with traceback at two waves
+// per SIMD instead of one fits 256 VGPRs without spills in its steps, yet the
+// long-tail batch runs 279 -> 343 ms: its long pairs' strip pipelines are the
+// critical path, and a second wave halves each strip's own pace).
 #ifndef MPG_SCORE_WAVES
 #define MPG_SCORE_WAVES 4
 #endif
@@ -30,9 +33,13 @@
 #ifndef MPG_TB_STEP_BARRIER
 #define MPG_TB_STEP_BARRIER 0
 #endif
+#ifndef MPG_K4_WAVES
+#define MPG_K4_WAVES 1
+#endif
 template <int K, bool TB>
 struct WavesPerEu {
-    static constexpr int value = K > 2 ? 1 : (TB ? (K == 2 ? MPG_TB_WAVES : 1) : MPG_SCORE_WAVES);
+    static constexpr int value =
+        K > 2 ? MPG_K4_WAVES : (TB ? (K == 2 ? MPG_TB_WAVES : 1) : MPG_SCORE_WAVES);
 };
 
 namespace mpg {
