@@ -634,8 +634,8 @@ typedef struct {
  * p; MPG_ALLOW_I16 in p also tunes the int16 width); with n = 0 a built-in
  * sample is used (1,024 pairs of 511 residues x 4,096 nucleotides, half with
  * traceback; p, d_prot, d_dna and segs may then be NULL).  Each choice runs
- * twice and the second run's DP time counts.  Results never depend on these
- * choices.  Serving uses its own width (the narrowest, for the shortest per-pair
+ * three times and the faster of the last two DP times counts.  Results never
+ * depend on these choices.  Serving uses its own width (the narrowest, for the shortest per-pair
  * critical path).  Call it while no other work of the context is in flight.
  * out may be NULL.
  */
