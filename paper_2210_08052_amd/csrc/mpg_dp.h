@@ -184,7 +184,7 @@ struct LdsLayout {
     static constexpr int RING = 128 * DS;      // two chunks of descriptors
     static constexpr int PROF = 25 * SW * PS;  // profile: 24 aa + poison row
     static constexpr int IN = 64 * 8;          // incoming boundary of the chunk
-    static constexpr int OUT = 128 * 8;        // outgoing boundary, then a dummy slot per lane
+    static constexpr int OUT = 192 * 8;        // outgoing boundary, then the other lanes' dummy slots
     static constexpr int MAT = 640;            // substitution matrix, then the letter codes
     static constexpr int RING2 = RING + PROF + IN + OUT + MAT;  // SEG: second ring
     static constexpr int WAVE = RING2 + (SEG ? RING : 0);
@@ -432,60 +432,51 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
     inbA[lane] = neg2;
     inbB[lane] = neg2;
     bool failed = false;
-    int2 nbA = neg2, nbB = neg2;
+    // Each chunk loads its own boundary and descriptor rows when it starts
+    // (nothing is held in registers across a chunk: a packed wavefront has
+    // none to spare).  The left strips' counters are read a chunk ahead, so
+    // the check at a chunk start normally finds the value loaded long before.
     int seenA = 0, seenB = 0;
-    if (leftA) {
-        if (!wait_prog(&progA[stripA - 1], nchunks < 2 ? nchunks : 2, P.max_polls)) failed = true;
-        nbA = ld_dev2(&bndA[kBndLo + lane]);
-        seenA = ld_dev(&progA[stripA - 1]);
-    }
-    if (leftB) {
-        if (!wait_prog(&progB[stripB - 1], nchunks < 2 ? nchunks : 2, P.max_polls)) failed = true;
-        nbB = ld_dev2(&bndB[kBndLo + lane]);
-        seenB = ld_dev(&progB[stripB - 1]);
-    }
-    int4 pfA = make_int4(0, 0, 0, 0), pfB = make_int4(0, 0, 0, 0);
     const uint8_t* ring_l = sg ? ringB : ringA;
     const int2* inb_l = sg ? inbB : inbA;
 
     for (int ch = 0; ch < nchunks && !failed; ++ch) {
-        // incoming boundary rows ch*64 .. ch*64+63 of each pair with a left strip
+        // incoming boundary rows ch*64 .. ch*64+63 of each pair with a left
+        // strip: they need the left strip's chunks up to ch+1
+        const int need = ch + 2 < nchunks ? ch + 2 : nchunks;
+        if (leftA && __builtin_amdgcn_readfirstlane(seenA) < need &&
+            !wait_prog(&progA[stripA - 1], need, P.max_polls)) {
+            failed = true;
+            break;
+        }
+        if (leftB && __builtin_amdgcn_readfirstlane(seenB) < need &&
+            !wait_prog(&progB[stripB - 1], need, P.max_polls)) {
+            failed = true;
+            break;
+        }
+        int2 nbA = neg2, nbB = neg2;
         if (leftA) {
-            inbA[lane] = ch * 64 + lane > nA ? neg2 : nbA;
-            if (ch + 1 < nchunks) {
-                const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
-                if (__builtin_amdgcn_readfirstlane(seenA) < need &&
-                    !wait_prog(&progA[stripA - 1], need, P.max_polls)) {
-                    failed = true;
-                    break;
-                }
-                nbA = ld_dev2(&bndA[kBndLo + (ch + 1) * 64 + lane]);
-                seenA = ld_dev(&progA[stripA - 1]);
-            }
+            nbA = ld_dev2(&bndA[kBndLo + ch * 64 + lane]);
+            seenA = ld_dev(&progA[stripA - 1]);
         }
         if (leftB) {
-            inbB[lane] = ch * 64 + lane > nB ? neg2 : nbB;
-            if (ch + 1 < nchunks) {
-                const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
-                if (__builtin_amdgcn_readfirstlane(seenB) < need &&
-                    !wait_prog(&progB[stripB - 1], need, P.max_polls)) {
-                    failed = true;
-                    break;
-                }
-                nbB = ld_dev2(&bndB[kBndLo + (ch + 1) * 64 + lane]);
-                seenB = ld_dev(&progB[stripB - 1]);
-            }
+            nbB = ld_dev2(&bndB[kBndLo + ch * 64 + lane]);
+            seenB = ld_dev(&progB[stripB - 1]);
         }
         if (ch > 0) {
+            // slide both rings (current chunk -> previous half) and load this
+            // chunk's rows
+            const int4 dA = *(const int4*)(dscA + (int64_t)(ch * 64 + lane + kDescLo) * LY::DS);
+            const int4 dB = *(const int4*)(dscB + (int64_t)(ch * 64 + lane + kDescLo) * LY::DS);
             const int4 oA = *(const int4*)(ringA + (64 + lane) * LY::DS);
             const int4 oB = *(const int4*)(ringB + (64 + lane) * LY::DS);
             *(int4*)(ringA + lane * LY::DS) = oA;
-            *(int4*)(ringA + (64 + lane) * LY::DS) = pfA;
+            *(int4*)(ringA + (64 + lane) * LY::DS) = dA;
             *(int4*)(ringB + lane * LY::DS) = oB;
-            *(int4*)(ringB + (64 + lane) * LY::DS) = pfB;
+            *(int4*)(ringB + (64 + lane) * LY::DS) = dB;
         }
-        pfA = *(const int4*)(dscA + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS);
-        pfB = *(const int4*)(dscB + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS);
+        if (leftA) inbA[lane] = ch * 64 + lane > nA ? neg2 : nbA;
+        if (leftB) inbB[lane] = ch * 64 + lane > nB ? neg2 : nbB;
         const uint8_t* rb = ring_l + (64 - kk) * LY::DS;
         auto ld_prof = [&](const int4& x0, int* scv) {
             if (TB) {
@@ -715,6 +706,11 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
     uint8_t* prof = smem + LY::RING;
     int2* inb = (int2*)(smem + LY::RING + LY::PROF);
     int2* outb = (int2*)(smem + LY::RING + LY::PROF + LY::IN);
+    // step t's outgoing row: lane 63 writes slot t, lane l < 63 the dummy slot
+    // 64 + l + t, never read.  One base per lane with the step in the store's
+    // immediate offset: a per-step select of the slot is invariant across
+    // chunks, and the compiler hoists all 64 of them into registers.
+    int2* const outw = outb + (lane == 63 ? 0 : 64 + lane);
     int8_t* smat = (int8_t*)(smem + LY::RING + LY::PROF + LY::IN + LY::OUT);
     uint8_t* saa = (uint8_t*)(smat + 24 * 24);
     // the matrix and the letter codes, read with per-lane indices when a
@@ -1122,7 +1118,7 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                     // lane 63 records the row; the other lanes write to slots
                     // of their own, so the store needs no branch (a branch
                     // splits the step's scheduling region and costs spills)
-                    outb[lane == 63 ? t : 64 + lane] = make_int2(Hout, Iout);
+                    outw[t] = make_int2(Hout, Iout);
                     // rotate the pipeline
                     cd0 = nd0; nd0 = fd0;
 #pragma unroll
