@@ -8,15 +8,13 @@
 #include "mpg_walk.h"
 
 // Occupancy targets of the DP kernels (waves per SIMD; 1 = no cap).  The
-// score-only kernels of width <= 2 run four waves per SIMD (128 VGPRs: a few
-// spills per 64-step chunk, none in the steps; 3.4% faster than three waves
-// on the 10k batch); the width-2 traceback kernels run three (a few spilled
-// registers outside the step loop, which the third wave repays: 4.9% on the
-// traceback batch).  Width 1 with traceback (about 190 VGPRs, two waves) and
-// width 4 keep the registers they need (width 4 with traceback at two waves
-// per SIMD instead of one fits 256 VGPRs without spills in its steps, yet the
-// long-tail batch runs 279 -> 343 ms: its long pairs' strip pipelines are the
-// critical path, and a second wave halves each strip's own pace).
+// score-only kernels of width <= 2 run four waves per SIMD (128 VGPRs; 3.4%
+// faster than three waves on the 10k batch); the width-2 traceback kernels
+// run three (4.9% on the traceback batch), which their LDS also caps.  Width 1
+// with traceback and width 4 keep the registers they need (about 320 and 400
+// with traceback: one wave per SIMD; width 4 at two waves slows the long-tail
+// batch 279 -> 343 ms: its long pairs' strip pipelines are the critical path,
+// and a second wave halves each strip's own pace).
 #ifndef MPG_SCORE_WAVES
 #define MPG_SCORE_WAVES 4
 #endif
@@ -184,7 +182,9 @@ struct LdsLayout {
     static constexpr int RING = 128 * DS;      // two chunks of descriptors
     static constexpr int PROF = 25 * SW * PS;  // profile: 24 aa + poison row
     static constexpr int IN = 64 * 8;          // incoming boundary of the chunk
-    static constexpr int OUT = 192 * 8;        // outgoing boundary, then the other lanes' dummy slots
+    // outgoing boundary, then the other lanes' dummy slots (one per lane and
+    // step at width 2, one per lane otherwise)
+    static constexpr int OUT = (K == 2 ? 192 : 128) * 8;
     static constexpr int MAT = 640;            // substitution matrix, then the letter codes
     static constexpr int RING2 = RING + PROF + IN + OUT + MAT;  // SEG: second ring
     static constexpr int WAVE = RING2 + (SEG ? RING : 0);
@@ -432,51 +432,68 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
     inbA[lane] = neg2;
     inbB[lane] = neg2;
     bool failed = false;
-    // Each chunk loads its own boundary and descriptor rows when it starts
-    // (nothing is held in registers across a chunk: a packed wavefront has
-    // none to spare).  The left strips' counters are read a chunk ahead, so
-    // the check at a chunk start normally finds the value loaded long before.
+    int2 nbA = neg2, nbB = neg2;
     int seenA = 0, seenB = 0;
-    const uint8_t* ring_l = sg ? ringB : ringA;
-    const int2* inb_l = sg ? inbB : inbA;
+    if (leftA) {
+        if (!wait_prog(&progA[stripA - 1], nchunks < 2 ? nchunks : 2, P.max_polls)) failed = true;
+        nbA = ld_dev2(&bndA[kBndLo + lane]);
+        seenA = ld_dev(&progA[stripA - 1]);
+    }
+    if (leftB) {
+        if (!wait_prog(&progB[stripB - 1], nchunks < 2 ? nchunks : 2, P.max_polls)) failed = true;
+        nbB = ld_dev2(&bndB[kBndLo + lane]);
+        seenB = ld_dev(&progB[stripB - 1]);
+    }
+    int4 pfA = make_int4(0, 0, 0, 0), pfB = make_int4(0, 0, 0, 0);
+    // this lane's ring and incoming rows; at width 2 as one LDS offset each,
+    // opaque to the compiler: a select of the two pairs' areas is distributed
+    // over the steps' addresses, which are invariant across chunks, and the
+    // compiler hoists all of them into registers, which width 2 spills (the
+    // widths that run one wave per SIMD hold them; see the outgoing rows)
+    int ring_off = sg ? LY::RING2 : 0;
+    int inb_off = sg ? LY::RING + LY::PROF + LY::IN : LY::RING + LY::PROF;
+    if constexpr (K == 2) asm volatile("" : "+v"(ring_off), "+v"(inb_off));
+    const uint8_t* ring_l = K != 2 ? (sg ? ringB : ringA) : smem + ring_off;
+    const int2* inb_l = K != 2 ? (sg ? inbB : inbA) : (const int2*)(smem + inb_off);
 
     for (int ch = 0; ch < nchunks && !failed; ++ch) {
-        // incoming boundary rows ch*64 .. ch*64+63 of each pair with a left
-        // strip: they need the left strip's chunks up to ch+1
-        const int need = ch + 2 < nchunks ? ch + 2 : nchunks;
-        if (leftA && __builtin_amdgcn_readfirstlane(seenA) < need &&
-            !wait_prog(&progA[stripA - 1], need, P.max_polls)) {
-            failed = true;
-            break;
-        }
-        if (leftB && __builtin_amdgcn_readfirstlane(seenB) < need &&
-            !wait_prog(&progB[stripB - 1], need, P.max_polls)) {
-            failed = true;
-            break;
-        }
-        int2 nbA = neg2, nbB = neg2;
+        // incoming boundary rows ch*64 .. ch*64+63 of each pair with a left strip
         if (leftA) {
-            nbA = ld_dev2(&bndA[kBndLo + ch * 64 + lane]);
-            seenA = ld_dev(&progA[stripA - 1]);
+            inbA[lane] = ch * 64 + lane > nA ? neg2 : nbA;
+            if (ch + 1 < nchunks) {
+                const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
+                if (__builtin_amdgcn_readfirstlane(seenA) < need &&
+                    !wait_prog(&progA[stripA - 1], need, P.max_polls)) {
+                    failed = true;
+                    break;
+                }
+                nbA = ld_dev2(&bndA[kBndLo + (ch + 1) * 64 + lane]);
+                seenA = ld_dev(&progA[stripA - 1]);
+            }
         }
         if (leftB) {
-            nbB = ld_dev2(&bndB[kBndLo + ch * 64 + lane]);
-            seenB = ld_dev(&progB[stripB - 1]);
+            inbB[lane] = ch * 64 + lane > nB ? neg2 : nbB;
+            if (ch + 1 < nchunks) {
+                const int need = ch + 3 < nchunks ? ch + 3 : nchunks;
+                if (__builtin_amdgcn_readfirstlane(seenB) < need &&
+                    !wait_prog(&progB[stripB - 1], need, P.max_polls)) {
+                    failed = true;
+                    break;
+                }
+                nbB = ld_dev2(&bndB[kBndLo + (ch + 1) * 64 + lane]);
+                seenB = ld_dev(&progB[stripB - 1]);
+            }
         }
         if (ch > 0) {
-            // slide both rings (current chunk -> previous half) and load this
-            // chunk's rows
-            const int4 dA = *(const int4*)(dscA + (int64_t)(ch * 64 + lane + kDescLo) * LY::DS);
-            const int4 dB = *(const int4*)(dscB + (int64_t)(ch * 64 + lane + kDescLo) * LY::DS);
             const int4 oA = *(const int4*)(ringA + (64 + lane) * LY::DS);
             const int4 oB = *(const int4*)(ringB + (64 + lane) * LY::DS);
             *(int4*)(ringA + lane * LY::DS) = oA;
-            *(int4*)(ringA + (64 + lane) * LY::DS) = dA;
+            *(int4*)(ringA + (64 + lane) * LY::DS) = pfA;
             *(int4*)(ringB + lane * LY::DS) = oB;
-            *(int4*)(ringB + (64 + lane) * LY::DS) = dB;
+            *(int4*)(ringB + (64 + lane) * LY::DS) = pfB;
         }
-        if (leftA) inbA[lane] = ch * 64 + lane > nA ? neg2 : nbA;
-        if (leftB) inbB[lane] = ch * 64 + lane > nB ? neg2 : nbB;
+        pfA = *(const int4*)(dscA + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS);
+        pfB = *(const int4*)(dscB + (int64_t)((ch + 1) * 64 + lane + kDescLo) * LY::DS);
         const uint8_t* rb = ring_l + (64 - kk) * LY::DS;
         auto ld_prof = [&](const int4& x0, int* scv) {
             if (TB) {
@@ -505,8 +522,17 @@ __device__ __forceinline__ void seg_item(const int2 item, const PairJob* __restr
                 nin = inb_l[t + 1];
             }
             const int4 ds0 = cd0;
-            // a segment's first lane takes its own pair's boundary
-            int hl0 = shr1(cin.x, Hout), il0 = shr1(cin.y, Iout);
+            // a segment's first lane takes its own pair's boundary (the
+            // shift's own lane 0 value is replaced too, so the shift needs no
+            // copy of the boundary value as its old operand)
+            int hl0, il0;
+            if constexpr (K == 2) {
+                hl0 = __builtin_amdgcn_mov_dpp(Hout, kShr1, 0xF, 0xF, true);
+                il0 = __builtin_amdgcn_mov_dpp(Iout, kShr1, 0xF, 0xF, true);
+            } else {
+                hl0 = shr1(cin.x, Hout);
+                il0 = shr1(cin.y, Iout);
+            }
             hl0 = first ? cin.x : hl0;
             il0 = first ? cin.y : il0;
             const int z = ds0.y;
@@ -706,10 +732,16 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
     uint8_t* prof = smem + LY::RING;
     int2* inb = (int2*)(smem + LY::RING + LY::PROF);
     int2* outb = (int2*)(smem + LY::RING + LY::PROF + LY::IN);
-    // step t's outgoing row: lane 63 writes slot t, lane l < 63 the dummy slot
-    // 64 + l + t, never read.  One base per lane with the step in the store's
-    // immediate offset: a per-step select of the slot is invariant across
-    // chunks, and the compiler hoists all 64 of them into registers.
+    // step t's outgoing row: lane 63 writes slot t, lane l < 63 a dummy slot,
+    // never read.  A per-step select of the slot is invariant across chunks,
+    // and the compiler hoists all 64 of them into registers.  Width 2 (three
+    // or four waves per SIMD) spills them, and every reload waited for the
+    // chunk's direction-bit stores, so it writes slot 64 + l + t through one
+    // base per lane with the step in the store's immediate offset (traceback
+    // batch DP 26.3 -> 25.4 ms with the packed strips' offsets below).  The
+    // other widths keep the select: built without the hoisted registers they
+    // run more waves per SIMD, which slows the long-tail batch (280 -> 331 ms)
+    // and doubles the serving latency (p50 1.9 -> 3.9 ms).
     int2* const outw = outb + (lane == 63 ? 0 : 64 + lane);
     int8_t* smat = (int8_t*)(smem + LY::RING + LY::PROF + LY::IN + LY::OUT);
     uint8_t* saa = (uint8_t*)(smat + 24 * 24);
@@ -1118,7 +1150,8 @@ dp_kernel(const PairJob* __restrict__ jobs, const int2* __restrict__ items, int 
                     // lane 63 records the row; the other lanes write to slots
                     // of their own, so the store needs no branch (a branch
                     // splits the step's scheduling region and costs spills)
-                    outw[t] = make_int2(Hout, Iout);
+                    if constexpr (K == 2) outw[t] = make_int2(Hout, Iout);
+                    else outb[lane == 63 ? t : 64 + lane] = make_int2(Hout, Iout);
                     // rotate the pipeline
                     cd0 = nd0; nd0 = fd0;
 #pragma unroll
