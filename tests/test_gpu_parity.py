@@ -225,11 +225,11 @@ def test_lane_segment_packs(ctx, K, tb, monkeypatch):
     pairs' last strips share a wavefront (pairs of one strip, and pairs whose
     last strip streams its boundary from the previous strip); the results
     (with traceback: begin cell and op string too) equal those of the same
-    call without packs and the oracle's, with and without the intron and
-    frameshift terms."""
+    call without packs and the oracle's, under each combination of the
+    intron and frameshift terms (each is a kernel variant of its own)."""
     monkeypatch.setenv("MPG_FORCE_K", str(K))
     pairs = _seg_pairs(K, 900 + K)
-    for flags in (0, 3):
+    for flags in (0, 1, 2, 3):
         print("case K=%d tb=%d flags=%d" % (K, tb, flags), flush=True)
         g, o = scorings(0, flags)
         ctx.enable_timing(True)
