@@ -39,12 +39,6 @@ using namespace dev;
 namespace dev {
 
 // ----------------------------------------------------------------- prepass
-// Rows per prepass thread (the int32 layouts): eight halve the blocks, and with
-// them each block's owner search and barriers, against four.
-constexpr int kRowsPP = 8;
-static_assert(64 % kRowsPP == 0 && kDescLo % kRowsPP == 0 && kDescHi % kRowsPP == 0,
-              "a pair's rows must split into whole per-thread runs");
-
 __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict__ jobs,
                                                       const int64_t* __restrict__ row_start,
                                                       int npairs, int64_t total_rows,
@@ -59,10 +53,10 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
     // (pairs are laid out in row order).  Each thread writes its rows here,
     // then the block copies the range out in consecutive 16-byte pieces, so
     // the stores coalesce although a thread owns several consecutive rows.
-    __shared__ __align__(16) uint8_t s_out[256 * kRowsPP * 16];
+    __shared__ __align__(16) uint8_t s_out[256 * kPrepassRows * 16];
     __shared__ int64_t s_base;  // byte offset in desc of the block's first row
     __shared__ int s_len;       // bytes of the block's rows
-    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x * kRowsPP;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x * kPrepassRows;
     if (threadIdx.x < 64) {
         const int o = wave_find_owner(row_start, npairs, g0);
         if (threadIdx.x == 0) {
@@ -78,10 +72,10 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
         s_acceptor[threadIdx.x] = P.acceptor[threadIdx.x];
     }
     __syncthreads();
-    // kRowsPP consecutive rows per thread: a pair's rows start at a
+    // kPrepassRows consecutive rows per thread: a pair's rows start at a
     // multiple of 64 and number a multiple of 64, so they share one pair, one
     // window of bases and one run of stores
-    const int64_t q = g0 + (int64_t)threadIdx.x * kRowsPP;
+    const int64_t q = g0 + (int64_t)threadIdx.x * kPrepassRows;
     const bool active = q < total_rows;
     if (active) {
         int lo = first_owner;
@@ -90,8 +84,8 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
         const int i0 = (int)(q - row_start[lo]) - kDescLo;
         const int n = J.n;
         const uint8_t* T = dna + J.dna_off;
-        constexpr int W = kRowsPP + 8;
-        int b[W];  // bases i0-4 .. i0+kRowsPP+3 (code 4 outside 1..n)
+        constexpr int W = kPrepassRows + 8;
+        int b[W];  // bases i0-4 .. i0+kPrepassRows+3 (code 4 outside 1..n)
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const int x = i0 - 4 + k;
@@ -102,7 +96,7 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
         const int64_t at = J.desc_off + (int64_t)(i0 + kDescLo) * 16 - s_base;
         uint8_t* rowp = s_out + at;
 #pragma unroll
-        for (int rr = 0; rr < kRowsPP; ++rr) {
+        for (int rr = 0; rr < kPrepassRows; ++rr) {
             const int i = i0 + rr;
             const int* bb = b + rr;  // bb[k] = T[i-4+k]
             // codon ending at i: T[i-2..i]
@@ -131,7 +125,7 @@ __global__ void __launch_bounds__(256) prepass_kernel(const PairJob* __restrict_
                 ((int4*)rowp)[rr] = make_int4(tr, z + 15, 5 - 16 * (P.r + dpen(i + 1)),
                                               16 * apen(i));
         }
-        atomicMax(&s_len, (int)at + kRowsPP * 16);
+        atomicMax(&s_len, (int)at + kPrepassRows * 16);
     }
     __syncthreads();
     const int len = s_len;
@@ -479,7 +473,7 @@ int dp_lds_bytes(int K, bool tb) {
 hipError_t launch_prepass(hipStream_t s, const PairJob* jobs, const int64_t* row_start, int npairs,
                           int64_t total_rows, const uint8_t* dna, uint8_t* desc, const DevParams& P) {
     if (total_rows <= 0) return hipSuccess;
-    const int64_t per_block = 256 * dev::kRowsPP;
+    const int64_t per_block = 256 * dev::kPrepassRows;
     const int64_t blocks = (total_rows + per_block - 1) / per_block;
     hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)blocks), dim3(256), 0, s, jobs, row_start,
                        npairs, total_rows, dna, desc, P);
